@@ -1,0 +1,182 @@
+/*
+ * ffbspca.h - C ABI of the MI355X (gfx950) fast Fourier-Bessel steerable PCA library.
+ *
+ * Method: Zhao, Shkolnisky, Singer, "Fast Steerable Principal Component
+ * Analysis" (arXiv:1412.0781).  The library computes
+ *   - the Fourier-Bessel expansion a = T* I of each image (Algorithm 1:
+ *     polar Fourier samples Eq.(nufft) by a non-uniform FFT, the angular sum
+ *     Eq.(1DFFT) by an FFT on each ring, the radial Gauss-Legendre sum Eq.(a));
+ *   - the steerable covariance blocks C^(k) (Eqs.(ck),(ck_0)) with the mean
+ *     removed from k = 0 (Algorithm 2, step 1) and their eigenpairs
+ *     (Algorithm 2, step 4);
+ *   - the adjoint T (synthesis of images from coefficients), the transpose of T*.
+ *
+ * Conventions (all calls):
+ *   images   float32 [n][L][L], C-contiguous, device memory.  Axis 0 is i1 (the
+ *            x coordinate), axis 1 is i2 (y); pixel indices run over
+ *            -ceil((L-1)/2) .. floor((L-1)/2) (Sec. II).
+ *   coeffs   float32 [n][p_half][2] (real, imaginary), device memory: a_{k,q}
+ *            for k = 0..k_max, q = 1..p_k, ordered k ascending then q ascending
+ *            (a_{-k,q} = conj(a_{k,q}) is implied, Sec. II-B).  The imaginary
+ *            part of every k = 0 entry is written as exactly 0.
+ *   The polar transform Eq.(nufft) is taken with normalisation 1 (a Riemann
+ *   sum of the continuous Fourier transform with unit pixel); the printed
+ *   1/(2R)^2 would scale a by 1/(2R)^2 and C, lambda by 1/(2R)^4.
+ *
+ * Ownership: the library owns a plan and the device tables inside it.  The
+ * caller owns every image, coefficient, accumulator and workspace buffer.
+ * Compute calls are asynchronous on the given HIP stream, allocate nothing and
+ * never synchronise the host.  A plan is immutable once built and may be used
+ * from several streams at once, provided the workspaces differ.
+ *
+ * Errors: every call returns 0 on success or a negative FB_ERR_* code; no
+ * exception crosses the ABI.  Argument errors are detected before any work is
+ * enqueued.  FB_ERR_HIP means a HIP runtime call failed; fb_plan_last_hip_error
+ * returns that HIP error code.
+ */
+#ifndef FFBSPCA_H
+#define FFBSPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fb_plan_s* fb_plan_t;
+
+/* Return codes */
+#define FB_OK 0
+#define FB_ERR_INVALID_ARG (-1)        /* a size, pointer or parameter is out of range */
+#define FB_ERR_ALLOC (-2)              /* host or device allocation failed (plan creation only) */
+#define FB_ERR_HIP (-3)                /* a HIP runtime call failed */
+#define FB_ERR_UNSUPPORTED (-4)        /* e.g. odd n_theta, FFT length with a prime factor > 31 */
+#define FB_ERR_NO_DEVICE (-5)          /* compute call on a plan built with fb_plan_host */
+#define FB_ERR_WORKSPACE (-6)          /* workspace too small for even one image */
+
+/* Arithmetic of the two dense contractions (radial quadrature Eq.(a) and covariance Eq.(ck)). */
+#define FB_FP32 0    /* FP32 matrix-core products, FP32 accumulation */
+#define FB_BF16X3 1  /* split-BF16 operands x = hi + lo, products hi*hi + hi*lo + lo*hi, FP32 accumulation */
+
+typedef struct fb_info {
+  int32_t L;          /* image side */
+  double c;           /* band limit, 0 < c <= 1/2 (Sec. II) */
+  double R;           /* support radius, 0 < R <= L/2 (Sec. II-A) */
+  int32_t n_xi;       /* ceil(4 c R), radial Gauss-Legendre nodes (Algorithm 1, step 1) */
+  int32_t n_theta;    /* ceil(16 c R), angular nodes per ring (Algorithm 1, step 1) */
+  int32_t k_max;      /* largest admissible angular frequency (Eq.(criterion1)) */
+  int32_t p0;         /* p_0 */
+  int64_t p_half;     /* sum_{k=0}^{k_max} p_k: complex coefficients stored per image */
+  int64_t p_total;    /* the paper's p = p_0 + 2 sum_{k>0} p_k (Sec. II-A) */
+  int64_t cov_size;   /* sum_k p_k^2: doubles in a packed covariance / eigenvector array */
+  int32_t grid_n;     /* side of the oversampled Cartesian grid of the non-uniform FFT */
+  int32_t kernel_w;   /* spreading kernel width, in grid points */
+  double kernel_beta; /* shape parameter of the exp(beta(sqrt(1-z^2)-1)) kernel */
+  int32_t has_device; /* 1 for fb_plan, 0 for fb_plan_host */
+} fb_info;
+
+/* Build a plan for L x L images with band limit c and support radius R
+ * (Algorithm 1, steps 1-2): the (k,q) selection of Eq.(criterion1), n_xi and
+ * n_theta, Gauss-Legendre nodes on [0, c], the radial table
+ * N_{k,q} J_k(R_{k,q} xi_j / c) xi_j w_j in FP64 (with FP32 and BF16 hi/lo
+ * copies), and the non-uniform FFT tables; uploads them to the current HIP
+ * device.  Synchronous.  Errors: FB_ERR_INVALID_ARG if L < 2, c not in
+ * (0, 1/2], R not in (0, L/2], or no (k,q) is admissible; FB_ERR_UNSUPPORTED
+ * if n_theta is odd or an FFT length has a prime factor above 31. */
+int fb_plan(int L, double c, double R, fb_plan_t* out);
+
+/* Same tables, host side only (no HIP call): for inspection of sizes and index
+ * tables on a machine without a GPU.  Compute calls on it return FB_ERR_NO_DEVICE. */
+int fb_plan_host(int L, double c, double R, fb_plan_t* out);
+
+/* Free a plan and its device tables.  NULL is accepted. */
+int fb_plan_destroy(fb_plan_t plan);
+
+/* Sizes of a plan. */
+int fb_plan_info(fb_plan_t plan, fb_info* out);
+
+/* Host copies of the index tables (any pointer may be NULL to skip it):
+ *   k, q      int32 [p_half]: the (k, q) of each stored coefficient, q from 1
+ *   p         int32 [k_max+1]: p_k
+ *   coef_off  int64 [k_max+2]: first coefficient of block k (coef_off[k_max+1] = p_half)
+ *   cov_off   int64 [k_max+2]: first entry of the p_k x p_k block k in packed arrays */
+int fb_plan_tables(fb_plan_t plan, int32_t* k, int32_t* q, int32_t* p, int64_t* coef_off, int64_t* cov_off);
+
+/* Host copies of FP64 tables (NULL skips):
+ *   roots   [p_half]  R_{k,q}, the Bessel zeros (Eq.(FB))
+ *   norms   [p_half]  N_{k,q} = 1 / (c sqrt(pi) |J_{k+1}(R_{k,q})|)
+ *   xi, w   [n_xi]    Gauss-Legendre nodes and weights on [0, c]
+ *   radial  [p_half * n_xi]  row (k,q): N_{k,q} J_k(R_{k,q} xi_j / c) xi_j w_j (Eq.(a)) */
+int fb_plan_host_tables(fb_plan_t plan, double* roots, double* norms, double* xi, double* w, double* radial);
+
+/* Workspace bytes that make fb_expand / fb_adjoint process `batch` images per
+ * internal pass (any workspace of at least fb_workspace_bytes(plan, 1, ...) works;
+ * larger ones let the library use larger passes). */
+size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision);
+
+/* a = T* I (Algorithm 1, steps 3-4) for n images.  images and coeffs as in
+ * the conventions above; ws is device memory of ws_bytes bytes.  Asynchronous
+ * on `stream` (a hipStream_t; NULL is the null stream).  n = 0 is a no-op.
+ * Errors: FB_ERR_INVALID_ARG (NULL pointer with n > 0, n < 0, bad precision),
+ * FB_ERR_WORKSPACE, FB_ERR_NO_DEVICE, FB_ERR_HIP (launch failure). */
+int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Synthesis I = T b, the transpose of fb_expand with respect to the coefficient
+ * inner product sum_q b_{0q} c_{0q} + 2 Re sum_{k>0,q} conj(b_{kq}) c_{kq}
+ * (the +-k terms folded together, Sec. II-B), i.e.
+ *   (T b)(x) = Re sum_{k=-kmax}^{kmax} sum_q b_{kq} conj(M_{kq}(x)),  b_{-k} = conj(b_k),
+ * where M_{kq} is row (k,q) of T*.  The imaginary parts of the k = 0 inputs
+ * are ignored.  `weight_mode` 0 applies the fold weights (1 for k = 0, 2 for
+ * k > 0); 1 applies weight 1 to every k (the plain real transpose of
+ * fb_expand, used for gradients).  Asynchronous; same errors as fb_expand. */
+int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Accumulate the steerable covariance of n coefficient vectors (Eqs.(ck),(ck_0)):
+ *   G[cov_off[k] + q p_k + q'] += sum_i Re(a^i_{kq} conj(a^i_{kq'}))   (FP64, full p_k x p_k blocks)
+ *   S0[q] += sum_i a^i_{0q}                                           (FP64 [p_0])
+ *   *count += n                                                       (host int64)
+ * G and S0 are device memory owned by the caller (zero them before the first
+ * call).  Partial sums are formed in FP32 over at most 256 images and added to
+ * FP64 in a fixed order, so results are bitwise reproducible.  Asynchronous.
+ * precision selects FB_FP32 or FB_BF16X3 products. */
+int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
+                  int precision, void* stream);
+
+/* Finalise and diagonalise (Algorithm 2, steps 1 and 4), all FP64 on the device:
+ *   m = S0 / count;  C^(0) = G^(0)/count - m m^T;  C^(k) = G^(k)/count (k > 0);
+ *   evals [p_half]: eigenvalues of each C^(k), descending within block k (at coef_off[k]);
+ *   evecs [cov_size]: block k at cov_off[k], p_k x p_k row-major, column l = u_l,
+ *         sign-normalised so that its entry of largest magnitude is positive;
+ *   C_out [cov_size] (nullable): the finalised C^(k) blocks;
+ *   mean_out [p_0] (nullable): m.
+ * ws must hold fb_eig_workspace_bytes(plan) bytes.  Cyclic Jacobi sweeps until
+ * every off-diagonal entry is below 1e-15 of the block norm.  Asynchronous.
+ * Errors: FB_ERR_INVALID_ARG if count <= 0 or a required pointer is NULL. */
+int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, double* evals, double* evecs,
+           double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream);
+size_t fb_eig_workspace_bytes(fb_plan_t plan);
+
+/* Seeded synthetic inputs on the device (not part of the method): Philox-4x32-10
+ * (Salmon et al., SC'11) words with counter (word_block, index_lo, index_hi,
+ * stream) and key (seed_lo, seed_hi), Box-Muller normals on word pairs.
+ *   fb_synth_normals: out[i][t] = scale * z_t(seed, stream, first_index + i), t < n_per
+ *   fb_synth_words:   out[i][t] = 32-bit word t of image first_index + i
+ * Asynchronous on `stream` (the HIP stream); `rng_stream` is the Philox stream id. */
+int fb_synth_normals(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per,
+                     float scale, float* out, void* stream);
+int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per,
+                   uint32_t* out, void* stream);
+
+/* Human-readable text for a return code. */
+const char* fb_error_string(int code);
+
+/* HIP error code of the last failing HIP call made for this plan (0 if none). */
+int fb_plan_last_hip_error(fb_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFBSPCA_H */

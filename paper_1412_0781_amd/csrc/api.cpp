@@ -1,0 +1,223 @@
+// C ABI of the library (see include/ffbspca.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/ffbspca.h"
+#include "kernels.h"
+#include "plan.h"
+
+struct fb_plan_s {
+  fb::Plan pl;
+};
+
+namespace {
+
+constexpr int64_t kMaxPassImages = 16384;  // gridDim.y of the per-image kernels stays far below 65535
+
+int make_plan(int L, double c, double R, bool device, fb_plan_t* out) {
+  if (!out) return FB_ERR_INVALID_ARG;
+  *out = nullptr;
+  fb_plan_s* h = new (std::nothrow) fb_plan_s();
+  if (!h) return FB_ERR_ALLOC;
+  int rc;
+  try {
+    rc = fb::build_host_plan(L, c, R, h->pl);
+  } catch (const std::bad_alloc&) {
+    rc = FB_ERR_ALLOC;
+  } catch (...) {
+    rc = FB_ERR_INVALID_ARG;
+  }
+  if (rc == FB_OK && device) rc = fb::upload_plan(h->pl);
+  if (rc != FB_OK) {
+    fb::free_device(h->pl);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return FB_OK;
+}
+
+int hip_rc(fb::Plan& pl, hipError_t e) {
+  if (e == hipSuccess) return FB_OK;
+  pl.last_hip = e;
+  return FB_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fb_plan(int L, double c, double R, fb_plan_t* out) { return make_plan(L, c, R, true, out); }
+
+int fb_plan_host(int L, double c, double R, fb_plan_t* out) { return make_plan(L, c, R, false, out); }
+
+int fb_plan_destroy(fb_plan_t plan) {
+  if (!plan) return FB_OK;
+  fb::free_device(plan->pl);
+  delete plan;
+  return FB_OK;
+}
+
+int fb_plan_info(fb_plan_t plan, fb_info* out) {
+  if (!plan || !out) return FB_ERR_INVALID_ARG;
+  const fb::Plan& p = plan->pl;
+  out->L = p.L;
+  out->c = p.c;
+  out->R = p.R;
+  out->n_xi = p.n_xi;
+  out->n_theta = p.n_theta;
+  out->k_max = p.k_max;
+  out->p0 = p.p0;
+  out->p_half = p.p_half;
+  out->p_total = p.p_total;
+  out->cov_size = p.cov_size;
+  out->grid_n = p.N;
+  out->kernel_w = p.w;
+  out->kernel_beta = p.beta;
+  out->has_device = p.has_device ? 1 : 0;
+  return FB_OK;
+}
+
+int fb_plan_tables(fb_plan_t plan, int32_t* k, int32_t* q, int32_t* p, int64_t* coef_off, int64_t* cov_off) {
+  if (!plan) return FB_ERR_INVALID_ARG;
+  const fb::Plan& pl = plan->pl;
+  if (k) std::copy(pl.kq_k.begin(), pl.kq_k.end(), k);
+  if (q) std::copy(pl.kq_q.begin(), pl.kq_q.end(), q);
+  if (p) std::copy(pl.p.begin(), pl.p.end(), p);
+  if (coef_off) std::copy(pl.coef_off.begin(), pl.coef_off.end(), coef_off);
+  if (cov_off) std::copy(pl.cov_off.begin(), pl.cov_off.end(), cov_off);
+  return FB_OK;
+}
+
+int fb_plan_host_tables(fb_plan_t plan, double* roots, double* norms, double* xi, double* w, double* radial) {
+  if (!plan) return FB_ERR_INVALID_ARG;
+  const fb::Plan& pl = plan->pl;
+  if (roots) std::copy(pl.roots.begin(), pl.roots.end(), roots);
+  if (norms) std::copy(pl.norms.begin(), pl.norms.end(), norms);
+  if (xi) std::copy(pl.xi.begin(), pl.xi.end(), xi);
+  if (w) std::copy(pl.wq.begin(), pl.wq.end(), w);
+  if (radial) std::copy(pl.radial.begin(), pl.radial.end(), radial);
+  return FB_OK;
+}
+
+size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision) {
+  (void)precision;
+  if (!plan || batch < 1) return 0;
+  return fb::pass_layout(plan->pl).per_image * (size_t)std::min<int64_t>(batch, kMaxPassImages);
+}
+
+int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision, void* ws,
+              size_t ws_bytes, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  if (precision != FB_FP32 && precision != FB_BF16X3) return FB_ERR_INVALID_ARG;
+  if (n == 0) return FB_OK;
+  if (!images || !coeffs || !ws) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  fb::PassLayout lay = fb::pass_layout(pl);
+  int64_t nb = std::min<int64_t>({n, (int64_t)(ws_bytes / lay.per_image), kMaxPassImages});
+  if (nb < 1) return FB_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  float2* bufA = (float2*)ws;
+  float2* bufB = (float2*)((char*)ws + lay.bytes_a * (size_t)nb);
+  const size_t img_stride = (size_t)pl.L * pl.L;
+  const size_t coef_stride = 2 * (size_t)pl.p_half;
+  for (int64_t s = 0; s < n; s += nb) {
+    int m = (int)std::min<int64_t>(nb, n - s);
+    int rc = hip_rc(pl, fb::launch_forward_nufft(pl, images + s * img_stride, m, bufA, bufB, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_forward_angular(pl, bufA, bufB, m, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_radial_forward(pl, bufB, coeffs + s * coef_stride, m, precision, st));
+    if (rc != FB_OK) return rc;
+  }
+  return FB_OK;
+}
+
+int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode, void* ws,
+               size_t ws_bytes, void* stream) {
+  if (!plan || n < 0 || (weight_mode != 0 && weight_mode != 1)) return FB_ERR_INVALID_ARG;
+  if (n == 0) return FB_OK;
+  if (!images || !coeffs || !ws) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  fb::PassLayout lay = fb::pass_layout(pl);
+  int64_t nb = std::min<int64_t>({n, (int64_t)(ws_bytes / lay.per_image), kMaxPassImages});
+  if (nb < 1) return FB_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  float2* bufA = (float2*)ws;
+  float2* bufB = (float2*)((char*)ws + lay.bytes_a * (size_t)nb);
+  const size_t img_stride = (size_t)pl.L * pl.L;
+  const size_t coef_stride = 2 * (size_t)pl.p_half;
+  for (int64_t s = 0; s < n; s += nb) {
+    int m = (int)std::min<int64_t>(nb, n - s);
+    int rc = hip_rc(pl, fb::launch_radial_adjoint(pl, coeffs + s * coef_stride, bufB, m, weight_mode, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_adjoint_angular(pl, bufB, bufA, m, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_adjoint_nufft(pl, bufA, m, bufA, bufB, images + s * img_stride, st));
+    if (rc != FB_OK) return rc;
+  }
+  return FB_OK;
+}
+
+int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
+                  int precision, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  if (precision != FB_FP32 && precision != FB_BF16X3) return FB_ERR_INVALID_ARG;
+  if (!G || !S0 || !count) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (n == 0) return FB_OK;
+  if (!coeffs) return FB_ERR_INVALID_ARG;
+  int rc = hip_rc(pl, fb::launch_covariance(pl, coeffs, n, G, S0, precision, (hipStream_t)stream));
+  if (rc == FB_OK) *count += n;
+  return rc;
+}
+
+size_t fb_eig_workspace_bytes(fb_plan_t plan) { return plan ? fb::eig_workspace_bytes(plan->pl) : 0; }
+
+int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, double* evals, double* evecs,
+           double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || count <= 0 || !G || !S0 || !evals || !evecs || !ws) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (ws_bytes < fb::eig_workspace_bytes(pl)) return FB_ERR_WORKSPACE;
+  return hip_rc(pl, fb::launch_eig(pl, G, S0, count, evals, evecs, C_out, mean_out, (double*)ws, (hipStream_t)stream));
+}
+
+int fb_synth_normals(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per, float scale,
+                     float* out, void* stream) {
+  if (n < 0 || n_per < 0 || first_index < 0) return FB_ERR_INVALID_ARG;
+  if (n == 0 || n_per == 0) return FB_OK;
+  if (!out) return FB_ERR_INVALID_ARG;
+  return fb::launch_synth_normals(seed, rng_stream, first_index, n, n_per, scale, out, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FB_OK
+             : FB_ERR_HIP;
+}
+
+int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per, uint32_t* out,
+                   void* stream) {
+  if (n < 0 || n_per < 0 || first_index < 0) return FB_ERR_INVALID_ARG;
+  if (n == 0 || n_per == 0) return FB_OK;
+  if (!out) return FB_ERR_INVALID_ARG;
+  return fb::launch_synth_words(seed, rng_stream, first_index, n, n_per, out, (hipStream_t)stream) == hipSuccess
+             ? FB_OK
+             : FB_ERR_HIP;
+}
+
+const char* fb_error_string(int code) {
+  switch (code) {
+    case FB_OK: return "success";
+    case FB_ERR_INVALID_ARG: return "invalid argument";
+    case FB_ERR_ALLOC: return "allocation failed";
+    case FB_ERR_HIP: return "HIP runtime error";
+    case FB_ERR_UNSUPPORTED: return "unsupported plan parameters";
+    case FB_ERR_NO_DEVICE: return "plan has no device tables";
+    case FB_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int fb_plan_last_hip_error(fb_plan_t plan) { return plan ? (int)plan->pl.last_hip : 0; }
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Algorithm 2, steps 1 and 4 in FP64 on the device: finalise each covariance
+// block C^(k) = G^(k)/n (k = 0: minus m m^T, m the mean of a_{0,q}) and
+// diagonalise it by cyclic two-sided Jacobi rotations.  One workgroup per k;
+// every round applies p_k/2 disjoint rotations in parallel (round-robin
+// pairing), so a sweep of p_k - 1 rounds visits every pair once.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace fb {
+
+constexpr int EIG_THREADS = 256;
+constexpr int EIG_MAX_SWEEPS = 40;
+
+__device__ double block_sum(double v, double* red) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];  // fixed order
+  return s;
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ G, const double* __restrict__ S0,
+                                                     long long count, double* __restrict__ evals,
+                                                     double* __restrict__ evecs, double* __restrict__ C_out,
+                                                     double* __restrict__ mean_out, double* __restrict__ work,
+                                                     const int* __restrict__ p, const int* __restrict__ coef_off,
+                                                     const long long* __restrict__ cov_off) {
+  __shared__ double red[EIG_THREADS / 64];
+  __shared__ double cs[EIG_MAX_P / 2], sn[EIG_MAX_P / 2];
+  __shared__ int pa[EIG_MAX_P / 2], pb[EIG_MAX_P / 2];
+  __shared__ int stop;
+  const int k = blockIdx.x;
+  const int pk = p[k];
+  const long long base = cov_off[k];
+  double* A = work + base;
+  double* V = evecs + base;
+  const double inv = 1.0 / (double)count;
+  for (int i = threadIdx.x; i < pk * pk; i += blockDim.x) {
+    int q = i / pk, r = i - q * pk;
+    double v = G[base + i] * inv;
+    if (k == 0) v -= (S0[q] * inv) * (S0[r] * inv);
+    A[i] = v;
+    if (C_out) C_out[base + i] = v;
+    V[i] = (q == r) ? 1.0 : 0.0;
+  }
+  if (k == 0 && mean_out)
+    for (int q = threadIdx.x; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
+  __syncthreads();
+
+  const int m = pk + (pk & 1);  // even number of positions; position pk is a dummy when pk is odd
+  const int npair = m / 2;
+  for (int sweep = 0; sweep < EIG_MAX_SWEEPS && pk > 1; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = threadIdx.x; i < pk * pk; i += blockDim.x) {
+      int q = i / pk, r = i - q * pk;
+      double a2 = A[i] * A[i];
+      tot += a2;
+      if (q != r) off += a2;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (threadIdx.x == 0) stop = (off <= 1e-30 * tot) || (off == 0.0);
+    __syncthreads();
+    if (stop) break;
+    for (int round = 0; round < m - 1; ++round) {
+      for (int i = threadIdx.x; i < npair; i += blockDim.x) {
+        int t0 = i, t1 = m - 1 - i;
+        int a = t0 == 0 ? 0 : 1 + (t0 - 1 + round) % (m - 1);
+        int b = t1 == 0 ? 0 : 1 + (t1 - 1 + round) % (m - 1);
+        double c = 1.0, s = 0.0;
+        if (a < pk && b < pk) {
+          double apq = A[(size_t)a * pk + b];
+          if (apq != 0.0) {
+            double app = A[(size_t)a * pk + a], aqq = A[(size_t)b * pk + b];
+            double theta = (aqq - app) / (2.0 * apq);
+            double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        cs[i] = c;
+        sn[i] = s;
+        pa[i] = a;
+        pb[i] = b;
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      for (int i = threadIdx.x; i < npair * pk; i += blockDim.x) {
+        int pr = i / pk, r = i - pr * pk;
+        int a = pa[pr], b = pb[pr];
+        if (a >= pk || b >= pk) continue;
+        double c = cs[pr], s = sn[pr];
+        double x = A[(size_t)r * pk + a], y = A[(size_t)r * pk + b];
+        A[(size_t)r * pk + a] = c * x - s * y;
+        A[(size_t)r * pk + b] = s * x + c * y;
+        x = V[(size_t)r * pk + a];
+        y = V[(size_t)r * pk + b];
+        V[(size_t)r * pk + a] = c * x - s * y;
+        V[(size_t)r * pk + b] = s * x + c * y;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int i = threadIdx.x; i < npair * pk; i += blockDim.x) {
+        int pr = i / pk, r = i - pr * pk;
+        int a = pa[pr], b = pb[pr];
+        if (a >= pk || b >= pk) continue;
+        double c = cs[pr], s = sn[pr];
+        double x = A[(size_t)a * pk + r], y = A[(size_t)b * pk + r];
+        A[(size_t)a * pk + r] = c * x - s * y;
+        A[(size_t)b * pk + r] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+  }
+  // eigenvalues = diagonal, ordered descending (ties by index); columns sign-normalised
+  // so that the entry of largest magnitude (lowest index on ties) is positive
+  __shared__ int rk[EIG_MAX_P];
+  const int off_k = coef_off[k];
+  for (int col = threadIdx.x; col < pk; col += blockDim.x) {
+    double di = A[(size_t)col * pk + col];
+    int rank = 0;
+    for (int j = 0; j < pk; ++j) {
+      double dj = A[(size_t)j * pk + j];
+      rank += (dj > di) || (dj == di && j < col);
+    }
+    rk[col] = rank;
+    evals[off_k + rank] = di;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < pk * pk; i += blockDim.x) A[i] = V[i];  // A is scratch from here on
+  __syncthreads();
+  for (int col = threadIdx.x; col < pk; col += blockDim.x) {
+    int imax = 0;
+    double vmax = -1.0;
+    for (int r = 0; r < pk; ++r) {
+      double v = fabs(A[(size_t)r * pk + col]);
+      if (v > vmax) {
+        vmax = v;
+        imax = r;
+      }
+    }
+    double sg = A[(size_t)imax * pk + col] < 0 ? -1.0 : 1.0;
+    int rank = rk[col];
+    for (int r = 0; r < pk; ++r) V[(size_t)r * pk + rank] = sg * A[(size_t)r * pk + col];
+  }
+}
+
+size_t eig_workspace_bytes(const Plan& pl) { return (size_t)pl.cov_size * sizeof(double); }
+
+hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
+                      double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, count, evals, evecs,
+                     C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+  return hipGetLastError();
+}
+
+}  // namespace fb

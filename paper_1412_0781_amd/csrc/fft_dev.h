@@ -1,0 +1,196 @@
+// Mixed-radix Stockham FFT on LDS for gfx950 workgroups.
+//
+// `count` independent transforms of length d.n sit at buf + t * stride (t <
+// count) in LDS.  Each stage reads one buffer and writes the other (autosort,
+// natural order out); the caller passes both and receives the one holding the
+// result.  Forward transform: X_m = sum_x x_x exp(-2 pi i m x / n).  The
+// inverse (exp(+...), unnormalised) is obtained as conj(FFT(conj(x))).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace fb {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// In-register DFT of length R with the forward sign.
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<2> {
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <>
+struct Dft<4> {
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    float2 b0 = cadd(v[1], v[3]), b1 = cmul_mi(csub(v[1], v[3]));
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, b1);
+    v[3] = csub(a1, b1);
+  }
+};
+
+template <>
+struct Dft<8> {
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    const float r = 0.70710678118654752440f;
+    // radix-2 over pairs (0,4),(1,5),(2,6),(3,7)
+    float2 a[4], b[4];
+    for (int i = 0; i < 4; ++i) {
+      a[i] = cadd(v[i], v[i + 4]);
+      b[i] = csub(v[i], v[i + 4]);
+    }
+    // twiddles w8^i on b
+    b[1] = make_float2(r * (b[1].x + b[1].y), r * (b[1].y - b[1].x));
+    b[2] = cmul_mi(b[2]);
+    b[3] = make_float2(r * (b[3].y - b[3].x), -r * (b[3].x + b[3].y));
+    // two radix-4 DFTs
+    Dft<4>::run(a, nullptr, 0, 0);
+    Dft<4>::run(b, nullptr, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = a[i];
+      v[2 * i + 1] = b[i];
+    }
+  }
+};
+
+template <>
+struct Dft<3> {
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    const float c1 = -0.5f, s1 = -0.86602540378443864676f;  // exp(-2 pi i / 3)
+    float2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    float2 m = make_float2(v[0].x + c1 * t1.x, v[0].y + c1 * t1.y);
+    float2 n = make_float2(-s1 * t2.y, s1 * t2.x);  // i s1 t2
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, n);
+    v[2] = csub(m, n);
+  }
+};
+
+template <>
+struct Dft<5> {
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    const float s1 = -0.95105651629515357212f, s2 = -0.58778525229247312917f;  // forward sign
+    float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    float2 x0 = v[0];
+    float2 m1 = make_float2(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+    float2 m2 = make_float2(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+    // i*(s1 t3 + s2 t4) and i*(s2 t3 - s1 t4)
+    float2 u1 = make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+    float2 u2 = make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+    float2 iu1 = make_float2(-u1.y, u1.x), iu2 = make_float2(-u2.y, u2.x);
+    v[0] = make_float2(x0.x + t1.x + t2.x, x0.y + t1.y + t2.y);
+    v[1] = cadd(m1, iu1);
+    v[4] = csub(m1, iu1);
+    v[2] = cadd(m2, iu2);
+    v[3] = csub(m2, iu2);
+  }
+};
+
+// Generic odd prime R <= 31: direct O(R^2) DFT with roots taken from the twiddle table of length n.
+template <int RMAX>
+__device__ __forceinline__ void dft_generic(float2* v, int R, const float2* tw, int n) {
+  float2 out[RMAX];
+  int step = n / R;
+  for (int m = 0; m < R; ++m) {
+    float2 s = make_float2(0.f, 0.f);
+    for (int x = 0; x < R; ++x) s = cadd(s, cmul(v[x], tw[((m * x) % R) * step]));
+    out[m] = s;
+  }
+  for (int m = 0; m < R; ++m) v[m] = out[m];
+}
+
+// One Stockham stage of radix R for `count` transforms (stride `stride`) of length n.
+template <int R>
+__device__ __forceinline__ void fft_stage_r(const float2* __restrict__ in, float2* __restrict__ out, int n, int Ns,
+                                            int count, int stride, const float2* __restrict__ tw, int tid,
+                                            int nthr) {
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  for (int idx = tid; idx < count * nb; idx += nthr) {
+    int t = idx / nb, j = idx - t * nb;
+    const float2* src = in + t * stride;
+    float2* dst = out + t * stride;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    int k = j % Ns;
+    if (k) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * twstep]);
+    }
+    Dft<R>::run(v, tw, n, R);
+    int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+__device__ __forceinline__ void fft_stage_generic(const float2* __restrict__ in, float2* __restrict__ out, int n,
+                                                  int R, int Ns, int count, int stride,
+                                                  const float2* __restrict__ tw, int tid, int nthr) {
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  for (int idx = tid; idx < count * nb; idx += nthr) {
+    int t = idx / nb, j = idx - t * nb;
+    const float2* src = in + t * stride;
+    float2* dst = out + t * stride;
+    float2 v[31];
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    int k = j % Ns;
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(k * r * twstep) % n]);
+    dft_generic<31>(v, R, tw, n);
+    int base = (j - k) * R + k;
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+// Full forward FFT; buf holds the input and must be followed by scratch of the
+// same size at `tmp`.  Returns the pointer holding the result.  All threads of
+// the block must call it; it synchronises the block between stages.
+__device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int stride, const FftDesc& d,
+                                  const float2* __restrict__ tw_all) {
+  const float2* tw = tw_all + d.tw_off;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  float2* in = buf;
+  float2* out = tmp;
+  int Ns = 1;
+  for (int s = 0; s < d.nstage; ++s) {
+    int R = d.radix[s];
+    switch (R) {
+      case 8: fft_stage_r<8>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 4: fft_stage_r<4>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 2: fft_stage_r<2>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 3: fft_stage_r<3>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 5: fft_stage_r<5>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      default: fft_stage_generic(in, out, d.n, R, Ns, count, stride, tw, tid, nthr); break;
+    }
+    __syncthreads();
+    float2* t = in;
+    in = out;
+    out = t;
+    Ns *= R;
+  }
+  return in;
+}
+
+}  // namespace fb

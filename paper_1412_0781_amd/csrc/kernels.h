@@ -1,0 +1,43 @@
+// Launchers of the gfx950 kernels (all asynchronous on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace fb {
+
+// Largest p_k the device eigensolver handles (one workgroup per block C^(k)).
+constexpr int EIG_MAX_P = 256;
+
+// Eq.(nufft) for nimg images: images -> polar half-ring samples in bufA (bufB is scratch).
+hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
+                                hipStream_t st);
+// Eq.(1DFFT): polar samples P -> angular spectrum Fh [k][j][image] (complex).
+hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st);
+// Eq.(a): Fh -> coefficients [image][p_half][2].
+hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs, int nimg, int precision,
+                                 hipStream_t st);
+
+// transposes
+hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
+                                 hipStream_t st);
+hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st);
+hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
+                                float* images, hipStream_t st);
+
+// Eqs.(ck),(ck_0) accumulation and the k = 0 sums.
+hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
+                             hipStream_t st);
+
+// Algorithm 2, steps 1 and 4 (FP64).
+hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
+                      double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st);
+size_t eig_workspace_bytes(const Plan& pl);
+
+// seeded inputs
+hipError_t launch_synth_normals(unsigned long long seed, unsigned rng_stream, long long first, long long n,
+                                long long n_per, float scale, float* out, hipStream_t st);
+hipError_t launch_synth_words(unsigned long long seed, unsigned rng_stream, long long first, long long n,
+                              long long n_per, unsigned* out, hipStream_t st);
+
+}  // namespace fb

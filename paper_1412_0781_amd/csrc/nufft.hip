@@ -1,0 +1,427 @@
+// Non-uniform FFT stages of the expansion (Algorithm 1, step 3, Eq.(nufft)),
+// the angular FFT (Eq.(1DFFT)) and their transposes, for gfx950.
+//
+// Forward, per image (s = 1, full L x L grid):
+//   rows    : deconvolve by 1/phi_hat(x1/N) 1/phi_hat(x2/N), zero-pad to N, FFT along i2
+//             (two real rows packed in one complex FFT), keep m2 = -hw..N/2+hw
+//   cols    : FFT along i1 of every kept m2 row  ->  oversampled half-plane grid G(m1, m2)
+//   gather  : F(xi_j, theta_l) = sum_taps phi(t1 - m1) phi(t2 - m2) G(m1, m2), l < n_theta/2
+//   angular : real FFT of length n_theta of s_l = Re F_l + Im F_l, s_{l+H} = Re F_l - Im F_l,
+//             then Fhat(k) = (2 pi/n_theta) S(k) (k even) or i (2 pi/n_theta) S(k) (k odd)
+// Adjoint: the transpose of each stage in reverse order.
+#include <hip/hip_runtime.h>
+
+#include "fft_dev.h"
+#include "kernels.h"
+
+namespace fb {
+
+__device__ __forceinline__ float es_eval(float z, float beta) {
+  float t = 1.0f - z * z;
+  return t > 0.f ? __expf(beta * (sqrtf(t) - 1.0f)) : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// forward rows: images [n][L][L] -> G1 [n][M2][L]   (m2 = -hw..N/2+hw)
+// block: RP row pairs of one image
+// ---------------------------------------------------------------------------
+__global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g1, const float* __restrict__ deconv,
+                           FftDesc fd, const float2* __restrict__ tw, int L, int M2, int hw, int RP) {
+  extern __shared__ float2 sm[];
+  const int N = fd.n;
+  float2* buf = sm;
+  float2* tmp = sm + RP * N;
+  const int im = blockIdx.y;
+  const int pair0 = blockIdx.x * RP;
+  const int npairs = (L + 1) / 2;
+  const int np = min(RP, npairs - pair0);
+  const int x0 = -((L - 1 + 1) / 2);  // -ceil((L-1)/2)
+  const float* src = img + (size_t)im * L * L;
+  for (int i = threadIdx.x; i < RP * N; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int i = threadIdx.x; i < np * 2 * L; i += blockDim.x) {
+    int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
+    int a = 2 * (pair0 + p) + which;
+    int pos = x0 + b;
+    pos += (pos < 0) ? N : 0;
+    float v = (a < L) ? src[(size_t)a * L + b] * deconv[a] * deconv[b] : 0.f;
+    if (which == 0) buf[p * N + pos].x = v;
+    else buf[p * N + pos].y = v;
+  }
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, np, N, fd, tw);
+  // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i)
+  float2* out = g1 + (size_t)im * M2 * L;
+  for (int i = threadIdx.x; i < M2 * 2 * np; i += blockDim.x) {
+    int mi = i / (2 * np), r = i - mi * 2 * np;
+    int p = r >> 1, which = r & 1;
+    int a = 2 * (pair0 + p) + which;
+    if (a >= L) continue;
+    int m2 = mi - hw;
+    int mp = m2 % N; mp += (mp < 0) ? N : 0;
+    int mn = (-m2) % N; mn += (mn < 0) ? N : 0;
+    float2 z1 = res[p * N + mp], z2 = cconj(res[p * N + mn]);
+    float2 v;
+    if (which == 0) v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+    else {
+      float2 u = csub(z1, z2);
+      v = make_float2(0.5f * u.y, -0.5f * u.x);
+    }
+    out[(size_t)mi * L + a] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward cols: G1 [n][M2][L] -> G [n][M2][N]
+// ---------------------------------------------------------------------------
+__global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g, FftDesc fd,
+                           const float2* __restrict__ tw, int L, int M2, int CP) {
+  extern __shared__ float2 sm[];
+  const int N = fd.n;
+  float2* buf = sm;
+  float2* tmp = sm + CP * N;
+  const int im = blockIdx.y;
+  const int r0 = blockIdx.x * CP;
+  const int nc = min(CP, M2 - r0);
+  const int x0 = -((L - 1 + 1) / 2);
+  for (int i = threadIdx.x; i < CP * N; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  const float2* src = g1 + ((size_t)im * M2 + r0) * L;
+  for (int i = threadIdx.x; i < nc * L; i += blockDim.x) {
+    int cidx = i / L, a = i - cidx * L;
+    int pos = x0 + a;
+    pos += (pos < 0) ? N : 0;
+    buf[cidx * N + pos] = src[(size_t)cidx * L + a];
+  }
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, nc, N, fd, tw);
+  float2* dst = g + ((size_t)im * M2 + r0) * N;
+  for (int i = threadIdx.x; i < nc * N; i += blockDim.x) dst[i] = res[i];
+}
+
+// ---------------------------------------------------------------------------
+// forward gather: G [n][M2][N] -> P [n][n_xi * H]
+// thread per polar node; blockIdx.y covers groups of IG images
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P, const NodeTap* __restrict__ nodes,
+                             int nnodes, int N, int M2, float beta, int nimg, int IG) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nnodes) return;
+  NodeTap t = nodes[n];
+  float w1[W], w2[W];
+  const float s = 2.0f / W;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    w1[a] = es_eval((t.f1 - a) * s, beta);
+    w2[a] = es_eval((t.f2 - a) * s, beta);
+  }
+  int col[W];
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    int cc = t.b1 + a;
+    col[a] = cc >= N ? cc - N : cc;
+  }
+  const int i0 = blockIdx.y * IG;
+  const int i1 = min(nimg, i0 + IG);
+  for (int im = i0; im < i1; ++im) {
+    const float2* gi = g + (size_t)im * M2 * N + (size_t)t.b2 * N;
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int bb = 0; bb < W; ++bb) {
+      float rx = 0.f, ry = 0.f;
+      const float2* row = gi + (size_t)bb * N;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        float2 v = row[col[a]];
+        rx = fmaf(w1[a], v.x, rx);
+        ry = fmaf(w1[a], v.y, ry);
+      }
+      ax = fmaf(w2[bb], rx, ax);
+      ay = fmaf(w2[bb], ry, ay);
+    }
+    P[(size_t)im * nnodes + n] = make_float2(ax, ay);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward angular: P [n][n_xi][H] -> Fh [K+1][n_xi][ncol]  (ncol = 2 * images in the pass)
+// block: ring j for AG consecutive images
+// ---------------------------------------------------------------------------
+__global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__ Fh, FftDesc fd,
+                              const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
+                              int nimg, int AG, float scale) {
+  extern __shared__ float2 sm[];
+  const int H = fd.n;
+  float2* buf = sm;
+  float2* tmp = sm + AG * H;
+  const int j = blockIdx.x;
+  const int g0 = blockIdx.y * AG;
+  const int ng = min(AG, nimg - g0);
+  // packed z_m = s_{2m} + i s_{2m+1}, with s_t = u_t + v_t (t < H), u_{t-H} - v_{t-H} (t >= H)
+  for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
+    int gg = i / H, m = i - gg * H;
+    const float2* ring = P + ((size_t)(g0 + gg) * n_xi + j) * H;
+    float sv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      int t = 2 * m + e;
+      float2 f = ring[t < H ? t : t - H];
+      sv[e] = t < H ? (f.x + f.y) : (f.x - f.y);
+    }
+    buf[gg * H + m] = make_float2(sv[0], sv[1]);
+  }
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, ng, H, fd, tw);
+  const size_t ncol = 2 * (size_t)nimg;
+  for (int i = threadIdx.x; i < (K + 1) * ng; i += blockDim.x) {
+    int k = i / ng, gg = i - k * ng;
+    float2 zk = res[gg * H + (k == 0 ? 0 : k)];
+    float2 zc = cconj(res[gg * H + (k == 0 ? 0 : H - k)]);
+    // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
+    float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+    float2 d = csub(zk, zc);
+    float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
+    float2 S = cadd(e, cmul(angtw[k], o));
+    float2 F = (k & 1) ? make_float2(-S.y * scale, S.x * scale) : make_float2(S.x * scale, S.y * scale);
+    Fh[((size_t)k * n_xi + j) * (ncol / 2) + g0 + gg] = F;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint angular: D [K+1][n_xi][ncol] -> Q [n][n_xi][H]
+// Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H}),  s'_t = Re sum_{k<=K} E_k e^{2 pi i k t / n_theta},
+// E_k = c D_k (k even), -i c D_k (k odd)
+// ---------------------------------------------------------------------------
+__global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__ Q, FftDesc fd,
+                              const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
+                              int nimg, int AG, float scale) {
+  extern __shared__ float2 sm[];
+  const int H = fd.n;
+  float2* buf = sm;
+  float2* tmp = sm + AG * H;
+  const int j = blockIdx.x;
+  const int g0 = blockIdx.y * AG;
+  const int ng = min(AG, nimg - g0);
+  auto Ek = [&](int k, int gg) -> float2 {
+    float2 d = D[((size_t)k * n_xi + j) * nimg + g0 + gg];
+    return (k & 1) ? make_float2(d.y * scale, -d.x * scale) : make_float2(d.x * scale, d.y * scale);
+  };
+  // Zin(k') = (Y_k' + Y_{k'+H}) + i e^{+i pi k'/H} (Y_k' - Y_{k'+H}); stored conjugated for the forward FFT
+  for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
+    int gg = i / H, kp = i - gg * H;
+    float2 y0 = make_float2(0.f, 0.f), y1 = make_float2(0.f, 0.f);
+    if (kp == 0) {
+      y0 = make_float2(Ek(0, gg).x, 0.f);
+    } else if (kp <= K) {
+      float2 e = Ek(kp, gg);
+      y0 = make_float2(0.5f * e.x, 0.5f * e.y);
+    }
+    int km = H - kp;  // Y_{k'+H} = conj(E_{H-k'}) / 2
+    if (km >= 1 && km <= K) {
+      float2 e = Ek(km, gg);
+      y1 = make_float2(0.5f * e.x, -0.5f * e.y);
+    }
+    float2 ze = cadd(y0, y1);
+    float2 zo = cmul(cconj(angtw[kp]), csub(y0, y1));
+    float2 zin = make_float2(ze.x - zo.y, ze.y + zo.x);
+    buf[gg * H + kp] = cconj(zin);
+  }
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, ng, H, fd, tw);
+  // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1}
+  for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
+    int gg = i / H, l = i - gg * H;
+    auto sp = [&](int t) -> float {
+      float2 z = res[gg * H + (t >> 1)];
+      return (t & 1) ? -z.y : z.x;
+    };
+    float a = sp(l), b = sp(l + H);
+    Q[((size_t)(g0 + gg) * n_xi + j) * H + l] = make_float2(a + b, a - b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint spread (gather form): Q [n][n_xi*H] -> Y [n][N/2+1][N]
+// one wavefront per grid point, lanes split its entries, fixed-order reduction
+// ---------------------------------------------------------------------------
+template <int IG>
+__global__ void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y, const int* __restrict__ ptr,
+                             const SpreadEntry* __restrict__ ent, int nrows, int nnodes, int nimg) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  const int i0 = blockIdx.y * IG;
+  const int ni = min(IG, nimg - i0);
+  float ax[IG], ay[IG];
+#pragma unroll
+  for (int g = 0; g < IG; ++g) ax[g] = ay[g] = 0.f;
+  const int e0 = ptr[row], e1 = ptr[row + 1];
+  for (int e = e0 + lane; e < e1; e += 64) {
+    SpreadEntry en = ent[e];
+    uint32_t nd = en.node & 0x7fffffffu;
+    float sg = (en.node & 0x80000000u) ? -1.f : 1.f;
+#pragma unroll
+    for (int g = 0; g < IG; ++g) {
+      if (g < ni) {
+        float2 q = Q[(size_t)(i0 + g) * nnodes + nd];
+        ax[g] = fmaf(en.weight, q.x, ax[g]);
+        ay[g] = fmaf(en.weight * sg, q.y, ay[g]);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < IG; ++g) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      ax[g] += __shfl_xor(ax[g], off, 64);
+      ay[g] += __shfl_xor(ay[g], off, 64);
+    }
+  }
+  if (lane == 0) {
+    for (int g = 0; g < ni; ++g) Y[(size_t)(i0 + g) * nrows + row] = make_float2(ax[g], ay[g]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint cols: Y [n][N/2+1][N] -> Zc [n][N/2+1][L]: inverse FFT along m1, keep x1 in the pixel range
+// ---------------------------------------------------------------------------
+__global__ void k_adj_cols(const float2* __restrict__ Y, float2* __restrict__ Zc, FftDesc fd,
+                           const float2* __restrict__ tw, int L, int CP) {
+  extern __shared__ float2 sm[];
+  const int N = fd.n, Nh = N / 2 + 1;
+  float2* buf = sm;
+  float2* tmp = sm + CP * N;
+  const int im = blockIdx.y;
+  const int r0 = blockIdx.x * CP;
+  const int nc = min(CP, Nh - r0);
+  const float2* src = Y + ((size_t)im * Nh + r0) * N;
+  for (int i = threadIdx.x; i < nc * N; i += blockDim.x) buf[i] = cconj(src[i]);
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, nc, N, fd, tw);
+  const int x0 = -((L - 1 + 1) / 2);
+  float2* dst = Zc + ((size_t)im * Nh + r0) * L;
+  for (int i = threadIdx.x; i < nc * L; i += blockDim.x) {
+    int cidx = i / L, a = i - cidx * L;
+    int pos = x0 + a;
+    pos += (pos < 0) ? N : 0;
+    dst[(size_t)cidx * L + a] = cconj(res[cidx * N + pos]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint rows: Zc [n][N/2+1][L] -> images [n][L][L]
+// two real rows per complex inverse FFT of the Hermitian-completed sequences
+// ---------------------------------------------------------------------------
+__global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ img, const float* __restrict__ deconv,
+                           FftDesc fd, const float2* __restrict__ tw, int L, int RP) {
+  extern __shared__ float2 sm[];
+  const int N = fd.n, Nh = N / 2 + 1;
+  float2* buf = sm;
+  float2* tmp = sm + RP * N;
+  const int im = blockIdx.y;
+  const int pair0 = blockIdx.x * RP;
+  const int npairs = (L + 1) / 2;
+  const int np = min(RP, npairs - pair0);
+  const float2* src = Zc + (size_t)im * Nh * L;
+  // h(m) = r(m) for m <= N/2, conj r(N-m) above; h(0), h(N/2) real.  z = conj(h_a + i h_b)
+  for (int i = threadIdx.x; i < np * N; i += blockDim.x) {
+    int p = i / N, m = i - p * N;
+    int a = 2 * (pair0 + p);
+    int ms = m <= N / 2 ? m : N - m;
+    bool cj = m > N / 2;
+    float2 ra = src[(size_t)ms * L + a];
+    float2 rb = (a + 1 < L) ? src[(size_t)ms * L + a + 1] : make_float2(0.f, 0.f);
+    if (ms == 0 || 2 * ms == N) {
+      ra.y = 0.f;
+      rb.y = 0.f;
+    }
+    if (cj) {
+      ra.y = -ra.y;
+      rb.y = -rb.y;
+    }
+    float2 h = make_float2(ra.x - rb.y, ra.y + rb.x);
+    buf[p * N + m] = cconj(h);
+  }
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, np, N, fd, tw);
+  const int x0 = -((L - 1 + 1) / 2);
+  float* dst = img + (size_t)im * L * L;
+  for (int i = threadIdx.x; i < np * 2 * L; i += blockDim.x) {
+    int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
+    int a = 2 * (pair0 + p) + which;
+    if (a >= L) continue;
+    int pos = x0 + b;
+    pos += (pos < 0) ? N : 0;
+    float2 z = res[p * N + pos];  // conj of the inverse transform
+    float v = which == 0 ? z.x : -z.y;
+    dst[(size_t)a * L + b] = v * deconv[a] * deconv[b];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static int rows_per_block(int N) {
+  int rp = 32768 / (8 * N);  // two LDS buffers of rp * N complex within 64 KiB
+  return rp < 1 ? 1 : (rp > 16 ? 16 : rp);
+}
+
+hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
+                                hipStream_t st) {
+  const int N = pl.N, L = pl.L;
+  int RP = rows_per_block(N);
+  dim3 g1((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  hipLaunchKernelGGL(k_fwd_rows, g1, dim3(256), 2 * RP * N * sizeof(float2), st, images, bufA, pl.d_deconv,
+                     pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, RP);
+  int CP = rows_per_block(N);
+  dim3 g2((unsigned)((pl.M2 + CP - 1) / CP), (unsigned)nimg);
+  hipLaunchKernelGGL(k_fwd_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufA, bufB, pl.fft_grid,
+                     pl.d_tw, L, pl.M2, CP);
+  const int nnodes = pl.n_xi * pl.H;
+  const int IG = 4;
+  dim3 g3((unsigned)((nnodes + 255) / 256), (unsigned)((nimg + IG - 1) / IG));
+  hipLaunchKernelGGL(k_fwd_gather<7>, g3, dim3(256), 0, st, bufB, bufA, pl.d_nodes, nnodes, N, pl.M2,
+                     (float)pl.beta, nimg, IG);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
+  int AG = rows_per_block(pl.H);
+  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
+  const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+  hipLaunchKernelGGL(k_fwd_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, P, Fh, pl.fft_ang,
+                     pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st) {
+  int AG = rows_per_block(pl.H);
+  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
+  const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+  hipLaunchKernelGGL(k_adj_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, D, Q, pl.fft_ang,
+                     pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
+                                float* images, hipStream_t st) {
+  const int N = pl.N, L = pl.L, Nh = N / 2 + 1;
+  const int nrows = N * Nh;
+  const int nnodes = pl.n_xi * pl.H;
+  constexpr int IG = 4;
+  dim3 g1((unsigned)((nrows + 3) / 4), (unsigned)((nimg + IG - 1) / IG));
+  hipLaunchKernelGGL(k_adj_spread<IG>, g1, dim3(256), 0, st, Q, bufB, pl.d_csr_ptr, pl.d_csr, nrows, nnodes,
+                     nimg);
+  int CP = rows_per_block(N);
+  dim3 g2((unsigned)((Nh + CP - 1) / CP), (unsigned)nimg);
+  hipLaunchKernelGGL(k_adj_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufB, bufA, pl.fft_grid,
+                     pl.d_tw, L, CP);
+  int RP = rows_per_block(N);
+  dim3 g3((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  hipLaunchKernelGGL(k_adj_rows, g3, dim3(256), 2 * RP * N * sizeof(float2), st, bufA, images, pl.d_deconv,
+                     pl.fft_grid, pl.d_tw, L, RP);
+  return hipGetLastError();
+}
+
+}  // namespace fb

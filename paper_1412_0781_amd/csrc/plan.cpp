@@ -1,0 +1,309 @@
+// Plan construction (Algorithm 1, steps 1-2) in FP64 on the host, and its upload.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "hostmath.h"
+
+namespace fb {
+
+static const double kPi = 3.14159265358979323846;
+
+static uint16_t float_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+static void add_fft(FftDesc& d, int n, std::vector<float>& tw) {
+  d.n = n;
+  std::vector<int> rad;
+  fft_radices(n, rad);
+  d.nstage = (int)rad.size();
+  for (int i = 0; i < d.nstage; ++i) d.radix[i] = rad[i];
+  d.tw_off = (int)(tw.size() / 2);
+  for (int t = 0; t < n; ++t) {
+    double a = -2.0 * kPi * (double)t / (double)n;
+    tw.push_back((float)std::cos(a));
+    tw.push_back((float)std::sin(a));
+  }
+}
+
+int build_host_plan(int L, double c, double R, Plan& pl) {
+  if (L < 2) return FB_ERR_INVALID_ARG;
+  if (L > 2048) return FB_ERR_UNSUPPORTED;  // FFT rows of the 2L grid must fit the 64 KiB LDS budget
+  if (!(c > 0.0 && c <= 0.5)) return FB_ERR_INVALID_ARG;
+  if (!(R > 0.0 && R <= L / 2.0)) return FB_ERR_INVALID_ARG;
+  pl.L = L;
+  pl.c = c;
+  pl.R = R;
+  pl.n_xi = (int)std::ceil(4 * c * R);
+  pl.n_theta = (int)std::ceil(16 * c * R);
+  const double bound = 2 * kPi * c * R;
+
+  // (k, q) selection, Eq.(criterion1): q admissible iff R_{k,q+1} <= 2 pi c R
+  std::vector<std::vector<double>> z = bessel_zeros_upto(bound);
+  pl.p.clear();
+  for (size_t k = 0; k < z.size(); ++k) {
+    int pk = (int)z[k].size() - 1;
+    if (pk < 1) break;
+    pl.p.push_back(pk);
+  }
+  if (pl.p.empty()) return FB_ERR_INVALID_ARG;
+  pl.k_max = (int)pl.p.size() - 1;
+  pl.p0 = pl.p[0];
+  if (pl.p0 > 256) return FB_ERR_UNSUPPORTED;  // the device eigensolver handles blocks up to 256
+  if (pl.n_theta % 2 != 0) return FB_ERR_UNSUPPORTED;  // half-ring symmetry needs even n_theta
+  if (pl.k_max >= pl.n_theta / 2) return FB_ERR_UNSUPPORTED;
+
+  pl.coef_off.assign(pl.k_max + 2, 0);
+  pl.cov_off.assign(pl.k_max + 2, 0);
+  for (int k = 0; k <= pl.k_max; ++k) {
+    pl.coef_off[k + 1] = pl.coef_off[k] + pl.p[k];
+    pl.cov_off[k + 1] = pl.cov_off[k] + (int64_t)pl.p[k] * pl.p[k];
+  }
+  pl.p_half = pl.coef_off[pl.k_max + 1];
+  pl.cov_size = pl.cov_off[pl.k_max + 1];
+  pl.p_total = pl.p0 + 2 * (pl.p_half - pl.p0);
+  pl.kq_k.resize(pl.p_half);
+  pl.kq_q.resize(pl.p_half);
+  pl.roots.resize(pl.p_half);
+  pl.norms.resize(pl.p_half);
+  for (int k = 0; k <= pl.k_max; ++k)
+    for (int q = 0; q < pl.p[k]; ++q) {
+      int64_t i = pl.coef_off[k] + q;
+      pl.kq_k[i] = k;
+      pl.kq_q[i] = q + 1;
+      pl.roots[i] = z[k][q];
+      // N_{k,q} = 1 / (c sqrt(pi) |J_{k+1}(R_{k,q})|)   (Eq.(FB))
+      pl.norms[i] = 1.0 / (c * std::sqrt(kPi) * std::fabs(bessel_j(k + 1, z[k][q])));
+    }
+
+  // Gauss-Legendre nodes and weights on [0, c] (Eq.(a))
+  std::vector<double> gx, gw;
+  gauss_legendre(pl.n_xi, gx, gw);
+  pl.xi.resize(pl.n_xi);
+  pl.wq.resize(pl.n_xi);
+  for (int j = 0; j < pl.n_xi; ++j) {
+    pl.xi[j] = c * (gx[j] + 1.0) / 2.0;
+    pl.wq[j] = (c / 2.0) * gw[j];
+  }
+
+  // radial table B_{(k,q), j} = N_{k,q} J_k(R_{k,q} xi_j / c) xi_j w_j  (Eq.(a)); rows split over threads
+  pl.radial.assign((size_t)pl.p_half * pl.n_xi, 0.0);
+  {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        std::vector<double> buf(pl.k_max + 2);
+        for (int64_t i = t; i < pl.p_half; i += nth) {
+          int k = pl.kq_k[i];
+          for (int j = 0; j < pl.n_xi; ++j) {
+            bessel_j_all(pl.roots[i] * pl.xi[j] / c, k, buf.data());
+            pl.radial[(size_t)i * pl.n_xi + j] = pl.norms[i] * buf[k] * pl.xi[j] * pl.wq[j];
+          }
+        }
+      });
+    for (auto& x : th) x.join();
+  }
+
+  // Non-uniform FFT: oversampled grid N >= 2L (2,3,5-smooth), kernel width 7, and the
+  // kernel shape beta = 0.97 pi (1 - 1/(2 sigma)) w for oversampling sigma = N / L.
+  pl.N = next_smooth_235(2 * L);
+  if (pl.N % 2) pl.N = next_smooth_235(pl.N + 1);
+  pl.w = 7;
+  double sigma = (double)pl.N / L;
+  pl.beta = 0.97 * kPi * (1.0 - 1.0 / (2.0 * sigma)) * pl.w;
+  pl.hw = pl.w / 2 + 1;
+  pl.M2 = pl.N / 2 + 2 * pl.hw + 1;
+  pl.H = pl.n_theta / 2;
+
+  int x0 = -(int)std::ceil((L - 1) / 2.0);
+  pl.deconv.resize(L);
+  for (int a = 0; a < L; ++a) pl.deconv[a] = 1.0 / es_kernel_ft((double)(x0 + a) / pl.N, pl.w, pl.beta);
+
+  // polar half-ring nodes theta_l = 2 pi l / n_theta, l < n_theta / 2
+  pl.nodes.resize((size_t)pl.n_xi * pl.H);
+  for (int j = 0; j < pl.n_xi; ++j)
+    for (int l = 0; l < pl.H; ++l) {
+      double th = 2.0 * kPi * l / pl.n_theta;
+      double t1 = pl.N * pl.xi[j] * std::cos(th);
+      double t2 = pl.N * pl.xi[j] * std::sin(th);
+      double b1 = std::ceil(t1 - pl.w / 2.0), b2 = std::ceil(t2 - pl.w / 2.0);
+      NodeTap nt;
+      int ib1 = (int)b1, ib2 = (int)b2;
+      nt.b1 = ((ib1 % pl.N) + pl.N) % pl.N;
+      nt.b2 = ib2 + pl.hw;
+      nt.f1 = (float)(t1 - b1);
+      nt.f2 = (float)(t2 - b2);
+      if (nt.b2 < 0 || nt.b2 + pl.w > pl.M2) return FB_ERR_UNSUPPORTED;  // cannot happen for c <= 1/2
+      pl.nodes[(size_t)j * pl.H + l] = nt;
+    }
+
+  // FFTs: grid side N and the angular half length H
+  pl.tw.clear();
+  std::vector<int> rad;
+  if (!fft_radices(pl.N, rad) || !fft_radices(pl.H, rad)) return FB_ERR_UNSUPPORTED;
+  if ((int)rad.size() > kMaxRadices) return FB_ERR_UNSUPPORTED;
+  add_fft(pl.fft_grid, pl.N, pl.tw);
+  add_fft(pl.fft_ang, pl.H, pl.tw);
+  pl.angtw.resize(2 * (pl.H + 1));
+  for (int k = 0; k <= pl.H; ++k) {
+    double a = -2.0 * kPi * k / pl.n_theta;
+    pl.angtw[2 * k] = (float)std::cos(a);
+    pl.angtw[2 * k + 1] = (float)std::sin(a);
+  }
+
+  // Adjoint spreading as a gather over the folded half plane m2 = 0..N/2.
+  // A node with value Q and tap weight om at (m1, m2), m2 in [-hw, N/2 + hw], adds
+  //   om/2 * Q       to (m1, m2)              when 0 <= m2 <= N/2
+  //   om/2 * conj(Q) to (-m1, -m2) mod N      when m2 <= 0 or m2 >= N/2
+  // so that the half plane holds X(m) = (G(m) + conj G(-m)) / 2 of the full spread G.
+  {
+    const int N = pl.N, Nh = N / 2 + 1;
+    const size_t nrows = (size_t)N * Nh;
+    std::vector<int> cnt(nrows + 1, 0);
+    auto for_each_tap = [&](auto&& fn) {
+      for (size_t n = 0; n < pl.nodes.size(); ++n) {
+        int j = (int)(n / pl.H), l = (int)(n % pl.H);
+        double th = 2.0 * kPi * l / pl.n_theta;
+        double t1 = pl.N * pl.xi[j] * std::cos(th);
+        double t2 = pl.N * pl.xi[j] * std::sin(th);
+        int b1 = (int)std::ceil(t1 - pl.w / 2.0), b2 = (int)std::ceil(t2 - pl.w / 2.0);
+        for (int bb = 0; bb < pl.w; ++bb) {
+          int m2 = b2 + bb;
+          double w2 = es_kernel(2.0 * (t2 - m2) / pl.w, pl.beta);
+          for (int a = 0; a < pl.w; ++a) {
+            int m1 = b1 + a;
+            double om = 0.5 * w2 * es_kernel(2.0 * (t1 - m1) / pl.w, pl.beta);
+            int m1p = ((m1 % N) + N) % N;
+            if (m2 >= 0 && m2 <= N / 2) fn((size_t)m2 * N + m1p, (uint32_t)n, (float)om);
+            if (m2 <= 0 || m2 >= N / 2) {
+              int mm1 = ((-m1 % N) + N) % N, mm2 = ((-m2 % N) + N) % N;
+              fn((size_t)mm2 * N + mm1, (uint32_t)n | 0x80000000u, (float)om);
+            }
+          }
+        }
+      }
+    };
+    for_each_tap([&](size_t row, uint32_t, float) { cnt[row + 1]++; });
+    pl.csr_ptr.assign(nrows + 1, 0);
+    for (size_t r = 0; r < nrows; ++r) pl.csr_ptr[r + 1] = pl.csr_ptr[r] + cnt[r + 1];
+    pl.csr.resize(pl.csr_ptr[nrows]);
+    std::vector<int> fill(pl.csr_ptr.begin(), pl.csr_ptr.end() - 1);
+    for_each_tap([&](size_t row, uint32_t node, float om) { pl.csr[fill[row]++] = SpreadEntry{node, om}; });
+  }
+
+  // grouped-GEMM work items
+  pl.items_fwd.clear();
+  pl.items_adj.clear();
+  pl.items_cov.clear();
+  for (int k = 0; k <= pl.k_max; ++k) {
+    for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm) pl.items_fwd.push_back(GemmItem{k, m0, 0, 0});
+    for (int j0 = 0; j0 < pl.n_xi; j0 += pl.bm) pl.items_adj.push_back(GemmItem{k, j0, 0, 0});
+    for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm)
+      for (int n0 = m0; n0 < pl.p[k]; n0 += pl.bn) pl.items_cov.push_back(GemmItem{k, m0, n0, 0});
+  }
+  return FB_OK;
+}
+
+#define FB_HIP_TRY(expr)                \
+  do {                                  \
+    hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) {             \
+      pl.last_hip = e_;                 \
+      free_device(pl);                  \
+      return e_ == hipErrorOutOfMemory ? FB_ERR_ALLOC : FB_ERR_HIP; \
+    }                                   \
+  } while (0)
+
+template <class T>
+static hipError_t upload(T** dptr, const T* src, size_t count) {
+  hipError_t e = hipMalloc((void**)dptr, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (count) e = hipMemcpy(*dptr, src, count * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+int upload_plan(Plan& pl) {
+  FB_HIP_TRY(hipGetDevice(&pl.device));
+  size_t nb = (size_t)pl.p_half * pl.n_xi;
+  std::vector<float> r32(nb);
+  std::vector<uint16_t> rhi(nb), rlo(nb);
+  for (size_t i = 0; i < nb; ++i) {
+    double v = pl.radial[i];
+    r32[i] = (float)v;
+    uint16_t h = float_to_bf16_rne((float)v);
+    rhi[i] = h;
+    rlo[i] = float_to_bf16_rne((float)(v - (double)bf16_to_float(h)));
+  }
+  FB_HIP_TRY(upload(&pl.d_radial, r32.data(), nb));
+  FB_HIP_TRY(upload(&pl.d_radial_hi, rhi.data(), nb));
+  FB_HIP_TRY(upload(&pl.d_radial_lo, rlo.data(), nb));
+  std::vector<int> off32(pl.coef_off.begin(), pl.coef_off.end());
+  FB_HIP_TRY(upload(&pl.d_coef_off, off32.data(), off32.size()));
+  FB_HIP_TRY(upload(&pl.d_p, pl.p.data(), pl.p.size()));
+  std::vector<long long> coff(pl.cov_off.begin(), pl.cov_off.end());
+  FB_HIP_TRY(upload(&pl.d_cov_off, coff.data(), coff.size()));
+  std::vector<float> dc(pl.deconv.begin(), pl.deconv.end());
+  FB_HIP_TRY(upload(&pl.d_deconv, dc.data(), dc.size()));
+  FB_HIP_TRY(upload(&pl.d_nodes, pl.nodes.data(), pl.nodes.size()));
+  FB_HIP_TRY(upload(&pl.d_tw, (const float2*)pl.tw.data(), pl.tw.size() / 2));
+  FB_HIP_TRY(upload(&pl.d_angtw, (const float2*)pl.angtw.data(), pl.angtw.size() / 2));
+  FB_HIP_TRY(upload(&pl.d_csr_ptr, pl.csr_ptr.data(), pl.csr_ptr.size()));
+  FB_HIP_TRY(upload(&pl.d_csr, pl.csr.data(), pl.csr.size()));
+  FB_HIP_TRY(upload(&pl.d_items_fwd, pl.items_fwd.data(), pl.items_fwd.size()));
+  FB_HIP_TRY(upload(&pl.d_items_adj, pl.items_adj.data(), pl.items_adj.size()));
+  FB_HIP_TRY(upload(&pl.d_items_cov, pl.items_cov.data(), pl.items_cov.size()));
+  pl.has_device = true;
+  return FB_OK;
+}
+
+void free_device(Plan& pl) {
+  void* ptrs[] = {pl.d_radial, pl.d_radial_hi, pl.d_radial_lo, pl.d_coef_off, pl.d_p, pl.d_cov_off,
+                  pl.d_deconv, pl.d_nodes, pl.d_tw, pl.d_angtw, pl.d_csr_ptr, pl.d_csr,
+                  pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  pl.d_radial = nullptr;
+  pl.d_radial_hi = pl.d_radial_lo = nullptr;
+  pl.d_coef_off = pl.d_p = nullptr;
+  pl.d_cov_off = nullptr;
+  pl.d_deconv = nullptr;
+  pl.d_nodes = nullptr;
+  pl.d_tw = pl.d_angtw = nullptr;
+  pl.d_csr_ptr = nullptr;
+  pl.d_csr = nullptr;
+  pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = nullptr;
+  pl.has_device = false;
+}
+
+PassLayout pass_layout(const Plan& pl) {
+  PassLayout lay;
+  const size_t c8 = 8;  // complex64
+  size_t a1 = (size_t)pl.M2 * pl.L;                    // forward row pass output
+  size_t a2 = (size_t)pl.n_xi * pl.H;                  // polar samples / adjoint Q
+  size_t a3 = (size_t)(pl.N / 2 + 1) * pl.L;           // adjoint column pass output
+  size_t b1 = (size_t)pl.M2 * pl.N;                    // forward grid
+  size_t b2 = (size_t)(pl.k_max + 1) * pl.n_xi;        // angular spectrum / adjoint D
+  size_t b3 = (size_t)(pl.N / 2 + 1) * pl.N;           // adjoint folded grid
+  lay.bytes_a = std::max(a1, std::max(a2, a3)) * c8;
+  lay.bytes_b = std::max(b1, std::max(b2, b3)) * c8;
+  lay.per_image = lay.bytes_a + lay.bytes_b;
+  return lay;
+}
+
+}  // namespace fb

@@ -1,0 +1,118 @@
+// Internal plan of the library: FP64 host tables (Algorithm 1, steps 1-2) and
+// their device copies, plus launch descriptors for the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ffbspca.h"
+
+namespace fb {
+
+constexpr int kMaxRadices = 24;
+
+// One FFT length: its radix sequence and where its twiddles
+// exp(-2 pi i t / n), t = 0..n-1, start in the plan's twiddle table.
+struct FftDesc {
+  int n;
+  int nstage;
+  int tw_off;
+  int pad;
+  int radix[kMaxRadices];
+};
+
+// Interpolation footprint of one polar node (j, l), l < n_theta/2, on the
+// oversampled grid: grid coordinate t = grid_n * xi (first axis t1 = along i1,
+// second t2 = along i2); the w x w taps start at integer b = ceil(t - w/2) and
+// carry weights phi(2 (f - a) / w), a = 0..w-1, with f = t - b.
+struct NodeTap {
+  int b1;    // first tap column, reduced modulo grid_n into [0, grid_n)
+  int b2;    // first tap row index into the stored half-plane rows (m2 + hw >= 0)
+  float f1;  // t1 - ceil(t1 - w/2)
+  float f2;  // t2 - ceil(t2 - w/2)
+};
+
+// Adjoint spreading, written as a gather: entry of grid point (m1, m2) of the
+// folded half-plane m2 = 0..grid_n/2.  node index in bits 0..30, bit 31 set when
+// the node's conjugate contributes (Hermitian fold of the m2 < 0 / m2 > n/2 taps).
+struct SpreadEntry {
+  uint32_t node;
+  float weight;
+};
+
+struct GemmItem {  // one (k, tile) work item of a grouped GEMM
+  int k;
+  int t0;  // first row (or first row tile) of the tile
+  int t1;  // second tile coordinate (covariance only)
+  int pad;
+};
+
+struct Plan {
+  // problem
+  int L = 0;
+  double c = 0, R = 0;
+  int n_xi = 0, n_theta = 0, k_max = 0, p0 = 0;
+  int64_t p_half = 0, p_total = 0, cov_size = 0;
+  std::vector<int> p;               // p_k
+  std::vector<int64_t> coef_off;    // k_max + 2
+  std::vector<int64_t> cov_off;     // k_max + 2
+  std::vector<int> kq_k, kq_q;      // p_half
+  std::vector<double> roots, norms; // p_half
+  std::vector<double> xi, wq;       // n_xi
+  std::vector<double> radial;       // p_half x n_xi
+
+  // non-uniform FFT
+  int N = 0;        // oversampled grid side
+  int w = 0;        // kernel width
+  double beta = 0;  // kernel shape
+  int hw = 0;       // half-plane rows stored: m2 = -hw .. N/2 + hw
+  int M2 = 0;       // = N/2 + 2 hw + 1
+  int H = 0;        // n_theta / 2: half-ring nodes, also the complex FFT length of the angular step
+  std::vector<double> deconv;      // 1 / phi_hat(x / N), x over pixel indices
+  std::vector<NodeTap> nodes;      // n_xi * H
+  FftDesc fft_grid{}, fft_ang{};
+  std::vector<float> tw;           // interleaved (re, im) twiddles of both FFT lengths
+  std::vector<float> angtw;        // exp(-2 pi i k / n_theta), k = 0..H, interleaved
+  std::vector<int> csr_ptr;        // N * (N/2 + 1) + 1
+  std::vector<SpreadEntry> csr;    // spreading entries
+  std::vector<GemmItem> items_fwd, items_adj, items_cov;
+  int bm = 64, bn = 64;            // GEMM tile
+
+  // device
+  bool has_device = false;
+  int device = -1;
+  hipError_t last_hip = hipSuccess;
+  float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
+  uint16_t* d_radial_hi = nullptr;    // BF16 hi part
+  uint16_t* d_radial_lo = nullptr;    // BF16 lo part (radial - hi, rounded)
+  int* d_coef_off = nullptr;          // k_max + 2 (fits int32)
+  int* d_p = nullptr;                 // k_max + 1
+  long long* d_cov_off = nullptr;     // k_max + 2
+  float* d_deconv = nullptr;
+  NodeTap* d_nodes = nullptr;
+  float2* d_tw = nullptr;
+  float2* d_angtw = nullptr;
+  int* d_csr_ptr = nullptr;
+  SpreadEntry* d_csr = nullptr;
+  GemmItem* d_items_fwd = nullptr;
+  GemmItem* d_items_adj = nullptr;
+  GemmItem* d_items_cov = nullptr;
+};
+
+// Build host tables; returns FB_OK or an FB_ERR_* code.
+int build_host_plan(int L, double c, double R, Plan& pl);
+// Upload to the current device; returns FB_OK / FB_ERR_HIP / FB_ERR_ALLOC.
+int upload_plan(Plan& pl);
+void free_device(Plan& pl);
+
+// Per-image workspace layout of one expand/adjoint pass.
+struct PassLayout {
+  size_t bytes_a;   // buffer A: row-pass output, later polar samples
+  size_t bytes_b;   // buffer B: grid, later angular spectrum
+  size_t per_image;
+};
+PassLayout pass_layout(const Plan& pl);
+
+}  // namespace fb

@@ -1,0 +1,248 @@
+"""Python binding of the MI355X Fourier-Bessel steerable PCA library.
+
+Argument marshalling only: every step of the expansion, adjoint, covariance and
+eigendecomposition runs in the HIP kernels of libffbspca.so.  torch provides
+device memory and the current HIP stream.
+
+Layouts (Sec. II of the paper): images are float32 [n, L, L] with axis 0 = x;
+coefficients are float32 [n, p_half, 2] = (Re, Im) of a_{k,q}, k = 0..k_max,
+q = 1..p_k, k-major.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FB_BF16X3, FB_FP32, FBInfo, check, lib
+
+PRECISIONS = {"fp32": FB_FP32, "bf16x3": FB_BF16X3}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, shape, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+@dataclass
+class CovState:
+    """FP64 accumulators of fb_covariance: G (packed p_k x p_k blocks), S0 (k = 0 sums), count."""
+    G: torch.Tensor
+    S0: torch.Tensor
+    count: int = 0
+
+
+class Plan:
+    """A plan for L x L images with band limit c and support radius R (Algorithm 1, steps 1-2).
+
+    device=False builds the host tables only (sizes and index tables can be read
+    without a GPU; compute calls then raise)."""
+
+    def __init__(self, L: int, c: float, R: float, device: bool = True):
+        h = ctypes.c_void_p()
+        fn = lib().fb_plan if device else lib().fb_plan_host
+        check(fn(int(L), float(c), float(R), ctypes.byref(h)))
+        self._h = h
+        info = FBInfo()
+        check(lib().fb_plan_info(h, ctypes.byref(info)))
+        self.info = info
+        self.L, self.c, self.R = info.L, info.c, info.R
+        self.n_xi, self.n_theta, self.k_max, self.p0 = info.n_xi, info.n_theta, info.k_max, info.p0
+        self.p_half, self.p_total, self.cov_size = info.p_half, info.p_total, info.cov_size
+        self.grid_n, self.kernel_w = info.grid_n, info.kernel_w
+        K = self.k_max
+        self.k = np.zeros(self.p_half, np.int32)
+        self.q = np.zeros(self.p_half, np.int32)
+        self.p = np.zeros(K + 1, np.int32)
+        self.coef_off = np.zeros(K + 2, np.int64)
+        self.cov_off = np.zeros(K + 2, np.int64)
+        check(lib().fb_plan_tables(h, self.k.ctypes.data, self.q.ctypes.data, self.p.ctypes.data,
+                                   self.coef_off.ctypes.data, self.cov_off.ctypes.data))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device else None
+        self._ws = None
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fb_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host tables -----------------------------------------------------------
+    def host_tables(self):
+        """FP64 roots R_{k,q}, norms N_{k,q}, Gauss-Legendre xi and w, and the radial table [p_half, n_xi]."""
+        roots = np.zeros(self.p_half)
+        norms = np.zeros(self.p_half)
+        xi = np.zeros(self.n_xi)
+        w = np.zeros(self.n_xi)
+        radial = np.zeros((self.p_half, self.n_xi))
+        check(lib().fb_plan_host_tables(self._h, roots.ctypes.data, norms.ctypes.data, xi.ctypes.data,
+                                        w.ctypes.data, radial.ctypes.data))
+        return roots, norms, xi, w, radial
+
+    # -- workspace -----------------------------------------------------------
+    def workspace_bytes(self, batch: int) -> int:
+        return int(lib().fb_workspace_bytes(self._h, int(batch), 0))
+
+    def workspace(self, batch: int) -> torch.Tensor:
+        need = self.workspace_bytes(batch)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _ws_for(self, n: int, batch: int | None):
+        b = max(1, min(int(n), int(batch) if batch else 2048))
+        ws = self.workspace(b)
+        return ws, self.workspace_bytes(b)
+
+    # -- compute -----------------------------------------------------------
+    def expand(self, images: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
+               batch: int | None = None) -> torch.Tensor:
+        """a = T* I (Algorithm 1, steps 3-4).  images float32 [n, L, L] -> float32 [n, p_half, 2]."""
+        n = images.shape[0]
+        _need(images, torch.float32, (n, self.L, self.L), "images")
+        if out is None:
+            out = torch.empty((n, self.p_half, 2), dtype=torch.float32, device=images.device)
+        _need(out, torch.float32, (n, self.p_half, 2), "out")
+        ws, wsb = self._ws_for(n, batch)
+        check(lib().fb_expand(self._h, images.data_ptr(), n, out.data_ptr(), _prec(precision), ws.data_ptr(), wsb,
+                              _stream_ptr(images.device)), self._h)
+        return out
+
+    def adjoint(self, coeffs: torch.Tensor, weight_mode: int = 0, out: torch.Tensor | None = None,
+                batch: int | None = None) -> torch.Tensor:
+        """I = T b: synthesis, the transpose of expand (weight_mode 0: +-k folded; 1: plain transpose)."""
+        n = coeffs.shape[0]
+        _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
+        if out is None:
+            out = torch.empty((n, self.L, self.L), dtype=torch.float32, device=coeffs.device)
+        _need(out, torch.float32, (n, self.L, self.L), "out")
+        ws, wsb = self._ws_for(n, batch)
+        check(lib().fb_adjoint(self._h, coeffs.data_ptr(), n, out.data_ptr(), int(weight_mode), ws.data_ptr(), wsb,
+                               _stream_ptr(coeffs.device)), self._h)
+        return out
+
+    def new_covariance(self) -> CovState:
+        return CovState(G=torch.zeros(self.cov_size, dtype=torch.float64, device=self.device),
+                        S0=torch.zeros(self.p0, dtype=torch.float64, device=self.device), count=0)
+
+    def covariance(self, coeffs: torch.Tensor, state: CovState | None = None, precision="fp32") -> CovState:
+        """Accumulate G^(k) += Re(A A^*) and the k = 0 sums (Eqs.(ck),(ck_0))."""
+        n = coeffs.shape[0]
+        _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
+        if state is None:
+            state = self.new_covariance()
+        cnt = ctypes.c_int64(state.count)
+        check(lib().fb_covariance(self._h, coeffs.data_ptr(), n, state.G.data_ptr(), state.S0.data_ptr(),
+                                  ctypes.byref(cnt), _prec(precision), _stream_ptr(coeffs.device)), self._h)
+        state.count = int(cnt.value)
+        return state
+
+    def eig(self, state: CovState):
+        """Finalise C^(k) and diagonalise (Algorithm 2, steps 1 and 4).
+
+        Returns (evals [p_half], evecs [cov_size], C [cov_size], mean [p0]), FP64 device tensors."""
+        dev = state.G.device
+        evals = torch.empty(self.p_half, dtype=torch.float64, device=dev)
+        evecs = torch.empty(self.cov_size, dtype=torch.float64, device=dev)
+        C = torch.empty(self.cov_size, dtype=torch.float64, device=dev)
+        mean = torch.empty(self.p0, dtype=torch.float64, device=dev)
+        wsb = int(lib().fb_eig_workspace_bytes(self._h))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        check(lib().fb_eig(self._h, state.G.data_ptr(), state.S0.data_ptr(), state.count, evals.data_ptr(),
+                           evecs.data_ptr(), C.data_ptr(), mean.data_ptr(), ws.data_ptr(), wsb,
+                           _stream_ptr(dev)), self._h)
+        return evals, evecs, C, mean
+
+    # -- helpers -----------------------------------------------------------
+    def blocks(self, packed: torch.Tensor | np.ndarray):
+        """Split a packed [cov_size] array into its p_k x p_k blocks."""
+        return [packed[self.cov_off[k]:self.cov_off[k + 1]].reshape(self.p[k], self.p[k])
+                for k in range(self.k_max + 1)]
+
+    def to_complex(self, coeffs: torch.Tensor) -> torch.Tensor:
+        return torch.view_as_complex(coeffs)
+
+
+def synth_normals(seed: int, rng_stream: int, first: int, n: int, n_per: int, scale: float = 1.0,
+                  device=None) -> torch.Tensor:
+    """Philox-4x32-10 + Box-Muller normals on the device, float32 [n, n_per] (seeded inputs)."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((n, n_per), dtype=torch.float32, device=device)
+    check(lib().fb_synth_normals(int(seed), int(rng_stream), int(first), int(n), int(n_per), float(scale),
+                                 out.data_ptr(), _stream_ptr(device)))
+    return out
+
+
+def synth_words(seed: int, rng_stream: int, first: int, n: int, n_per: int, device=None) -> torch.Tensor:
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((n, n_per), dtype=torch.int32, device=device)
+    check(lib().fb_synth_words(int(seed), int(rng_stream), int(first), int(n), int(n_per), out.data_ptr(),
+                               _stream_ptr(device)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# autograd
+# ----------------------------------------------------------------------------
+class FBExpand(torch.autograd.Function):
+    """a = T* I with gradient T g (plain transpose, weight 1 for every k; k = 0 imaginary parts ignored)."""
+
+    @staticmethod
+    def forward(ctx, images, plan: Plan, precision="fp32"):
+        ctx.plan = plan
+        return plan.expand(images.contiguous(), precision=precision)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.adjoint(g.contiguous(), weight_mode=1), None, None
+
+
+class FBSynth(torch.autograd.Function):
+    """I = T b (+-k folded) with gradient w * (T* g), w = 1 for k = 0 and 2 for k > 0."""
+
+    @staticmethod
+    def forward(ctx, coeffs, plan: Plan):
+        ctx.plan = plan
+        return plan.adjoint(coeffs.contiguous(), weight_mode=0)
+
+    @staticmethod
+    def backward(ctx, g):
+        plan = ctx.plan
+        a = plan.expand(g.contiguous(), precision="fp32")
+        w = torch.full((plan.p_half, 1), 2.0, dtype=a.dtype, device=a.device)
+        w[:plan.p0] = 1.0
+        return a * w, None
+
+
+def fb_expand(images, plan: Plan, precision="fp32"):
+    return FBExpand.apply(images, plan, precision)
+
+
+def fb_synth(coeffs, plan: Plan):
+    return FBSynth.apply(coeffs, plan)

@@ -1,0 +1,33 @@
+"""Shared helpers of the GPU tests: seeded inputs built on the host (never by the
+HIP path) and error measures."""
+
+import numpy as np
+
+import oracle
+from paper_1412_0781_amd import synth
+
+
+def structured_images(pl_or, n, seed=0, snr=0.1, first=0):
+    """Images with the workload's structure: the oracle's synthesis T a of random
+    coefficients with variance (1+q)^-2 (1+|k|)^-1, plus white noise at the given SNR.
+    Rounded to float32 so that both sides see identical inputs."""
+    idx = np.arange(first, first + n)
+    k, q = pl_or.kq[:, 0], pl_or.kq[:, 1]
+    a = synth.random_coefficients(seed, idx, k, q)
+    clean = oracle.adjoint(a, pl_or)
+    sigma = np.sqrt(synth.noise_sigma2(k, q, pl_or.L, snr))
+    img = clean + synth.noise_images(seed, idx, pl_or.L, sigma)
+    return img.astype(np.float32)
+
+
+def noise_images(L, n, seed=0, first=0):
+    return synth.noise_images(seed, np.arange(first, first + n), L, 1.0).astype(np.float32)
+
+
+def rel_l2(x, ref):
+    return float(np.linalg.norm(np.asarray(x) - np.asarray(ref)) / np.linalg.norm(np.asarray(ref)))
+
+
+def as_complex(coeffs_t):
+    c = coeffs_t.detach().cpu().numpy().astype(np.float64)
+    return c[..., 0] + 1j * c[..., 1]

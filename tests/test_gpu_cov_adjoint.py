@@ -1,0 +1,174 @@
+"""GPU parity of the covariance and eigendecomposition (Algorithm 2, steps 1, 3,
+4) and of the adjoint T, through the C ABI, against the FP64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import as_complex, noise_images, rel_l2, structured_images
+from paper_1412_0781_amd import FBExpand, FBSynth, Plan, synth, synth_normals, synth_words
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    torch.cuda.set_device(0)
+    yield
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_covariance_and_eig_workload_L32(precision):
+    """n = 1000, L = 32, R = 16, SNR 1/10 (the FP64 reference workload): C^(k) and lambda
+    within 1e-5 relative of the oracle computed from the oracle's own coefficients."""
+    L, c, R, n = 32, 0.5, 16, 1000
+    print(f"[cov] L={L} n={n} {precision}", flush=True)
+    po = oracle.plan(L, c, R)
+    img = structured_images(po, n, seed=0, snr=0.1)
+    a_ref = oracle.expand(img.astype(np.float64), po)
+    mean_ref, C_ref = oracle.mean_and_covariance(a_ref, po)
+    lam_ref, U_ref = oracle.eig_blocks(C_ref)
+
+    plan = Plan(L, c, R)
+    x = torch.tensor(img, device="cuda")
+    st = plan.new_covariance()
+    for s in range(0, n, 300):  # accumulate over several calls
+        a = plan.expand(x[s:s + 300], precision=precision)
+        plan.covariance(a, st, precision=precision)
+    evals, evecs, C, mean = plan.eig(st)
+    torch.cuda.synchronize()
+    assert st.count == n
+    C = C.cpu().numpy()
+    Cb = plan.blocks(C)
+    worst = max(np.linalg.norm(Cb[k] - C_ref[k]) / np.linalg.norm(C_ref[k]) for k in range(po.k_max + 1))
+    print(f"  worst per-k C rel {worst:.3e}", flush=True)
+    assert worst <= TOL
+    assert rel_l2(mean.cpu().numpy(), mean_ref) <= TOL
+    lam = evals.cpu().numpy()
+    for k in range(po.k_max + 1):
+        o = po.coef_off[k]
+        assert np.max(np.abs(lam[o:o + po.p[k]] - lam_ref[k])) <= TOL * np.max(np.abs(lam_ref[k]))
+    # eigenvectors where the eigenvalue gap is large enough to make them unique
+    V = plan.blocks(evecs.cpu().numpy())
+    for k in range(po.k_max + 1):
+        lr = lam_ref[k]
+        for l in range(po.p[k]):
+            gap = min([abs(lr[l] - lr[m]) for m in range(po.p[k]) if m != l] or [np.inf])
+            if gap > 1e-2 * abs(lr[0]):
+                assert np.max(np.abs(V[k][:, l] - U_ref[k][:, l])) <= 1e-3, (k, l)
+
+
+def test_eig_is_an_eigendecomposition_of_C():
+    plan = Plan(64, 0.5, 32)
+    x = torch.tensor(noise_images(64, 500, seed=2), device="cuda")
+    st = plan.covariance(plan.expand(x))
+    evals, evecs, C, _ = plan.eig(st)
+    torch.cuda.synchronize()
+    Cb = plan.blocks(C.cpu().numpy())
+    Vb = plan.blocks(evecs.cpu().numpy())
+    lam = evals.cpu().numpy()
+    for k in range(plan.k_max + 1):
+        o = plan.coef_off[k]
+        lk = lam[o:o + plan.p[k]]
+        assert np.all(np.diff(lk) <= 0)
+        V = Vb[k]
+        assert np.allclose(V.T @ V, np.eye(plan.p[k]), atol=1e-12)
+        assert np.allclose(Cb[k] @ V, V * lk[None, :], atol=1e-12 * max(1.0, abs(lk).max()))
+
+
+def test_covariance_deterministic_and_additive():
+    plan = Plan(32, 0.5, 16)
+    x = torch.tensor(noise_images(32, 700, seed=9), device="cuda")
+    a = plan.expand(x)
+    s1 = plan.covariance(a)
+    s2 = plan.covariance(a)
+    s3 = plan.covariance(a[:350])
+    plan.covariance(a[350:], s3)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.G, s2.G) and torch.equal(s1.S0, s2.S0)
+    # splitting the images over two calls only moves FP32 partial-sum boundaries
+    assert float((s1.G - s3.G).norm() / s1.G.norm()) <= 1e-6
+    assert float((s1.S0 - s3.S0).norm() / s1.S0.norm()) <= 1e-6
+
+
+@pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (31, 0.5, 15.5), (64, 0.3, 32)])
+def test_adjoint_matches_oracle(L, c, R):
+    print(f"[adjoint] L={L} c={c} R={R}", flush=True)
+    po = oracle.plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(4, np.arange(6), k, q)
+    ref = oracle.adjoint(b, po)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    got = plan.adjoint(bt).cpu().numpy()
+    assert rel_l2(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (128, 0.5, 64), (31, 0.5, 15.5)])
+def test_dot_product_identity_gpu(L, c, R):
+    """<T* I, b> = <I, T b> with the folded inner product, to 1e-6 in FP32, relative to
+    ||T* I|| ||b|| (the Cauchy-Schwarz scale of both sides; |<T* I, b>| itself can cancel
+    towards 0 for random inputs)."""
+    plan = Plan(L, c, R)
+    po = oracle.plan(L, c, R)
+    rng = np.random.default_rng(1)
+    I = torch.tensor(rng.standard_normal((4, L, L)).astype(np.float32), device="cuda")
+    b = rng.standard_normal((4, plan.p_half, 2)).astype(np.float32)
+    b[:, :plan.p0, 1] = 0
+    bt = torch.tensor(b, device="cuda")
+    a = as_complex(plan.expand(I))
+    Tb = plan.adjoint(bt).cpu().numpy().astype(np.float64)
+    bc = b[..., 0] + 1j * b[..., 1]
+    lhs = oracle.coeff_inner(a, bc, po)
+    rhs = np.sum(I.cpu().numpy().astype(np.float64) * Tb, axis=(1, 2))
+    scale = np.sqrt(oracle.coeff_inner(a, a, po) * oracle.coeff_inner(bc, bc, po))
+    print(f"  dot test {np.max(np.abs(lhs - rhs) / scale):.3e}", flush=True)
+    assert np.max(np.abs(lhs - rhs) / scale) <= 1e-6
+
+
+def test_autograd_expand_gradient():
+    """FBExpand backward is the plain transpose: dot test and central differences."""
+    L = 32
+    plan = Plan(L, 0.5, 16)
+    rng = np.random.default_rng(2)
+    I = torch.tensor(rng.standard_normal((3, L, L)).astype(np.float32), device="cuda", requires_grad=True)
+    g = torch.tensor(rng.standard_normal((3, plan.p_half, 2)).astype(np.float32), device="cuda")
+    a = FBExpand.apply(I, plan, "fp32")
+    (a * g).sum().backward()
+    lhs = float((a.detach().double() * g.double()).sum())
+    rhs = float((I.detach().double() * I.grad.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(a.detach().double().norm() * g.double().norm())
+    # central difference along a random direction (the map is linear)
+    d = torch.tensor(rng.standard_normal((3, L, L)).astype(np.float32), device="cuda")
+    h = 1e-3
+    fp = float((FBExpand.apply(I.detach() + h * d, plan, "fp32").double() * g.double()).sum())
+    fm = float((FBExpand.apply(I.detach() - h * d, plan, "fp32").double() * g.double()).sum())
+    fd = (fp - fm) / (2 * h)
+    an = float((I.grad.double() * d.double()).sum())
+    assert abs(fd - an) <= 1e-4 * max(1.0, abs(an))
+
+
+def test_autograd_synth_gradient():
+    L = 32
+    plan = Plan(L, 0.5, 16)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((2, plan.p_half, 2)).astype(np.float32)
+    b[:, :plan.p0, 1] = 0
+    bt = torch.tensor(b, device="cuda", requires_grad=True)
+    out = FBSynth.apply(bt, plan)
+    G = torch.tensor(rng.standard_normal((2, L, L)).astype(np.float32), device="cuda")
+    (out * G).sum().backward()
+    lhs = float((out.detach().double() * G.double()).sum())
+    rhs = float((bt.detach().double() * bt.grad.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(out.detach().double().norm() * G.double().norm())
+
+
+def test_device_philox_matches_host():
+    w = synth_words(123, 2, 7, 3, 10).cpu().numpy().view(np.uint32)
+    ref = synth._words(123, 2, np.arange(7, 10), 10)
+    assert np.array_equal(w, ref)
+    z = synth_normals(5, 2, 11, 4, 1001).cpu().numpy()
+    zr = synth.normals(5, 2, np.arange(11, 15), 1001)
+    assert np.max(np.abs(z - zr)) <= 1e-6 * np.max(np.abs(zr))
