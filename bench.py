@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Throughput of the Fourier-Bessel expansion + steerable covariance on one MI355X.
+
+Workload (the headline configuration): n = 100 000 synthetic cryo-EM-shaped
+images, L = 256, support radius R = 128, band limit c = 1/2.  Each image is the
+synthesis T a of random Fourier-Bessel coefficients with variance
+(1+q)^-2 (1+|k|)^-1 plus white Gaussian noise at SNR 1/20, generated on the
+device from seed 0 (Philox-4x32-10) before timing starts; inputs are resident
+in HBM when the timed region starts.
+
+One step = the whole hot path over all n images: fb_expand (polar NUFFT,
+angular FFT, radial quadrature) then fb_covariance (G^(k) += Re(A A^*), k = 0
+sums).  Both arithmetic forms are timed, FP32 and split-BF16x3; `value` is the
+BF16x3 form.  The plan (tables) and the eigendecomposition are outside the
+timed region (the eigendecomposition is timed on its own and reported).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "images/s (FB coeffs + covariance) at L=256, BF16x3 vs FP32, ≤1e-5 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_image(plan) -> dict:
+    """Minimum HBM bytes each kernel must move per image (read its input once, write its output once)."""
+    L, N, M2 = plan.L, plan.grid_n, plan.grid_n // 2 + 2 * (plan.kernel_w // 2 + 1) + 1
+    H = plan.n_theta // 2
+    c8 = 8
+    img = 4 * L * L
+    g1 = c8 * M2 * L
+    g = c8 * M2 * N
+    P = c8 * plan.n_xi * H
+    fh = c8 * (plan.k_max + 1) * plan.n_xi
+    co = c8 * plan.p_half
+    return {
+        "fwd_rows": img + g1,
+        "fwd_cols": g1 + g,
+        "fwd_gather": g + P,
+        "fwd_angular": P + fh,
+        "radial_fwd": fh + co,
+        "covariance": co,
+    }
+
+
+def make_images(plan, n, seed, snr, chunk=4096):
+    import numpy as np
+    import torch
+
+    from paper_1412_0781_amd import synth
+    from paper_1412_0781_amd.fb import synth_normals
+
+    dev = plan.device
+    k = plan.k.astype(np.float64)
+    q = plan.q.astype(np.float64)
+    v = synth.coef_variance(k, q)
+    sc = np.zeros((plan.p_half, 2), np.float32)
+    sc[:, 0] = np.where(k == 0, np.sqrt(v), np.sqrt(v / 2))
+    sc[:, 1] = np.where(k == 0, 0.0, np.sqrt(v / 2))
+    scale = torch.tensor(sc, device=dev)
+    sigma = math.sqrt(synth.noise_sigma2(k, q, plan.L, snr))
+    images = torch.empty((n, plan.L, plan.L), dtype=torch.float32, device=dev)
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        a = synth_normals(seed, synth.STREAM_COEF, s, m, 2 * plan.p_half, 1.0, dev).view(m, plan.p_half, 2)
+        a.mul_(scale)
+        plan.adjoint(a, out=images[s:s + m], batch=min(m, 2048))
+        images[s:s + m].add_(synth_normals(seed, synth.STREAM_NOISE, s, m, plan.L * plan.L, sigma, dev)
+                             .view(m, plan.L, plan.L))
+    torch.cuda.synchronize()
+    return images, sigma
+
+
+def time_form(plan, images, coeffs, precision, steps, warmup, pass_images):
+    import torch
+
+    st = plan.new_covariance()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st.G.zero_()
+        st.S0.zero_()
+        st.count = 0
+        plan.expand(images, precision=precision, out=coeffs, batch=pass_images)
+        plan.covariance(coeffs, st, precision=precision)
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"{precision}: warmup step {i + 1}/{warmup} done")
+    plan.profile_read(reset=True)
+    plan.profile(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.profile(False)
+    prof = plan.profile_read(reset=True)
+    ev_ms = e0.elapsed_time(e1)
+    log(f"{precision}: {steps} steps in {wall:.3f} s (events {ev_ms / 1e3:.3f} s)")
+    return wall, ev_ms, prof, st
+
+
+def cpu_baseline(plan_args, sample, seed, snr):
+    """The FP64 oracle, timed on the host on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_1412_0781_amd import synth
+
+    L, c, R = plan_args
+    po = oracle.plan(L, c, R)
+    idx = np.arange(sample)
+    kk, qq = po.kq[:, 0], po.kq[:, 1]
+    a = synth.random_coefficients(seed, idx, kk, qq)
+    sigma = math.sqrt(synth.noise_sigma2(kk, qq, L, snr))
+    img = np.empty((sample, L, L), np.float32)
+    noise = synth.noise_images(seed, idx, L, sigma)
+    for i in range(sample):
+        img[i] = (oracle.adjoint(a[i:i + 1], po)[0] + noise[i]).astype(np.float32)
+        log(f"cpu baseline: synthesised sample image {i + 1}/{sample} on the host (not timed)")
+    _ = po.B  # radial table: part of the plan, outside the timed region
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    log(f"cpu baseline: timing the oracle on {sample} images with {cores} BLAS threads")
+    t0 = time.perf_counter()
+    coef = np.empty((sample, po.p_half), np.complex128)
+    for i in range(sample):
+        coef[i] = oracle.expand(img[i:i + 1].astype(np.float64), po)[0]
+        log(f"cpu baseline: oracle expansion of image {i + 1}/{sample} done")
+    oracle.mean_and_covariance(coef, po)
+    dt = time.perf_counter() - t0
+    return img, coef, po, {"value": sample / dt, "unit": "images/s", "cores": int(cores), "kind": "oracle",
+                           "sample": f"{sample} images of the same workload (L={L}, R={R}, c={c}), "
+                                     f"expansion + covariance in FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--snr", type=float, default=1 / 20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--pass-images", type=int, default=2048)
+    ap.add_argument("--forms", default="fp32,bf16x3")
+    ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1412_0781_amd import Plan
+
+    torch.cuda.set_device(0)
+    L = args.L
+    c, R = 0.5, L / 2
+    log(f"plan L={L} R={R} c={c}")
+    t0 = time.perf_counter()
+    plan = Plan(L, c, R)
+    plan_s = time.perf_counter() - t0
+    log(f"plan built in {plan_s:.2f} s: n_xi={plan.n_xi} n_theta={plan.n_theta} k_max={plan.k_max} "
+        f"p_half={plan.p_half}")
+    log(f"generating {args.n} images on the device")
+    t0 = time.perf_counter()
+    images, sigma = make_images(plan, args.n, args.seed, args.snr)
+    log(f"images ready in {time.perf_counter() - t0:.1f} s (noise sigma {sigma:.4g})")
+    coeffs = torch.empty((args.n, plan.p_half, 2), dtype=torch.float32, device=plan.device)
+    plan.workspace(args.pass_images)
+
+    forms = {}
+    profs = {}
+    for prec in [f.strip() for f in args.forms.split(",") if f.strip()]:
+        wall, ev_ms, prof, st = time_form(plan, images, coeffs, prec, args.steps, args.warmup, args.pass_images)
+        forms[prec] = {"images_per_s": args.n * args.steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+                       "event_ms_per_step": ev_ms / args.steps}
+        profs[prec] = prof
+    head = "bf16x3" if "bf16x3" in forms else next(iter(forms))
+
+    # eigendecomposition of the accumulated covariance (outside images/s)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    plan.eig(st)
+    torch.cuda.synchronize()
+    eig_ms = 1e3 * (time.perf_counter() - te)
+
+    # per-kernel figures of the headline form; dominant kernel against the HBM roofline
+    prof = profs[head]
+    bpi = algorithmic_bytes_per_image(plan)
+    stages = {}
+    for name, (ms, cnt) in prof.items():
+        stages[name] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / max(cnt, 1)}
+    dom = max((s for s in stages if s in bpi), key=lambda s: stages[s]["total_ms"])
+    per_launch_images = args.n * args.steps / stages[dom]["launches"]
+    alg_bytes = bpi[dom] * per_launch_images
+    achieved = alg_bytes / (stages[dom]["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(alg_bytes), "avg_launch_ms": round(stages[dom]["avg_ms"], 4)}
+
+    # accuracy on a host-generated sample, and the CPU oracle baseline
+    accuracy = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        img_s, coef_ref, po, cpu = cpu_baseline((L, c, R), args.cpu_sample, args.seed, args.snr)
+        xs = torch.tensor(img_s, device=plan.device)
+        accuracy = {}
+        for prec in forms:
+            got = plan.expand(xs, precision=prec).cpu().numpy().astype(np.float64)
+            gc = got[..., 0] + 1j * got[..., 1]
+            accuracy[prec] = float(np.linalg.norm(gc - coef_ref) / np.linalg.norm(coef_ref))
+        log(f"coefficient rel-L2 vs FP64 oracle on the sample: {accuracy}")
+
+    f = forms[head]
+    out = {
+        "metric": METRIC,
+        "value": round(f["images_per_s"], 1),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{head} matrix-core contractions, f32 NUFFT",
+        "data": "synthetic",
+        "config": {"workload": f"FB expansion + covariance, n={args.n} images L={L} R={R:g} c={c} "
+                               f"SNR=1/{round(1 / args.snr)} (synthetic, device-generated, seed {args.seed})",
+                   "n": args.n, "L": L, "R": R, "c": c, "precision": head, "pass_images": args.pass_images},
+        "forms": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in forms.items()},
+        "bf16x3_over_fp32": round(forms["bf16x3"]["images_per_s"] / forms["fp32"]["images_per_s"], 3)
+        if "bf16x3" in forms and "fp32" in forms else None,
+        "accuracy_rel_l2": accuracy,
+        "stages": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                   for k, v in stages.items()},
+        "eig_ms": round(eig_ms, 2),
+        "plan_s": round(plan_s, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

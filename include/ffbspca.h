@@ -170,6 +170,20 @@ int fb_synth_normals(uint64_t seed, uint32_t rng_stream, int64_t first_index, in
 int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per,
                    uint32_t* out, void* stream);
 
+/* Per-kernel timing (instrumentation, not part of the method).  While enabled,
+ * the library records a pair of HIP events on the caller's stream around every
+ * kernel it launches for this plan.  fb_profile_read waits for the recorded
+ * events, adds their elapsed times to per-stage totals and returns, for stage
+ * s < min(max_stages, FB_NUM_STAGES): total_ms[s] (milliseconds summed over
+ * launches) and launches[s]; reset = 1 clears the totals afterwards.  Returns
+ * the number of stages (FB_NUM_STAGES) or a negative FB_ERR_* code.  Stage
+ * names come from fb_stage_name.  Not for concurrent use of one plan from
+ * several streams while enabled. */
+#define FB_NUM_STAGES 12
+int fb_profile_enable(fb_plan_t plan, int enable);
+int fb_profile_read(fb_plan_t plan, double* total_ms, int64_t* launches, int max_stages, int reset);
+const char* fb_stage_name(int stage);
+
 /* Human-readable text for a return code. */
 const char* fb_error_string(int code);
 

@@ -314,8 +314,9 @@ def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096) -> np.ndarray:
     xi2 = xi2.ravel()
     out = np.zeros((n, pl.L, pl.L), dtype=np.float64)
     for s in range(0, xi1.size, node_block):
-        e1 = np.exp(+1j * TWO_PI * np.outer(xi1[s:s + node_block], x))  # [nb, L]
-        e2 = np.exp(+1j * TWO_PI * np.outer(xi2[s:s + node_block], x))
-        Pb = P[:, s:s + node_block]                                      # [n, nb]
-        out += np.einsum("bi,nb,bj->nij", e1, Pb, e2, optimize=True).real
+        e1 = np.exp(+1j * TWO_PI * np.outer(xi1[s:s + node_block], x))  # [nb, L] over i1
+        e2 = np.exp(+1j * TWO_PI * np.outer(xi2[s:s + node_block], x))  # [nb, L] over i2
+        for i in range(n):
+            # sum over the nodes b of e1[b, i1] P[b] e2[b, i2], as one matrix product
+            out[i] += ((e1 * P[i, s:s + node_block, None]).T @ e2).real
     return out

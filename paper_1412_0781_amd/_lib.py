@@ -51,6 +51,9 @@ SIGNATURES = [
     ("fb_eig_workspace_bytes", c_size_t, [c_void_p]),
     ("fb_synth_normals", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_float, c_void_p, c_void_p]),
     ("fb_synth_words", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_void_p, c_void_p]),
+    ("fb_profile_enable", c_int, [c_void_p, c_int]),
+    ("fb_profile_read", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    ("fb_stage_name", ctypes.c_char_p, [c_int]),
     ("fb_error_string", ctypes.c_char_p, [c_int]),
     ("fb_plan_last_hip_error", c_int, [c_void_p]),
 ]

@@ -205,6 +205,32 @@ int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int6
              : FB_ERR_HIP;
 }
 
+int fb_profile_enable(fb_plan_t plan, int enable) {
+  if (!plan) return FB_ERR_INVALID_ARG;
+  if (!plan->pl.has_device) return FB_ERR_NO_DEVICE;
+  plan->pl.prof.on = enable != 0;
+  return FB_OK;
+}
+
+int fb_profile_read(fb_plan_t plan, double* total_ms, int64_t* launches, int max_stages, int reset) {
+  if (!plan || max_stages < 0) return FB_ERR_INVALID_ARG;
+  fb::Profiler& pr = plan->pl.prof;
+  int rc = pr.collect();
+  if (rc != FB_OK) return rc;
+  for (int s = 0; s < std::min(max_stages, (int)fb::ST_COUNT); ++s) {
+    if (total_ms) total_ms[s] = pr.total_ms[s];
+    if (launches) launches[s] = pr.launches[s];
+  }
+  if (reset)
+    for (int s = 0; s < fb::ST_COUNT; ++s) {
+      pr.total_ms[s] = 0.0;
+      pr.launches[s] = 0;
+    }
+  return fb::ST_COUNT;
+}
+
+const char* fb_stage_name(int stage) { return fb::stage_name(stage); }
+
 const char* fb_error_string(int code) {
   switch (code) {
     case FB_OK: return "success";

@@ -153,8 +153,10 @@ size_t eig_workspace_bytes(const Plan& pl) { return (size_t)pl.cov_size * sizeof
 
 hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
                       double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st) {
+  pl.prof.begin(ST_EIG, st);
   hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, count, evals, evecs,
                      C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 

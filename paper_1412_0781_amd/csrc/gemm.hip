@@ -293,6 +293,7 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
                                  hipStream_t st) {
   const int ncol = 2 * nimg;
   dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_fwd.size());
+  pl.prof.begin(ST_RADIAL_FWD, st);
   if (precision == FB_BF16X3)
     hipLaunchKernelGGL(k_radial_fwd_bf16x3, g, dim3(256), 0, st, pl.d_radial_hi, pl.d_radial_lo,
                        (const float*)Fh, coeffs, pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, ncol,
@@ -300,6 +301,7 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
   else
     hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs,
                        pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 
@@ -307,20 +309,24 @@ hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D,
                                  hipStream_t st) {
   const int ncol = 2 * nimg;
   dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_adj.size());
+  pl.prof.begin(ST_RADIAL_ADJ, st);
   hipLaunchKernelGGL(k_radial_adj_f32, g, dim3(256), 0, st, pl.d_radial, coeffs, (float*)D, pl.d_items_adj,
                      pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half, weight_mode);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
                              hipStream_t st) {
   dim3 g((unsigned)pl.items_cov.size());
+  pl.prof.begin(ST_COVARIANCE, st);
   if (precision == FB_BF16X3)
     hipLaunchKernelGGL(k_covariance<1>, g, dim3(256), 0, st, coeffs, G, S0, pl.d_items_cov, pl.d_coef_off,
                        pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
   else
     hipLaunchKernelGGL(k_covariance<0>, g, dim3(256), 0, st, coeffs, G, S0, pl.d_items_cov, pl.d_coef_off,
                        pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 

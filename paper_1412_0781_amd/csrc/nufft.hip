@@ -372,17 +372,23 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   const int N = pl.N, L = pl.L;
   int RP = rows_per_block(N);
   dim3 g1((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  pl.prof.begin(ST_FWD_ROWS, st);
   hipLaunchKernelGGL(k_fwd_rows, g1, dim3(256), 2 * RP * N * sizeof(float2), st, images, bufA, pl.d_deconv,
                      pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, RP);
+  pl.prof.end(st);
   int CP = rows_per_block(N);
   dim3 g2((unsigned)((pl.M2 + CP - 1) / CP), (unsigned)nimg);
+  pl.prof.begin(ST_FWD_COLS, st);
   hipLaunchKernelGGL(k_fwd_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufA, bufB, pl.fft_grid,
                      pl.d_tw, L, pl.M2, CP);
+  pl.prof.end(st);
   const int nnodes = pl.n_xi * pl.H;
   const int IG = 4;
   dim3 g3((unsigned)((nnodes + 255) / 256), (unsigned)((nimg + IG - 1) / IG));
+  pl.prof.begin(ST_FWD_GATHER, st);
   hipLaunchKernelGGL(k_fwd_gather<7>, g3, dim3(256), 0, st, bufB, bufA, pl.d_nodes, nnodes, N, pl.M2,
                      (float)pl.beta, nimg, IG);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 
@@ -390,8 +396,10 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
   int AG = rows_per_block(pl.H);
   dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+  pl.prof.begin(ST_FWD_ANGULAR, st);
   hipLaunchKernelGGL(k_fwd_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, P, Fh, pl.fft_ang,
                      pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 
@@ -399,8 +407,10 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
   int AG = rows_per_block(pl.H);
   dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+  pl.prof.begin(ST_ADJ_ANGULAR, st);
   hipLaunchKernelGGL(k_adj_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, D, Q, pl.fft_ang,
                      pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 
@@ -411,16 +421,22 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   const int nnodes = pl.n_xi * pl.H;
   constexpr int IG = 4;
   dim3 g1((unsigned)((nrows + 3) / 4), (unsigned)((nimg + IG - 1) / IG));
+  pl.prof.begin(ST_ADJ_SPREAD, st);
   hipLaunchKernelGGL(k_adj_spread<IG>, g1, dim3(256), 0, st, Q, bufB, pl.d_csr_ptr, pl.d_csr, nrows, nnodes,
                      nimg);
+  pl.prof.end(st);
   int CP = rows_per_block(N);
   dim3 g2((unsigned)((Nh + CP - 1) / CP), (unsigned)nimg);
+  pl.prof.begin(ST_ADJ_COLS, st);
   hipLaunchKernelGGL(k_adj_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufB, bufA, pl.fft_grid,
                      pl.d_tw, L, CP);
+  pl.prof.end(st);
   int RP = rows_per_block(N);
   dim3 g3((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  pl.prof.begin(ST_ADJ_ROWS, st);
   hipLaunchKernelGGL(k_adj_rows, g3, dim3(256), 2 * RP * N * sizeof(float2), st, bufA, images, pl.d_deconv,
                      pl.fft_grid, pl.d_tw, L, RP);
+  pl.prof.end(st);
   return hipGetLastError();
 }
 

@@ -273,6 +273,7 @@ int upload_plan(Plan& pl) {
 }
 
 void free_device(Plan& pl) {
+  if (pl.has_device) pl.prof.release();
   void* ptrs[] = {pl.d_radial, pl.d_radial_hi, pl.d_radial_lo, pl.d_coef_off, pl.d_p, pl.d_cov_off,
                   pl.d_deconv, pl.d_nodes, pl.d_tw, pl.d_angtw, pl.d_csr_ptr, pl.d_csr,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov};
@@ -289,6 +290,57 @@ void free_device(Plan& pl) {
   pl.d_csr = nullptr;
   pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = nullptr;
   pl.has_device = false;
+}
+
+const char* stage_name(int s) {
+  static const char* names[ST_COUNT] = {"fwd_rows",    "fwd_cols",   "fwd_gather", "fwd_angular",
+                                        "radial_fwd",  "covariance", "radial_adj", "adj_angular",
+                                        "adj_spread",  "adj_cols",   "adj_rows",   "eig"};
+  return (s >= 0 && s < ST_COUNT) ? names[s] : "unknown";
+}
+
+hipEvent_t Profiler::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::begin(int stage, hipStream_t st) {
+  if (!on) return;
+  Rec r{stage, take(), take()};
+  if (!r.a || !r.b) return;
+  (void)hipEventRecord(r.a, st);
+  recs.push_back(r);
+}
+
+void Profiler::end(hipStream_t st) {
+  if (!on || recs.empty()) return;
+  (void)hipEventRecord(recs.back().b, st);
+}
+
+int Profiler::collect() {
+  int rc = FB_OK;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = FB_ERR_HIP;
+    total_ms[r.stage] += ms;
+    launches[r.stage] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+  return rc;
+}
+
+void Profiler::release() {
+  collect();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
 }
 
 PassLayout pass_layout(const Plan& pl) {

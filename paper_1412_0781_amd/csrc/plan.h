@@ -42,6 +42,44 @@ struct SpreadEntry {
   float weight;
 };
 
+// Kernel stages, in launch order (names in stage_name()).
+enum Stage {
+  ST_FWD_ROWS = 0,
+  ST_FWD_COLS,
+  ST_FWD_GATHER,
+  ST_FWD_ANGULAR,
+  ST_RADIAL_FWD,
+  ST_COVARIANCE,
+  ST_RADIAL_ADJ,
+  ST_ADJ_ANGULAR,
+  ST_ADJ_SPREAD,
+  ST_ADJ_COLS,
+  ST_ADJ_ROWS,
+  ST_EIG,
+  ST_COUNT
+};
+const char* stage_name(int s);
+
+// Optional per-kernel timing: HIP events recorded on the caller's stream around
+// every kernel launch of a plan while enabled.  Not for concurrent use of one
+// plan from several streams.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double total_ms[ST_COUNT] = {};
+  long long launches[ST_COUNT] = {};
+  hipEvent_t take();
+  void begin(int stage, hipStream_t st);
+  void end(hipStream_t st);
+  int collect();  // folds completed records into the totals; returns FB_OK or FB_ERR_HIP
+  void release();
+};
+
 struct GemmItem {  // one (k, tile) work item of a grouped GEMM
   int k;
   int t0;  // first row (or first row tile) of the tile
@@ -79,6 +117,8 @@ struct Plan {
   std::vector<SpreadEntry> csr;    // spreading entries
   std::vector<GemmItem> items_fwd, items_adj, items_cov;
   int bm = 64, bn = 64;            // GEMM tile
+
+  mutable Profiler prof;
 
   // device
   bool has_device = false;

@@ -179,6 +179,19 @@ class Plan:
                            _stream_ptr(dev)), self._h)
         return evals, evecs, C, mean
 
+    # -- per-kernel timing ---------------------------------------------------
+    def profile(self, enable: bool = True):
+        check(lib().fb_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{stage name: (total ms, launches)} of the kernels launched while profiling was on."""
+        ms = np.zeros(32)
+        n = np.zeros(32, np.int64)
+        ns = lib().fb_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 32, 1 if reset else 0)
+        if ns < 0:
+            check(ns, self._h)
+        return {lib().fb_stage_name(s).decode(): (float(ms[s]), int(n[s])) for s in range(ns) if n[s] > 0}
+
     # -- helpers -----------------------------------------------------------
     def blocks(self, packed: torch.Tensor | np.ndarray):
         """Split a packed [cov_size] array into its p_k x p_k blocks."""
