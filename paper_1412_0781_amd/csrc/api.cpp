@@ -15,6 +15,21 @@ struct fb_plan_s {
 namespace {
 
 constexpr int64_t kMaxPassImages = 16384;  // gridDim.y of the per-image kernels stays far below 65535
+constexpr size_t kAlign = 256;             // both pass buffers start on 256-byte boundaries
+
+// Images per pass that fit the workspace, and the two pass buffers inside it.
+int64_t split_workspace(const fb::PassLayout& lay, void* ws, size_t ws_bytes, int64_t n, float2** a, float2** b) {
+  uintptr_t base = ((uintptr_t)ws + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
+  size_t skip = base - (uintptr_t)ws;
+  if (ws_bytes < skip + kAlign) return 0;
+  size_t avail = ws_bytes - skip - kAlign;
+  int64_t nb = std::min<int64_t>({n, (int64_t)(avail / lay.per_image), kMaxPassImages});
+  if (nb < 1) return 0;
+  *a = (float2*)base;
+  size_t off_b = (lay.bytes_a * (size_t)nb + kAlign - 1) & ~(kAlign - 1);
+  *b = (float2*)(base + off_b);
+  return nb;
+}
 
 int make_plan(int L, double c, double R, bool device, fb_plan_t* out) {
   if (!out) return FB_ERR_INVALID_ARG;
@@ -105,7 +120,7 @@ int fb_plan_host_tables(fb_plan_t plan, double* roots, double* norms, double* xi
 size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision) {
   (void)precision;
   if (!plan || batch < 1) return 0;
-  return fb::pass_layout(plan->pl).per_image * (size_t)std::min<int64_t>(batch, kMaxPassImages);
+  return fb::pass_layout(plan->pl).per_image * (size_t)std::min<int64_t>(batch, kMaxPassImages) + kAlign;
 }
 
 int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision, void* ws,
@@ -117,11 +132,10 @@ int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   fb::PassLayout lay = fb::pass_layout(pl);
-  int64_t nb = std::min<int64_t>({n, (int64_t)(ws_bytes / lay.per_image), kMaxPassImages});
+  float2 *bufA = nullptr, *bufB = nullptr;
+  int64_t nb = split_workspace(lay, ws, ws_bytes, n, &bufA, &bufB);
   if (nb < 1) return FB_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  float2* bufA = (float2*)ws;
-  float2* bufB = (float2*)((char*)ws + lay.bytes_a * (size_t)nb);
   const size_t img_stride = (size_t)pl.L * pl.L;
   const size_t coef_stride = 2 * (size_t)pl.p_half;
   for (int64_t s = 0; s < n; s += nb) {
@@ -142,11 +156,10 @@ int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, in
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   fb::PassLayout lay = fb::pass_layout(pl);
-  int64_t nb = std::min<int64_t>({n, (int64_t)(ws_bytes / lay.per_image), kMaxPassImages});
+  float2 *bufA = nullptr, *bufB = nullptr;
+  int64_t nb = split_workspace(lay, ws, ws_bytes, n, &bufA, &bufB);
   if (nb < 1) return FB_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  float2* bufA = (float2*)ws;
-  float2* bufB = (float2*)((char*)ws + lay.bytes_a * (size_t)nb);
   const size_t img_stride = (size_t)pl.L * pl.L;
   const size_t coef_stride = 2 * (size_t)pl.p_half;
   for (int64_t s = 0; s < n; s += nb) {

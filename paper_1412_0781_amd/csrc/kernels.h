@@ -9,6 +9,9 @@ namespace fb {
 // Largest p_k the device eigensolver handles (one workgroup per block C^(k)).
 constexpr int EIG_MAX_P = 256;
 
+// Raise the dynamic-LDS limit of the FFT kernels (called once per plan upload).
+hipError_t configure_kernels();
+
 // Eq.(nufft) for nimg images: images -> polar half-ring samples in bufA (bufB is scratch).
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
                                 hipStream_t st);

@@ -21,6 +21,32 @@ __device__ __forceinline__ float es_eval(float z, float beta) {
   return t > 0.f ? __expf(beta * (sqrtf(t) - 1.0f)) : 0.f;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap the linear block id so that each XCD walks one contiguous range of work.
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  if (total % 8) return lin;
+  return (lin % 8) * (total / 8) + lin / 8;
+}
+
+// Copy `total` elements with every thread issuing U global loads before it stores
+// any of them, so that the loads of one thread are in flight together.
+template <int U, class LoadF, class StoreF>
+__device__ __forceinline__ void batched_copy(int total, LoadF ld, StoreF stv) {
+  for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+    decltype(ld(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int i = base + u * blockDim.x;
+      if (i < total) v[u] = ld(i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int i = base + u * blockDim.x;
+      if (i < total) stv(i, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // forward rows: images [n][L][L] -> G1 [n][M2][L]   (m2 = -hw..N/2+hw)
 // block: RP row pairs of one image
@@ -39,15 +65,20 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
   const float* src = img + (size_t)im * L * L;
   for (int i = threadIdx.x; i < RP * N; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  for (int i = threadIdx.x; i < np * 2 * L; i += blockDim.x) {
-    int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
-    int a = 2 * (pair0 + p) + which;
-    int pos = x0 + b;
-    pos += (pos < 0) ? N : 0;
-    float v = (a < L) ? src[(size_t)a * L + b] * deconv[a] * deconv[b] : 0.f;
-    if (which == 0) buf[p * N + pos].x = v;
-    else buf[p * N + pos].y = v;
-  }
+  batched_copy<8>(
+      np * 2 * L,
+      [&](int i) -> float {
+        int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
+        int a = 2 * (pair0 + p) + which;
+        return (a < L) ? src[(size_t)a * L + b] * deconv[a] * deconv[b] : 0.f;
+      },
+      [&](int i, float v) {
+        int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
+        int pos = x0 + b;
+        pos += (pos < 0) ? N : 0;
+        if (which == 0) buf[p * N + pos].x = v;
+        else buf[p * N + pos].y = v;
+      });
   __syncthreads();
   float2* res = fft_lds(buf, tmp, np, N, fd, tw);
   // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i)
@@ -72,119 +103,179 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
 }
 
 // ---------------------------------------------------------------------------
-// forward cols: G1 [n][M2][L] -> G [n][M2][N]
+// forward cols: G1 [n][M2][L] -> G [M2][N][n]   (image index innermost)
+// block: one stored row m2 for CI consecutive images; LDS transforms padded to N+1
 // ---------------------------------------------------------------------------
 __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g, FftDesc fd,
-                           const float2* __restrict__ tw, int L, int M2, int CP) {
+                           const float2* __restrict__ tw, int L, int M2, int nimg, int CI) {
   extern __shared__ float2 sm[];
-  const int N = fd.n;
+  const int N = fd.n, S = N + 1;
   float2* buf = sm;
-  float2* tmp = sm + CP * N;
-  const int im = blockIdx.y;
-  const int r0 = blockIdx.x * CP;
-  const int nc = min(CP, M2 - r0);
+  float2* tmp = sm + CI * S;
+  const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int m2 = lin / gridDim.x;             // image groups vary fastest: neighbours share lines
+  const int i0 = (lin % gridDim.x) * CI;
+  const int ni = min(CI, nimg - i0);
   const int x0 = -((L - 1 + 1) / 2);
-  for (int i = threadIdx.x; i < CP * N; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < CI * S; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  const float2* src = g1 + ((size_t)im * M2 + r0) * L;
-  for (int i = threadIdx.x; i < nc * L; i += blockDim.x) {
-    int cidx = i / L, a = i - cidx * L;
-    int pos = x0 + a;
-    pos += (pos < 0) ? N : 0;
-    buf[cidx * N + pos] = src[(size_t)cidx * L + a];
+  batched_copy<8>(
+      ni * L,
+      [&](int i) -> float2 {
+        int c = i / L, a = i - c * L;
+        return g1[((size_t)(i0 + c) * M2 + m2) * L + a];
+      },
+      [&](int i, float2 v) {
+        int c = i / L, a = i - c * L;
+        int pos = x0 + a;
+        pos += (pos < 0) ? N : 0;
+        buf[c * S + pos] = v;
+      });
+  __syncthreads();
+  float2* res = fft_lds(buf, tmp, ni, S, fd, tw);
+  float2* dst = g + (size_t)m2 * N * nimg + i0;
+  for (int i = threadIdx.x; i < N * ni; i += blockDim.x) {
+    int m1 = i / ni, c = i - m1 * ni;
+    dst[(size_t)m1 * nimg + c] = res[c * S + m1];
   }
-  __syncthreads();
-  float2* res = fft_lds(buf, tmp, nc, N, fd, tw);
-  float2* dst = g + ((size_t)im * M2 + r0) * N;
-  for (int i = threadIdx.x; i < nc * N; i += blockDim.x) dst[i] = res[i];
 }
 
 // ---------------------------------------------------------------------------
-// forward gather: G [n][M2][N] -> P [n][n_xi * H]
-// thread per polar node; blockIdx.y covers groups of IG images
+// forward gather: G [M2][N][n] -> P [n_xi * H][n]
+// block = (work item: one grid cell and up to kGatherChunk of its nodes, group of IG images).
+// The cell's (CS + W - 1)^2 box of grid points is staged in LDS for the IG images (each
+// point's IG values are one contiguous 8*IG-byte run in G), then every (node, image)
+// lane interpolates its W x W taps from LDS with the node's precomputed weights.
 // ---------------------------------------------------------------------------
-template <int W>
-__global__ void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P, const NodeTap* __restrict__ nodes,
-                             int nnodes, int N, int M2, float beta, int nimg, int IG) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nnodes) return;
-  NodeTap t = nodes[n];
-  float w1[W], w2[W];
-  const float s = 2.0f / W;
+template <int W, int CS, int IG>
+__global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P,
+                                                    const GatherItem* __restrict__ items,
+                                                    const GatherNode* __restrict__ gn, int nitems, int N,
+                                                    int M2, int nimg) {
+  constexpr int BW = CS + W - 1;
+  constexpr int NPT = BW * BW;            // grid points in the box
+  constexpr int NV4 = NPT * IG / 2;       // float4 = two images of one point
+  constexpr int PER = (NV4 + 255) / 256;  // float4 loads per thread
+  extern __shared__ float4 lds4[];
+  float2* box = (float2*)lds4;                               // [NPT][IG]
+  GatherNode* nodes = (GatherNode*)(lds4 + NV4);             // [kGatherChunk]
+  const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int itx = lin % nitems;  // neighbouring cells fastest
+  const int i0 = (lin / nitems) * IG;
+  const GatherItem it = items[itx];
+  const int nn = it.s1 - it.s0;
+  if (i0 + IG <= nimg && (nimg & 1) == 0) {
+    // full group, 16-byte aligned: issue every load of this thread before the LDS stores
+    float4 v[PER];
 #pragma unroll
-  for (int a = 0; a < W; ++a) {
-    w1[a] = es_eval((t.f1 - a) * s, beta);
-    w2[a] = es_eval((t.f2 - a) * s, beta);
-  }
-  int col[W];
+    for (int u = 0; u < PER; ++u) {
+      int i = threadIdx.x + u * 256;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (i < NV4) {
+        int pt = i / (IG / 2), h = i - pt * (IG / 2);
+        int r = pt / BW, cc = pt - r * BW;
+        int row = it.c2 + r, col = it.c1 + cc;
+        col = col >= N ? col - N : col;
+        if (row < M2) v[u] = *(const float4*)(g + ((size_t)row * N + col) * nimg + i0 + 2 * h);
+      }
+    }
 #pragma unroll
-  for (int a = 0; a < W; ++a) {
-    int cc = t.b1 + a;
-    col[a] = cc >= N ? cc - N : cc;
+    for (int u = 0; u < PER; ++u) {
+      int i = threadIdx.x + u * 256;
+      if (i < NV4) lds4[i] = v[u];
+    }
+  } else {
+    for (int i = threadIdx.x; i < NPT * IG; i += blockDim.x) {
+      int pt = i / IG, im = i - pt * IG;
+      int r = pt / BW, cc = pt - r * BW;
+      int row = it.c2 + r, col = it.c1 + cc;
+      col = col >= N ? col - N : col;
+      float2 v = make_float2(0.f, 0.f);
+      if (row < M2 && i0 + im < nimg) v = g[((size_t)row * N + col) * nimg + i0 + im];
+      box[i] = v;
+    }
   }
-  const int i0 = blockIdx.y * IG;
-  const int i1 = min(nimg, i0 + IG);
-  for (int im = i0; im < i1; ++im) {
-    const float2* gi = g + (size_t)im * M2 * N + (size_t)t.b2 * N;
+  {
+    const int* src = (const int*)(gn + it.s0);
+    int* dst = (int*)nodes;
+    constexpr int WPN = sizeof(GatherNode) / 4;
+    for (int i = threadIdx.x; i < nn * WPN; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int im = threadIdx.x % IG;
+  const int slot = threadIdx.x / IG;
+  constexpr int SLOTS = 256 / IG;
+  const bool active = i0 + im < nimg;
+  for (int s = slot; s < nn; s += SLOTS) {
+    const GatherNode& nd = nodes[s];
+    const float2* b = box + (size_t)nd.off * IG + im;
     float ax = 0.f, ay = 0.f;
 #pragma unroll
     for (int bb = 0; bb < W; ++bb) {
       float rx = 0.f, ry = 0.f;
-      const float2* row = gi + (size_t)bb * N;
 #pragma unroll
       for (int a = 0; a < W; ++a) {
-        float2 v = row[col[a]];
-        rx = fmaf(w1[a], v.x, rx);
-        ry = fmaf(w1[a], v.y, ry);
+        float2 v = b[(bb * BW + a) * IG];
+        rx = fmaf(nd.w1[a], v.x, rx);
+        ry = fmaf(nd.w1[a], v.y, ry);
       }
-      ax = fmaf(w2[bb], rx, ax);
-      ay = fmaf(w2[bb], ry, ay);
+      ax = fmaf(nd.w2[bb], rx, ax);
+      ay = fmaf(nd.w2[bb], ry, ay);
     }
-    P[(size_t)im * nnodes + n] = make_float2(ax, ay);
+    if (active) P[(size_t)nd.n * nimg + i0 + im] = make_float2(ax, ay);
   }
 }
 
+size_t gather_lds_bytes() {
+  constexpr int BW = kGatherCell + kGatherW - 1;
+  return (size_t)BW * BW * 16 * sizeof(float2) + kGatherChunk * sizeof(GatherNode);
+}
+
 // ---------------------------------------------------------------------------
-// forward angular: P [n][n_xi][H] -> Fh [K+1][n_xi][ncol]  (ncol = 2 * images in the pass)
-// block: ring j for AG consecutive images
+// forward angular: P [n_xi][H][n] -> Fh [K+1][n_xi][n] (complex; ncol = 2 n floats per row)
+// block: ring j for AG consecutive images; LDS transforms padded to H+1
 // ---------------------------------------------------------------------------
 __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__ Fh, FftDesc fd,
                               const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
                               int nimg, int AG, float scale) {
   extern __shared__ float2 sm[];
-  const int H = fd.n;
+  const int H = fd.n, S = H + 1;
   float2* buf = sm;
-  float2* tmp = sm + AG * H;
-  const int j = blockIdx.x;
-  const int g0 = blockIdx.y * AG;
+  float2* tmp = sm + AG * S;
+  const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int j = lin / gridDim.x;              // image groups vary fastest: neighbours share lines
+  const int g0 = (lin % gridDim.x) * AG;
   const int ng = min(AG, nimg - g0);
+  const float2* ring = P + (size_t)j * H * nimg + g0;
   // packed z_m = s_{2m} + i s_{2m+1}, with s_t = u_t + v_t (t < H), u_{t-H} - v_{t-H} (t >= H)
-  for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
-    int gg = i / H, m = i - gg * H;
-    const float2* ring = P + ((size_t)(g0 + gg) * n_xi + j) * H;
-    float sv[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      int t = 2 * m + e;
-      float2 f = ring[t < H ? t : t - H];
-      sv[e] = t < H ? (f.x + f.y) : (f.x - f.y);
-    }
-    buf[gg * H + m] = make_float2(sv[0], sv[1]);
-  }
+  batched_copy<8>(
+      ng * H,
+      [&](int i) -> float4 {
+        int m = i / ng, gg = i - m * ng;
+        int t0 = 2 * m, t1 = 2 * m + 1;
+        float2 f0 = ring[(size_t)(t0 < H ? t0 : t0 - H) * nimg + gg];
+        float2 f1 = ring[(size_t)(t1 < H ? t1 : t1 - H) * nimg + gg];
+        return make_float4(f0.x, f0.y, f1.x, f1.y);
+      },
+      [&](int i, float4 f) {
+        int m = i / ng, gg = i - m * ng;
+        float s0 = (2 * m < H) ? (f.x + f.y) : (f.x - f.y);
+        float s1 = (2 * m + 1 < H) ? (f.z + f.w) : (f.z - f.w);
+        buf[gg * S + m] = make_float2(s0, s1);
+      });
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, ng, H, fd, tw);
-  const size_t ncol = 2 * (size_t)nimg;
+  float2* res = fft_lds(buf, tmp, ng, S, fd, tw);
   for (int i = threadIdx.x; i < (K + 1) * ng; i += blockDim.x) {
     int k = i / ng, gg = i - k * ng;
-    float2 zk = res[gg * H + (k == 0 ? 0 : k)];
-    float2 zc = cconj(res[gg * H + (k == 0 ? 0 : H - k)]);
+    float2 zk = res[gg * S + k];
+    float2 zc = cconj(res[gg * S + (k == 0 ? 0 : H - k)]);
     // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
     float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
     float2 d = csub(zk, zc);
     float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
-    float2 S = cadd(e, cmul(angtw[k], o));
-    float2 F = (k & 1) ? make_float2(-S.y * scale, S.x * scale) : make_float2(S.x * scale, S.y * scale);
-    Fh[((size_t)k * n_xi + j) * (ncol / 2) + g0 + gg] = F;
+    float2 Sk = cadd(e, cmul(angtw[k], o));
+    float2 F = (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale);
+    Fh[((size_t)k * n_xi + j) * nimg + g0 + gg] = F;
   }
 }
 
@@ -362,9 +453,27 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-static int rows_per_block(int N) {
-  int rp = 32768 / (8 * N);  // two LDS buffers of rp * N complex within 64 KiB
+// Transforms per workgroup: two LDS buffers of rp transforms of S complex values within
+// kLdsBudget bytes, so that two workgroups share one CU's 160 KiB of LDS.
+constexpr int kLdsBudget = 72 * 1024;
+static int rows_per_block(int S) {
+  int rp = kLdsBudget / (16 * S);
   return rp < 1 ? 1 : (rp > 16 ? 16 : rp);
+}
+
+size_t gather_lds_bytes();
+
+hipError_t configure_kernels() {
+  hipError_t e0 = hipFuncSetAttribute((const void*)k_fwd_gather<kGatherW, kGatherCell, 16>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes());
+  if (e0 != hipSuccess) return e0;
+  const void* fns[] = {(const void*)k_fwd_rows,    (const void*)k_fwd_cols, (const void*)k_fwd_angular,
+                       (const void*)k_adj_angular, (const void*)k_adj_cols, (const void*)k_adj_rows};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
@@ -373,31 +482,32 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   int RP = rows_per_block(N);
   dim3 g1((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
   pl.prof.begin(ST_FWD_ROWS, st);
-  hipLaunchKernelGGL(k_fwd_rows, g1, dim3(256), 2 * RP * N * sizeof(float2), st, images, bufA, pl.d_deconv,
+  hipLaunchKernelGGL(k_fwd_rows, g1, dim3(512), 2 * RP * N * sizeof(float2), st, images, bufA, pl.d_deconv,
                      pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, RP);
   pl.prof.end(st);
-  int CP = rows_per_block(N);
-  dim3 g2((unsigned)((pl.M2 + CP - 1) / CP), (unsigned)nimg);
+  int CI = rows_per_block(N + 1);
+  dim3 g2((unsigned)((nimg + CI - 1) / CI), (unsigned)pl.M2);
   pl.prof.begin(ST_FWD_COLS, st);
-  hipLaunchKernelGGL(k_fwd_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufA, bufB, pl.fft_grid,
-                     pl.d_tw, L, pl.M2, CP);
+  hipLaunchKernelGGL(k_fwd_cols, g2, dim3(512), 2 * CI * (N + 1) * sizeof(float2), st, bufA, bufB, pl.fft_grid,
+                     pl.d_tw, L, pl.M2, nimg, CI);
   pl.prof.end(st);
-  const int nnodes = pl.n_xi * pl.H;
-  const int IG = 4;
-  dim3 g3((unsigned)((nnodes + 255) / 256), (unsigned)((nimg + IG - 1) / IG));
+  constexpr int IG = 16;
+  const int nitems = (int)pl.gitems.size();
+  dim3 g3((unsigned)nitems, (unsigned)((nimg + IG - 1) / IG));
   pl.prof.begin(ST_FWD_GATHER, st);
-  hipLaunchKernelGGL(k_fwd_gather<7>, g3, dim3(256), 0, st, bufB, bufA, pl.d_nodes, nnodes, N, pl.M2,
-                     (float)pl.beta, nimg, IG);
+  hipLaunchKernelGGL((k_fwd_gather<kGatherW, kGatherCell, IG>), g3, dim3(256), gather_lds_bytes(), st, bufB, bufA,
+                     pl.d_gitems,
+                     pl.d_gnodes, nitems, N, pl.M2, nimg);
   pl.prof.end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
-  int AG = rows_per_block(pl.H);
-  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
+  int AG = rows_per_block(pl.H + 1);
+  dim3 g((unsigned)((nimg + AG - 1) / AG), (unsigned)pl.n_xi);
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_FWD_ANGULAR, st);
-  hipLaunchKernelGGL(k_fwd_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, P, Fh, pl.fft_ang,
+  hipLaunchKernelGGL(k_fwd_angular, g, dim3(512), 2 * AG * (pl.H + 1) * sizeof(float2), st, P, Fh, pl.fft_ang,
                      pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
   pl.prof.end(st);
   return hipGetLastError();

@@ -7,6 +7,7 @@
 #include <thread>
 
 #include "hostmath.h"
+#include "kernels.h"
 
 namespace fb {
 
@@ -153,6 +154,47 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
       pl.nodes[(size_t)j * pl.H + l] = nt;
     }
 
+  // LDS-tiled gather: nodes grouped by the cell of their tap origin (b1, b2); cells in
+  // row-major order so that consecutive work items are neighbouring cells.  Weights in FP64.
+  {
+    if (pl.w != kGatherW) return FB_ERR_UNSUPPORTED;
+    const int CS = kGatherCell;
+    const int ncx = (pl.N + CS - 1) / CS, ncy = (pl.M2 + CS - 1) / CS;
+    std::vector<std::vector<int>> cell(ncx * ncy);
+    for (size_t n = 0; n < pl.nodes.size(); ++n) {
+      const NodeTap& t = pl.nodes[n];
+      cell[(t.b2 / CS) * ncx + t.b1 / CS].push_back((int)n);
+    }
+    pl.gnodes.clear();
+    pl.gitems.clear();
+    const int BW = CS + pl.w - 1;
+    for (int cy = 0; cy < ncy; ++cy)
+      for (int cx = 0; cx < ncx; ++cx) {
+        const std::vector<int>& lst = cell[cy * ncx + cx];
+        for (size_t a0 = 0; a0 < lst.size(); a0 += kGatherChunk) {
+          GatherItem it{cx * CS, cy * CS, (int)pl.gnodes.size(), 0};
+          for (size_t a = a0; a < std::min(lst.size(), a0 + kGatherChunk); ++a) {
+            int n = lst[a];
+            int j = n / pl.H, l = n % pl.H;
+            double th = 2.0 * kPi * l / pl.n_theta;
+            double t1 = pl.N * pl.xi[j] * std::cos(th), t2 = pl.N * pl.xi[j] * std::sin(th);
+            double b1 = std::ceil(t1 - pl.w / 2.0), b2 = std::ceil(t2 - pl.w / 2.0);
+            const NodeTap& t = pl.nodes[n];
+            GatherNode g;
+            g.n = n;
+            g.off = (t.b2 - cy * CS) * BW + (t.b1 - cx * CS);
+            for (int a2 = 0; a2 < pl.w; ++a2) {
+              g.w1[a2] = (float)es_kernel(2.0 * (t1 - (b1 + a2)) / pl.w, pl.beta);
+              g.w2[a2] = (float)es_kernel(2.0 * (t2 - (b2 + a2)) / pl.w, pl.beta);
+            }
+            pl.gnodes.push_back(g);
+          }
+          it.s1 = (int)pl.gnodes.size();
+          pl.gitems.push_back(it);
+        }
+      }
+  }
+
   // FFTs: grid side N and the angular half length H
   pl.tw.clear();
   std::vector<int> rad;
@@ -240,6 +282,7 @@ static hipError_t upload(T** dptr, const T* src, size_t count) {
 
 int upload_plan(Plan& pl) {
   FB_HIP_TRY(hipGetDevice(&pl.device));
+  FB_HIP_TRY(configure_kernels());
   size_t nb = (size_t)pl.p_half * pl.n_xi;
   std::vector<float> r32(nb);
   std::vector<uint16_t> rhi(nb), rlo(nb);
@@ -260,7 +303,8 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_cov_off, coff.data(), coff.size()));
   std::vector<float> dc(pl.deconv.begin(), pl.deconv.end());
   FB_HIP_TRY(upload(&pl.d_deconv, dc.data(), dc.size()));
-  FB_HIP_TRY(upload(&pl.d_nodes, pl.nodes.data(), pl.nodes.size()));
+  FB_HIP_TRY(upload(&pl.d_gnodes, pl.gnodes.data(), pl.gnodes.size()));
+  FB_HIP_TRY(upload(&pl.d_gitems, pl.gitems.data(), pl.gitems.size()));
   FB_HIP_TRY(upload(&pl.d_tw, (const float2*)pl.tw.data(), pl.tw.size() / 2));
   FB_HIP_TRY(upload(&pl.d_angtw, (const float2*)pl.angtw.data(), pl.angtw.size() / 2));
   FB_HIP_TRY(upload(&pl.d_csr_ptr, pl.csr_ptr.data(), pl.csr_ptr.size()));
@@ -275,7 +319,7 @@ int upload_plan(Plan& pl) {
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
   void* ptrs[] = {pl.d_radial, pl.d_radial_hi, pl.d_radial_lo, pl.d_coef_off, pl.d_p, pl.d_cov_off,
-                  pl.d_deconv, pl.d_nodes, pl.d_tw, pl.d_angtw, pl.d_csr_ptr, pl.d_csr,
+                  pl.d_deconv, pl.d_gnodes, pl.d_gitems, pl.d_tw, pl.d_angtw, pl.d_csr_ptr, pl.d_csr,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -284,7 +328,8 @@ void free_device(Plan& pl) {
   pl.d_coef_off = pl.d_p = nullptr;
   pl.d_cov_off = nullptr;
   pl.d_deconv = nullptr;
-  pl.d_nodes = nullptr;
+  pl.d_gnodes = nullptr;
+  pl.d_gitems = nullptr;
   pl.d_tw = pl.d_angtw = nullptr;
   pl.d_csr_ptr = nullptr;
   pl.d_csr = nullptr;

@@ -34,6 +34,24 @@ struct NodeTap {
   float f2;  // t2 - ceil(t2 - w/2)
 };
 
+// Forward gather, LDS-tiled: nodes grouped by the kGatherCell x kGatherCell grid cell
+// holding their tap origin.  A workgroup stages the cell's box of
+// (kGatherCell + w - 1)^2 grid points (for a group of images) in LDS and
+// interpolates its nodes from there.
+constexpr int kGatherCell = 16;
+constexpr int kGatherW = 7;                       // kernel width the gather kernels are built for
+constexpr int kGatherChunk = 128;                 // nodes per work item at most
+struct GatherNode {
+  int n;                 // polar node j * H + l
+  int off;               // tap origin inside the cell box: row * (cell + w - 1) + col
+  float w1[kGatherW];    // weights along the first grid axis (i1 / x)
+  float w2[kGatherW];    // weights along the second grid axis (i2 / y)
+};
+struct GatherItem {
+  int c1, c2;  // cell origin in grid columns (m1, before wrap) and stored rows (m2 + hw)
+  int s0, s1;  // node range in the cell-sorted node list
+};
+
 // Adjoint spreading, written as a gather: entry of grid point (m1, m2) of the
 // folded half-plane m2 = 0..grid_n/2.  node index in bits 0..30, bit 31 set when
 // the node's conjugate contributes (Hermitian fold of the m2 < 0 / m2 > n/2 taps).
@@ -109,7 +127,9 @@ struct Plan {
   int M2 = 0;       // = N/2 + 2 hw + 1
   int H = 0;        // n_theta / 2: half-ring nodes, also the complex FFT length of the angular step
   std::vector<double> deconv;      // 1 / phi_hat(x / N), x over pixel indices
-  std::vector<NodeTap> nodes;      // n_xi * H
+  std::vector<NodeTap> nodes;      // n_xi * H, node n = j * H + l
+  std::vector<GatherNode> gnodes;  // nodes sorted by gather cell
+  std::vector<GatherItem> gitems;  // (cell, node chunk) work items
   FftDesc fft_grid{}, fft_ang{};
   std::vector<float> tw;           // interleaved (re, im) twiddles of both FFT lengths
   std::vector<float> angtw;        // exp(-2 pi i k / n_theta), k = 0..H, interleaved
@@ -131,7 +151,8 @@ struct Plan {
   int* d_p = nullptr;                 // k_max + 1
   long long* d_cov_off = nullptr;     // k_max + 2
   float* d_deconv = nullptr;
-  NodeTap* d_nodes = nullptr;
+  GatherNode* d_gnodes = nullptr;
+  GatherItem* d_gitems = nullptr;
   float2* d_tw = nullptr;
   float2* d_angtw = nullptr;
   int* d_csr_ptr = nullptr;
