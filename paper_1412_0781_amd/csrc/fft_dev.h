@@ -167,6 +167,7 @@ __device__ __forceinline__ void fft_stage_generic(const float2* __restrict__ in,
 // Full forward FFT; buf holds the input and must be followed by scratch of the
 // same size at `tmp`.  Returns the pointer holding the result.  All threads of
 // the block must call it; it synchronises the block between stages.
+template <bool GENERIC>
 __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int stride, const FftDesc& d,
                                   const float2* __restrict__ tw_all) {
   const float2* tw = tw_all + d.tw_off;
@@ -182,7 +183,9 @@ __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int strid
       case 2: fft_stage_r<2>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
       case 3: fft_stage_r<3>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
       case 5: fft_stage_r<5>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
-      default: fft_stage_generic(in, out, d.n, R, Ns, count, stride, tw, tid, nthr); break;
+      default:
+        if constexpr (GENERIC) fft_stage_generic(in, out, d.n, R, Ns, count, stride, tw, tid, nthr);
+        break;
     }
     __syncthreads();
     float2* t = in;
@@ -191,6 +194,97 @@ __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int strid
     Ns *= R;
   }
   return in;
+}
+
+// In-place variant: a stage first reads every butterfly input of the calling
+// thread into registers, then (after a barrier) writes its outputs over the
+// same buffer, so one LDS buffer suffices.  A thread holds at most VMAX values;
+// the caller guarantees count * n <= fft_inplace_capacity(d, nthreads) and that
+// every radix of d is 4 or 8 (each supported radix adds its register arrays to
+// the kernel, so the in-place form is kept to the two that cover 2^k lengths).
+template <int R, int VMAX>
+__device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, int count, int stride,
+                                                  const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int BM = VMAX / R;
+  const int nb = n / R;
+  const int total = count * nb;
+  const int twstep = n / (Ns * R);
+  float2 v[BM][R];
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    int idx = tid + b * nthr;
+    if (idx < total) {
+      int t = idx / nb, j = idx - t * nb;
+      const float2* src = buf + t * stride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BM; ++b) {
+    int idx = tid + b * nthr;
+    if (idx < total) {
+      int t = idx / nb, j = idx - t * nb;
+      int k = j % Ns;
+      if (k) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[k * r * twstep]);
+      }
+      Dft<R>::run(v[b], tw, n, R);
+      float2* dst = buf + t * stride;
+      int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int kFftVmax = 16;
+
+// Largest count * n the in-place FFT can take with nthr threads (0 if a radix is unsupported).
+inline int fft_inplace_capacity(const FftDesc& d, int nthr) {
+  int cap = 1 << 30;
+  for (int s = 0; s < d.nstage; ++s) {
+    int R = d.radix[s];
+    if (R != 4 && R != 8) return 0;
+    cap = cap < (kFftVmax / R) * R * nthr ? cap : (kFftVmax / R) * R * nthr;
+  }
+  return cap;
+}
+
+__device__ inline void fft_lds_inplace(float2* buf, int count, int stride, const FftDesc& d,
+                                       const float2* __restrict__ tw_all) {
+  const float2* tw = tw_all + d.tw_off;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int Ns = 1;
+  for (int s = 0; s < d.nstage; ++s) {
+    int R = d.radix[s];
+    switch (R) {
+      case 8: fft_stage_inplace<8, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr); break;
+      default: fft_stage_inplace<4, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr); break;
+    }
+    Ns *= R;
+  }
+}
+
+// FFT forms, chosen per plan on the host and compiled as separate kernels so that
+// each kernel carries only its own code (and register budget):
+//   FFT_INPLACE  one LDS buffer, radices 4 and 8
+//   FFT_PINGPONG two LDS buffers, radices 2, 3, 4, 5, 8
+//   FFT_GENERIC  two LDS buffers, also odd primes up to 31
+enum FftForm { FFT_INPLACE = 0, FFT_PINGPONG = 1, FFT_GENERIC = 2 };
+
+template <int FORM>
+__device__ __forceinline__ float2* run_fft(float2* buf, float2* tmp, int count, int stride, const FftDesc& d,
+                                           const float2* __restrict__ tw_all) {
+  if constexpr (FORM == FFT_INPLACE) {
+    fft_lds_inplace(buf, count, stride, d, tw_all);
+    return buf;
+  } else {
+    return fft_lds<FORM == FFT_GENERIC>(buf, tmp, count, stride, d, tw_all);
+  }
 }
 
 }  // namespace fb

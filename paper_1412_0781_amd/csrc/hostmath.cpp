@@ -160,7 +160,7 @@ int next_smooth_235(int m) {
 bool fft_radices(int n, std::vector<int>& radices) {
   radices.clear();
   int r = n;
-  while (r % 8 == 0) { radices.push_back(8); r /= 8; }
+  while (r % 8 == 0 && r != 16) { radices.push_back(8); r /= 8; }  // 16 = 4 * 4 rather than 8 * 2
   while (r % 4 == 0) { radices.push_back(4); r /= 4; }
   while (r % 2 == 0) { radices.push_back(2); r /= 2; }
   for (int p = 3; p <= 31; p += 2) {

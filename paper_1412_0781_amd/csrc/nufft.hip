@@ -11,6 +11,8 @@
 // Adjoint: the transpose of each stage in reverse order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft_dev.h"
 #include "kernels.h"
 
@@ -51,6 +53,7 @@ __device__ __forceinline__ void batched_copy(int total, LoadF ld, StoreF stv) {
 // forward rows: images [n][L][L] -> G1 [n][M2][L]   (m2 = -hw..N/2+hw)
 // block: RP row pairs of one image
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g1, const float* __restrict__ deconv,
                            FftDesc fd, const float2* __restrict__ tw, int L, int M2, int hw, int RP) {
   extern __shared__ float2 sm[];
@@ -80,7 +83,7 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
         else buf[p * N + pos].y = v;
       });
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, np, N, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, np, N, fd, tw);
   // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i)
   float2* out = g1 + (size_t)im * M2 * L;
   for (int i = threadIdx.x; i < M2 * 2 * np; i += blockDim.x) {
@@ -106,6 +109,7 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
 // forward cols: G1 [n][M2][L] -> G [M2][N][n]   (image index innermost)
 // block: one stored row m2 for CI consecutive images; LDS transforms padded to N+1
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g, FftDesc fd,
                            const float2* __restrict__ tw, int L, int M2, int nimg, int CI) {
   extern __shared__ float2 sm[];
@@ -132,7 +136,7 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
         buf[c * S + pos] = v;
       });
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, ni, S, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, ni, S, fd, tw);
   float2* dst = g + (size_t)m2 * N * nimg + i0;
   for (int i = threadIdx.x; i < N * ni; i += blockDim.x) {
     int m1 = i / ni, c = i - m1 * ni;
@@ -160,9 +164,9 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g
   float2* box = (float2*)lds4;                               // [NPT][IG]
   GatherNode* nodes = (GatherNode*)(lds4 + NV4);             // [kGatherChunk]
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int itx = lin % nitems;  // neighbouring cells fastest
-  const int i0 = (lin / nitems) * IG;
-  const GatherItem it = items[itx];
+  const int ngrp = gridDim.x;    // image groups fastest: partners share the box's cache lines
+  const int i0 = (lin % ngrp) * IG;
+  const GatherItem it = items[lin / ngrp];
   const int nn = it.s1 - it.s0;
   if (i0 + IG <= nimg && (nimg & 1) == 0) {
     // full group, 16-byte aligned: issue every load of this thread before the LDS stores
@@ -226,15 +230,17 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g
   }
 }
 
+constexpr int kGatherImages = 8;  // images per gather workgroup
 size_t gather_lds_bytes() {
   constexpr int BW = kGatherCell + kGatherW - 1;
-  return (size_t)BW * BW * 16 * sizeof(float2) + kGatherChunk * sizeof(GatherNode);
+  return (size_t)BW * BW * kGatherImages * sizeof(float2) + kGatherChunk * sizeof(GatherNode);
 }
 
 // ---------------------------------------------------------------------------
 // forward angular: P [n_xi][H][n] -> Fh [K+1][n_xi][n] (complex; ncol = 2 n floats per row)
 // block: ring j for AG consecutive images; LDS transforms padded to H+1
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__ Fh, FftDesc fd,
                               const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
                               int nimg, int AG, float scale) {
@@ -264,7 +270,7 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
         buf[gg * S + m] = make_float2(s0, s1);
       });
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, ng, S, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, ng, S, fd, tw);
   for (int i = threadIdx.x; i < (K + 1) * ng; i += blockDim.x) {
     int k = i / ng, gg = i - k * ng;
     float2 zk = res[gg * S + k];
@@ -284,6 +290,7 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
 // Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H}),  s'_t = Re sum_{k<=K} E_k e^{2 pi i k t / n_theta},
 // E_k = c D_k (k even), -i c D_k (k odd)
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__ Q, FftDesc fd,
                               const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
                               int nimg, int AG, float scale) {
@@ -319,7 +326,7 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
     buf[gg * H + kp] = cconj(zin);
   }
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, ng, H, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, ng, H, fd, tw);
   // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1}
   for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
     int gg = i / H, l = i - gg * H;
@@ -377,6 +384,7 @@ __global__ void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ 
 // ---------------------------------------------------------------------------
 // adjoint cols: Y [n][N/2+1][N] -> Zc [n][N/2+1][L]: inverse FFT along m1, keep x1 in the pixel range
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_adj_cols(const float2* __restrict__ Y, float2* __restrict__ Zc, FftDesc fd,
                            const float2* __restrict__ tw, int L, int CP) {
   extern __shared__ float2 sm[];
@@ -389,7 +397,7 @@ __global__ void k_adj_cols(const float2* __restrict__ Y, float2* __restrict__ Zc
   const float2* src = Y + ((size_t)im * Nh + r0) * N;
   for (int i = threadIdx.x; i < nc * N; i += blockDim.x) buf[i] = cconj(src[i]);
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, nc, N, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, nc, N, fd, tw);
   const int x0 = -((L - 1 + 1) / 2);
   float2* dst = Zc + ((size_t)im * Nh + r0) * L;
   for (int i = threadIdx.x; i < nc * L; i += blockDim.x) {
@@ -404,6 +412,7 @@ __global__ void k_adj_cols(const float2* __restrict__ Y, float2* __restrict__ Zc
 // adjoint rows: Zc [n][N/2+1][L] -> images [n][L][L]
 // two real rows per complex inverse FFT of the Hermitian-completed sequences
 // ---------------------------------------------------------------------------
+template <int FORM>
 __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ img, const float* __restrict__ deconv,
                            FftDesc fd, const float2* __restrict__ tw, int L, int RP) {
   extern __shared__ float2 sm[];
@@ -435,7 +444,7 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
     buf[p * N + m] = cconj(h);
   }
   __syncthreads();
-  float2* res = fft_lds(buf, tmp, np, N, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, np, N, fd, tw);
   const int x0 = -((L - 1 + 1) / 2);
   float* dst = img + (size_t)im * L * L;
   for (int i = threadIdx.x; i < np * 2 * L; i += blockDim.x) {
@@ -453,22 +462,52 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Transforms per workgroup: two LDS buffers of rp transforms of S complex values within
-// kLdsBudget bytes, so that two workgroups share one CU's 160 KiB of LDS.
+// Transforms per workgroup and FFT form.  The in-place form needs one LDS buffer
+// (count * S complex values), the ping-pong forms two; either stays within
+// kLdsBudget bytes so that two workgroups share one CU's 160 KiB of LDS.
 constexpr int kLdsBudget = 72 * 1024;
-static int rows_per_block(int S) {
-  int rp = kLdsBudget / (16 * S);
-  return rp < 1 ? 1 : (rp > 16 ? 16 : rp);
+constexpr int kFftThreads = 512;
+constexpr int kMaxTransforms = 16;
+struct FftLaunch {
+  int count;
+  int form;
+  size_t lds;
+};
+static FftLaunch fft_launch(const FftDesc& d, int S) {
+  int cap = fft_inplace_capacity(d, kFftThreads);
+  if (cap > 0) {
+    int c = std::min(kMaxTransforms, std::min(cap / d.n, kLdsBudget / (8 * S)));
+    if (c >= 1) return FftLaunch{c, FFT_INPLACE, (size_t)c * S * sizeof(float2)};
+  }
+  bool special = true;
+  for (int s = 0; s < d.nstage; ++s) {
+    int R = d.radix[s];
+    special = special && (R == 2 || R == 3 || R == 4 || R == 5 || R == 8);
+  }
+  int c = std::max(1, std::min(kMaxTransforms, kLdsBudget / (16 * S)));
+  return FftLaunch{c, special ? FFT_PINGPONG : FFT_GENERIC, 2 * (size_t)c * S * sizeof(float2)};
 }
+
+#define FB_LAUNCH_FFT(KERNEL, form, grid, block, lds, st, ...)                                  \
+  do {                                                                                          \
+    if ((form) == FFT_INPLACE)                                                                  \
+      hipLaunchKernelGGL(KERNEL<FFT_INPLACE>, grid, block, lds, st, __VA_ARGS__);               \
+    else if ((form) == FFT_PINGPONG)                                                            \
+      hipLaunchKernelGGL(KERNEL<FFT_PINGPONG>, grid, block, lds, st, __VA_ARGS__);              \
+    else                                                                                        \
+      hipLaunchKernelGGL(KERNEL<FFT_GENERIC>, grid, block, lds, st, __VA_ARGS__);               \
+  } while (0)
 
 size_t gather_lds_bytes();
 
 hipError_t configure_kernels() {
-  hipError_t e0 = hipFuncSetAttribute((const void*)k_fwd_gather<kGatherW, kGatherCell, 16>,
+  hipError_t e0 = hipFuncSetAttribute((const void*)k_fwd_gather<kGatherW, kGatherCell, kGatherImages>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes());
   if (e0 != hipSuccess) return e0;
-  const void* fns[] = {(const void*)k_fwd_rows,    (const void*)k_fwd_cols, (const void*)k_fwd_angular,
-                       (const void*)k_adj_angular, (const void*)k_adj_cols, (const void*)k_adj_rows};
+#define FB_FORMS(K) (const void*)K<FFT_INPLACE>, (const void*)K<FFT_PINGPONG>, (const void*)K<FFT_GENERIC>
+  const void* fns[] = {FB_FORMS(k_fwd_rows),    FB_FORMS(k_fwd_cols), FB_FORMS(k_fwd_angular),
+                       FB_FORMS(k_adj_angular), FB_FORMS(k_adj_cols), FB_FORMS(k_adj_rows)};
+#undef FB_FORMS
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
     if (e != hipSuccess) return e;
@@ -479,47 +518,46 @@ hipError_t configure_kernels() {
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
                                 hipStream_t st) {
   const int N = pl.N, L = pl.L;
-  int RP = rows_per_block(N);
-  dim3 g1((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  FftLaunch fr = fft_launch(pl.fft_grid, N);
+  dim3 g1((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
   pl.prof.begin(ST_FWD_ROWS, st);
-  hipLaunchKernelGGL(k_fwd_rows, g1, dim3(512), 2 * RP * N * sizeof(float2), st, images, bufA, pl.d_deconv,
-                     pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, RP);
+  FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,
+                pl.d_tw, L, pl.M2, pl.hw, fr.count);
   pl.prof.end(st);
-  int CI = rows_per_block(N + 1);
-  dim3 g2((unsigned)((nimg + CI - 1) / CI), (unsigned)pl.M2);
+  FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
+  dim3 g2((unsigned)((nimg + fc.count - 1) / fc.count), (unsigned)pl.M2);
   pl.prof.begin(ST_FWD_COLS, st);
-  hipLaunchKernelGGL(k_fwd_cols, g2, dim3(512), 2 * CI * (N + 1) * sizeof(float2), st, bufA, bufB, pl.fft_grid,
-                     pl.d_tw, L, pl.M2, nimg, CI);
+  FB_LAUNCH_FFT(k_fwd_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufA, bufB, pl.fft_grid, pl.d_tw, L,
+                pl.M2, nimg, fc.count);
   pl.prof.end(st);
-  constexpr int IG = 16;
+  constexpr int IG = kGatherImages;
   const int nitems = (int)pl.gitems.size();
-  dim3 g3((unsigned)nitems, (unsigned)((nimg + IG - 1) / IG));
+  dim3 g3((unsigned)((nimg + IG - 1) / IG), (unsigned)nitems);
   pl.prof.begin(ST_FWD_GATHER, st);
   hipLaunchKernelGGL((k_fwd_gather<kGatherW, kGatherCell, IG>), g3, dim3(256), gather_lds_bytes(), st, bufB, bufA,
-                     pl.d_gitems,
-                     pl.d_gnodes, nitems, N, pl.M2, nimg);
+                     pl.d_gitems, pl.d_gnodes, nitems, N, pl.M2, nimg);
   pl.prof.end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
-  int AG = rows_per_block(pl.H + 1);
-  dim3 g((unsigned)((nimg + AG - 1) / AG), (unsigned)pl.n_xi);
+  FftLaunch fa = fft_launch(pl.fft_ang, pl.H + 1);
+  dim3 g((unsigned)((nimg + fa.count - 1) / fa.count), (unsigned)pl.n_xi);
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_FWD_ANGULAR, st);
-  hipLaunchKernelGGL(k_fwd_angular, g, dim3(512), 2 * AG * (pl.H + 1) * sizeof(float2), st, P, Fh, pl.fft_ang,
-                     pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  FB_LAUNCH_FFT(k_fwd_angular, fa.form, g, dim3(kFftThreads), fa.lds, st, P, Fh, pl.fft_ang, pl.d_tw, pl.d_angtw,
+                pl.n_xi, pl.k_max, nimg, fa.count, scale);
   pl.prof.end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st) {
-  int AG = rows_per_block(pl.H);
-  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + AG - 1) / AG));
+  FftLaunch fa = fft_launch(pl.fft_ang, pl.H);
+  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + fa.count - 1) / fa.count));
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_ADJ_ANGULAR, st);
-  hipLaunchKernelGGL(k_adj_angular, g, dim3(256), 2 * AG * pl.H * sizeof(float2), st, D, Q, pl.fft_ang,
-                     pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, AG, scale);
+  FB_LAUNCH_FFT(k_adj_angular, fa.form, g, dim3(kFftThreads), fa.lds, st, D, Q, pl.fft_ang, pl.d_tw, pl.d_angtw,
+                pl.n_xi, pl.k_max, nimg, fa.count, scale);
   pl.prof.end(st);
   return hipGetLastError();
 }
@@ -535,17 +573,17 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   hipLaunchKernelGGL(k_adj_spread<IG>, g1, dim3(256), 0, st, Q, bufB, pl.d_csr_ptr, pl.d_csr, nrows, nnodes,
                      nimg);
   pl.prof.end(st);
-  int CP = rows_per_block(N);
-  dim3 g2((unsigned)((Nh + CP - 1) / CP), (unsigned)nimg);
+  FftLaunch fc = fft_launch(pl.fft_grid, N);
+  dim3 g2((unsigned)((Nh + fc.count - 1) / fc.count), (unsigned)nimg);
   pl.prof.begin(ST_ADJ_COLS, st);
-  hipLaunchKernelGGL(k_adj_cols, g2, dim3(256), 2 * CP * N * sizeof(float2), st, bufB, bufA, pl.fft_grid,
-                     pl.d_tw, L, CP);
+  FB_LAUNCH_FFT(k_adj_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufB, bufA, pl.fft_grid, pl.d_tw, L,
+                fc.count);
   pl.prof.end(st);
-  int RP = rows_per_block(N);
-  dim3 g3((unsigned)(((L + 1) / 2 + RP - 1) / RP), (unsigned)nimg);
+  FftLaunch fr = fft_launch(pl.fft_grid, N);
+  dim3 g3((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
   pl.prof.begin(ST_ADJ_ROWS, st);
-  hipLaunchKernelGGL(k_adj_rows, g3, dim3(256), 2 * RP * N * sizeof(float2), st, bufA, images, pl.d_deconv,
-                     pl.fft_grid, pl.d_tw, L, RP);
+  FB_LAUNCH_FFT(k_adj_rows, fr.form, g3, dim3(kFftThreads), fr.lds, st, bufA, images, pl.d_deconv, pl.fft_grid,
+                pl.d_tw, L, fr.count);
   pl.prof.end(st);
   return hipGetLastError();
 }
