@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16x3")
     ap.add_argument("--cpu-sample", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -183,6 +185,15 @@ def main():
     from paper_1412_0781_amd import Plan
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_gib > 0:
+        nel = int(args.copy_calibration_gib * (1 << 30)) // 4
+        src = torch.empty(nel, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * nel, "copy_bytes_written": 4 * nel}), flush=True)
+        return
     L = args.L
     c, R = 0.5, L / 2
     log(f"plan L={L} R={R} c={c}")

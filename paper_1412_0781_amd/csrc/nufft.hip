@@ -151,29 +151,31 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
 // point's IG values are one contiguous 8*IG-byte run in G), then every (node, image)
 // lane interpolates its W x W taps from LDS with the node's precomputed weights.
 // ---------------------------------------------------------------------------
-template <int W, int CS, int IG>
-__global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P,
+template <int W, int CS, int IG, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P,
                                                     const GatherItem* __restrict__ items,
                                                     const GatherNode* __restrict__ gn, int nitems, int N,
                                                     int M2, int nimg) {
   constexpr int BW = CS + W - 1;
   constexpr int NPT = BW * BW;            // grid points in the box
   constexpr int NV4 = NPT * IG / 2;       // float4 = two images of one point
-  constexpr int PER = (NV4 + 255) / 256;  // float4 loads per thread
+  constexpr int PER = (NV4 + NT - 1) / NT;  // float4 loads per thread
   extern __shared__ float4 lds4[];
   float2* box = (float2*)lds4;                               // [NPT][IG]
   GatherNode* nodes = (GatherNode*)(lds4 + NV4);             // [kGatherChunk]
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int ngrp = gridDim.x;    // image groups fastest: partners share the box's cache lines
-  const int i0 = (lin % ngrp) * IG;
-  const GatherItem it = items[lin / ngrp];
+  // cells vary fastest inside one image group: an XCD then walks neighbouring cells,
+  // whose boxes overlap by the halo, while those rows are still in its L2
+  const int itx = lin % nitems;
+  const int i0 = (lin / nitems) * IG;
+  const GatherItem it = items[itx];
   const int nn = it.s1 - it.s0;
   if (i0 + IG <= nimg && (nimg & 1) == 0) {
     // full group, 16-byte aligned: issue every load of this thread before the LDS stores
     float4 v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      int i = threadIdx.x + u * 256;
+      int i = threadIdx.x + u * NT;
       v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (i < NV4) {
         int pt = i / (IG / 2), h = i - pt * (IG / 2);
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      int i = threadIdx.x + u * 256;
+      int i = threadIdx.x + u * NT;
       if (i < NV4) lds4[i] = v[u];
     }
   } else {
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g
   __syncthreads();
   const int im = threadIdx.x % IG;
   const int slot = threadIdx.x / IG;
-  constexpr int SLOTS = 256 / IG;
+  constexpr int SLOTS = NT / IG;
   const bool active = i0 + im < nimg;
   for (int s = slot; s < nn; s += SLOTS) {
     const GatherNode& nd = nodes[s];
@@ -230,7 +232,8 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const float2* __restrict__ g
   }
 }
 
-constexpr int kGatherImages = 8;  // images per gather workgroup
+constexpr int kGatherImages = 16;   // images per gather workgroup: one 128-byte line per grid point
+constexpr int kGatherThreads = 512;
 size_t gather_lds_bytes() {
   constexpr int BW = kGatherCell + kGatherW - 1;
   return (size_t)BW * BW * kGatherImages * sizeof(float2) + kGatherChunk * sizeof(GatherNode);
@@ -501,7 +504,7 @@ static FftLaunch fft_launch(const FftDesc& d, int S) {
 size_t gather_lds_bytes();
 
 hipError_t configure_kernels() {
-  hipError_t e0 = hipFuncSetAttribute((const void*)k_fwd_gather<kGatherW, kGatherCell, kGatherImages>,
+  hipError_t e0 = hipFuncSetAttribute((const void*)k_fwd_gather<kGatherW, kGatherCell, kGatherImages, kGatherThreads>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes());
   if (e0 != hipSuccess) return e0;
 #define FB_FORMS(K) (const void*)K<FFT_INPLACE>, (const void*)K<FFT_PINGPONG>, (const void*)K<FFT_GENERIC>
@@ -532,9 +535,10 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   pl.prof.end(st);
   constexpr int IG = kGatherImages;
   const int nitems = (int)pl.gitems.size();
-  dim3 g3((unsigned)((nimg + IG - 1) / IG), (unsigned)nitems);
+  dim3 g3((unsigned)nitems, (unsigned)((nimg + IG - 1) / IG));
   pl.prof.begin(ST_FWD_GATHER, st);
-  hipLaunchKernelGGL((k_fwd_gather<kGatherW, kGatherCell, IG>), g3, dim3(256), gather_lds_bytes(), st, bufB, bufA,
+  hipLaunchKernelGGL((k_fwd_gather<kGatherW, kGatherCell, IG, kGatherThreads>), g3, dim3(kGatherThreads),
+                     gather_lds_bytes(), st, bufB, bufA,
                      pl.d_gitems, pl.d_gnodes, nitems, N, pl.M2, nimg);
   pl.prof.end(st);
   return hipGetLastError();
