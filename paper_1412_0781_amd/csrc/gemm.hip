@@ -62,94 +62,166 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 }
 
 // ---------------------------------------------------------------------------
-// radial quadrature, FP32.  grid: (column tiles, work items (k, q-tile))
+// radial quadrature.  grid: (column tiles of 64 = 32 images, work items (k, 128-row tile))
 // Fh: float [K+1][n_xi][ncol], ncol = 2 * images (re, im interleaved)
 // coeffs: float [image][p_half][2]
+// A wave owns 32 rows x 64 columns (two 32x32 MFMA tiles).  The next K chunk is
+// loaded into registers while the current one is multiplied from LDS; the output
+// tile is transposed through LDS so that each image's rows are written as one run.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ radial, const float* __restrict__ Fh,
-                                                        float* __restrict__ coeffs, const GemmItem* __restrict__ items,
-                                                        const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                        int n_xi, int ncol, long long p_half) {
-  __shared__ float As[BK][BM + 4];
-  __shared__ float Bs[BK][BN + 4];
-  const GemmItem it = items[blockIdx.y];
-  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
-  const int n0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  const float* fk = Fh + (size_t)k * n_xi * ncol;
-  f32x16 acc = {};
-  for (int k0 = 0; k0 < n_xi; k0 += BK) {
-    for (int i = tid; i < BM * BK; i += 256) {
-      int m = i / BK, kk = i - m * BK;
-      int row = m0 + m, kc = k0 + kk;
-      As[kk][m] = (row < pk && kc < n_xi) ? radial[(size_t)(off + row) * n_xi + kc] : 0.f;
-    }
-    for (int i = tid; i < BK * BN; i += 256) {
-      int kk = i / BN, n = i - kk * BN;
-      int kc = k0 + kk, col = n0 + n;
-      Bs[kk][n] = (kc < n_xi && col < ncol) ? fk[(size_t)kc * ncol + col] : 0.f;
-    }
-    __syncthreads();
-    mma_f32(As, Bs, acc, wm, wn, lane);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int q = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-    if (q < pk && c < ncol) {
-      float v = (k == 0 && (c & 1)) ? 0.f : acc[i];
-      coeffs[(size_t)(c >> 1) * 2 * p_half + 2 * (size_t)(off + q) + (c & 1)] = v;
-    }
-  }
-}
+constexpr int RBM = 128, RBN = 64, RBK = 32;
+constexpr int RLDH = RBK + 8;
 
-// radial quadrature, split-BF16 x3
-__global__ __launch_bounds__(256) void k_radial_fwd_bf16x3(const unsigned short* __restrict__ rhi,
-                                                           const unsigned short* __restrict__ rlo,
-                                                           const float* __restrict__ Fh, float* __restrict__ coeffs,
-                                                           const GemmItem* __restrict__ items,
-                                                           const int* __restrict__ coef_off,
-                                                           const int* __restrict__ p, int n_xi, int ncol,
-                                                           long long p_half) {
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Al[BM][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Bl[BN][LDH];
+template <int PREC>
+struct RadialSmem;
+template <>
+struct RadialSmem<0> {
+  float As[RBK][RBM + 4];
+  float Bs[RBK][RBN + 4];
+};
+template <>
+struct RadialSmem<1> {
+  unsigned short Ah[RBM][RLDH], Al[RBM][RLDH];
+  unsigned short Bh[RBN][RLDH], Bl[RBN][RLDH];
+};
+union RadialOut {
+  float Cs[RBN][RBM + 4];
+};
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ radial, const float* __restrict__ Fh,
+                                                    float* __restrict__ coeffs, const GemmItem* __restrict__ items,
+                                                    const int* __restrict__ coef_off, const int* __restrict__ p,
+                                                    int n_xi, int ncol, long long p_half) {
+  constexpr size_t SZ = sizeof(RadialSmem<PREC>) > sizeof(RadialOut) ? sizeof(RadialSmem<PREC>) : sizeof(RadialOut);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[SZ];
+  RadialSmem<PREC>& S = *reinterpret_cast<RadialSmem<PREC>*>(smem);
+  RadialOut& O = *reinterpret_cast<RadialOut*>(smem);
   const GemmItem it = items[blockIdx.y];
   const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
-  const int n0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int n0 = blockIdx.x * RBN;
+  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
   const float* fk = Fh + (size_t)k * n_xi * ncol;
-  f32x16 acc = {};
-  for (int k0 = 0; k0 < n_xi; k0 += BKH) {
-    for (int i = tid; i < BM * BKH; i += 256) {
-      int m = i / BKH, kk = i - m * BKH;
-      int row = m0 + m, kc = k0 + kk;
-      bool ok = row < pk && kc < n_xi;
-      size_t src = (size_t)(off + row) * n_xi + kc;
-      Ah[m][kk] = ok ? rhi[src] : (unsigned short)0;
-      Al[m][kk] = ok ? rlo[src] : (unsigned short)0;
+  const bool vec = ((n_xi & 3) == 0) && ((ncol & 3) == 0);
+  float4 ra[4], rb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // A: 128 rows x 32 k, four consecutive k per thread
+      int idx = tid + u * 256, m = idx >> 3, kq = (idx & 7) * 4;
+      int row = m0 + m, kc = k0 + kq;
+      const float* src = radial + (size_t)(off + row) * n_xi + kc;
+      if (row < pk && vec && kc + 3 < n_xi) {
+        ra[u] = *(const float4*)src;
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (row < pk && kc + e < n_xi) ? src[e] : 0.f;
+        ra[u] = make_float4(t[0], t[1], t[2], t[3]);
+      }
     }
-    for (int i = tid; i < BKH * BN; i += 256) {
-      int kk = i / BN, n = i - kk * BN;
-      int kc = k0 + kk, col = n0 + n;
-      float x = (kc < n_xi && col < ncol) ? fk[(size_t)kc * ncol + col] : 0.f;
-      unsigned short h, l;
-      split_bf16(x, h, l);
-      Bh[n][kk] = h;
-      Bl[n][kk] = l;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {  // B: 32 k x 64 columns, four consecutive columns per thread
+      int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
+      int kc = k0 + kk, col = n0 + nq;
+      const float* src = fk + (size_t)kc * ncol + col;
+      if (kc < n_xi && vec && col + 3 < ncol) {
+        rb[u] = *(const float4*)src;
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (kc < n_xi && col + e < ncol) ? src[e] : 0.f;
+        rb[u] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int idx = tid + u * 256, m = idx >> 3, kq = (idx & 7) * 4;
+      float v[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
+      if constexpr (PREC == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) S.As[kq + e][m] = v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned short h, l;
+          split_bf16(v[e], h, l);
+          S.Ah[m][kq + e] = h;
+          S.Al[m][kq + e] = l;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
+      float v[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
+      if constexpr (PREC == 0) {
+        *(float4*)&S.Bs[kk][nq] = rb[u];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          unsigned short h, l;
+          split_bf16(v[e], h, l);
+          S.Bh[nq + e][kk] = h;
+          S.Bl[nq + e][kk] = l;
+        }
+      }
+    }
+  };
+  f32x16 acc0 = {}, acc1 = {};
+  const int nch = (n_xi + RBK - 1) / RBK;
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) gload((c + 1) * RBK);
+    if constexpr (PREC == 0) {
+#pragma unroll
+      for (int kk = 0; kk < RBK; kk += 2) {
+        float a = S.As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
+        float b0 = S.Bs[kk + (lane >> 5)][lane & 31];
+        float b1 = S.Bs[kk + (lane >> 5)][32 + (lane & 31)];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+      }
+    } else {
+      const int ra_ = wm * 32 + (lane & 31), rb0 = lane & 31, rb1 = 32 + (lane & 31);
+#pragma unroll
+      for (int kb = 0; kb < RBK; kb += 16) {
+        const int cc = kb + 8 * (lane >> 5);
+        bf16x8 ah = ld8(&S.Ah[ra_][cc]), al = ld8(&S.Al[ra_][cc]);
+        bf16x8 bh0 = ld8(&S.Bh[rb0][cc]), bl0 = ld8(&S.Bl[rb0][cc]);
+        bf16x8 bh1 = ld8(&S.Bh[rb1][cc]), bl1 = ld8(&S.Bl[rb1][cc]);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, acc1, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, acc1, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, acc1, 0, 0, 0);
+      }
     }
     __syncthreads();
-    mma_bf16x3(Ah, Al, Bh, Bl, acc, wm, wn, lane);
-    __syncthreads();
+    if (c + 1 < nch) {
+      lstore();
+      __syncthreads();
+    }
   }
+  // transpose the 128 x 64 tile through LDS: Cs[column][row]
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    int q = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-    if (q < pk && c < ncol) {
-      float v = (k == 0 && (c & 1)) ? 0.f : acc[i];
-      coeffs[(size_t)(c >> 1) * 2 * p_half + 2 * (size_t)(off + q) + (c & 1)] = v;
-    }
+    int r = wm * 32 + acc_row(i, lane);
+    O.Cs[lane & 31][r] = acc0[i];
+    O.Cs[32 + (lane & 31)][r] = acc1[i];
+  }
+  __syncthreads();
+  const int nq = min(RBM, pk - m0);
+  const int nimg_t = min(RBN, ncol - n0) / 2;
+  for (int i = tid; i < nimg_t * nq; i += 256) {
+    int il = i / nq, q = i - il * nq;
+    float re = O.Cs[2 * il][q];
+    float im = (k == 0) ? 0.f : O.Cs[2 * il + 1][q];
+    *(float2*)&coeffs[(size_t)(n0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
   }
 }
 
@@ -292,15 +364,14 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
 hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs, int nimg, int precision,
                                  hipStream_t st) {
   const int ncol = 2 * nimg;
-  dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_fwd.size());
+  dim3 g((unsigned)((ncol + RBN - 1) / RBN), (unsigned)pl.items_fwd.size());
   pl.prof.begin(ST_RADIAL_FWD, st);
   if (precision == FB_BF16X3)
-    hipLaunchKernelGGL(k_radial_fwd_bf16x3, g, dim3(256), 0, st, pl.d_radial_hi, pl.d_radial_lo,
-                       (const float*)Fh, coeffs, pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, ncol,
-                       (long long)pl.p_half);
+    hipLaunchKernelGGL(k_radial_fwd<1>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
+                       pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
   else
-    hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs,
-                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
+    hipLaunchKernelGGL(k_radial_fwd<0>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
+                       pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
   pl.prof.end(st);
   return hipGetLastError();
 }

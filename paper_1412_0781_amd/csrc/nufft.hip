@@ -57,16 +57,16 @@ template <int FORM>
 __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g1, const float* __restrict__ deconv,
                            FftDesc fd, const float2* __restrict__ tw, int L, int M2, int hw, int RP) {
   extern __shared__ float2 sm[];
-  const int N = fd.n;
+  const int N = fd.n, S = N + 1;  // odd stride: the unpack reads all transforms at one frequency
   float2* buf = sm;
-  float2* tmp = sm + RP * N;
+  float2* tmp = sm + RP * S;
   const int im = blockIdx.y;
   const int pair0 = blockIdx.x * RP;
   const int npairs = (L + 1) / 2;
   const int np = min(RP, npairs - pair0);
   const int x0 = -((L - 1 + 1) / 2);  // -ceil((L-1)/2)
   const float* src = img + (size_t)im * L * L;
-  for (int i = threadIdx.x; i < RP * N; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < RP * S; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
   batched_copy<8>(
       np * 2 * L,
@@ -79,11 +79,11 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
         int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
         int pos = x0 + b;
         pos += (pos < 0) ? N : 0;
-        if (which == 0) buf[p * N + pos].x = v;
-        else buf[p * N + pos].y = v;
+        if (which == 0) buf[p * S + pos].x = v;
+        else buf[p * S + pos].y = v;
       });
   __syncthreads();
-  float2* res = run_fft<FORM>(buf, tmp, np, N, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, np, S, fd, tw);
   // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i)
   float2* out = g1 + (size_t)im * M2 * L;
   for (int i = threadIdx.x; i < M2 * 2 * np; i += blockDim.x) {
@@ -94,7 +94,7 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
     int m2 = mi - hw;
     int mp = m2 % N; mp += (mp < 0) ? N : 0;
     int mn = (-m2) % N; mn += (mn < 0) ? N : 0;
-    float2 z1 = res[p * N + mp], z2 = cconj(res[p * N + mn]);
+    float2 z1 = res[p * S + mp], z2 = cconj(res[p * S + mn]);
     float2 v;
     if (which == 0) v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
     else {
@@ -521,7 +521,7 @@ hipError_t configure_kernels() {
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
                                 hipStream_t st) {
   const int N = pl.N, L = pl.L;
-  FftLaunch fr = fft_launch(pl.fft_grid, N);
+  FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
   dim3 g1((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
   pl.prof.begin(ST_FWD_ROWS, st);
   FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,

@@ -254,7 +254,7 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
   pl.items_adj.clear();
   pl.items_cov.clear();
   for (int k = 0; k <= pl.k_max; ++k) {
-    for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm) pl.items_fwd.push_back(GemmItem{k, m0, 0, 0});
+    for (int m0 = 0; m0 < pl.p[k]; m0 += kRadialRows) pl.items_fwd.push_back(GemmItem{k, m0, 0, 0});
     for (int j0 = 0; j0 < pl.n_xi; j0 += pl.bm) pl.items_adj.push_back(GemmItem{k, j0, 0, 0});
     for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm)
       for (int n0 = m0; n0 < pl.p[k]; n0 += pl.bn) pl.items_cov.push_back(GemmItem{k, m0, n0, 0});

@@ -98,6 +98,8 @@ struct Profiler {
   void release();
 };
 
+constexpr int kRadialRows = 128;  // row tile of the radial quadrature GEMM
+
 struct GemmItem {  // one (k, tile) work item of a grouped GEMM
   int k;
   int t0;  // first row (or first row tile) of the tile
