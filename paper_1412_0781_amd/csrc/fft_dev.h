@@ -123,17 +123,17 @@ __device__ __forceinline__ void dft_generic(float2* v, int R, const float2* tw, 
 template <int R>
 __device__ __forceinline__ void fft_stage_r(const float2* __restrict__ in, float2* __restrict__ out, int n, int Ns,
                                             int count, int stride, const float2* __restrict__ tw, int tid,
-                                            int nthr) {
+                                            int nthr, FastDiv dnb, FastDiv dns) {
   const int nb = n / R;
   const int twstep = n / (Ns * R);
   for (int idx = tid; idx < count * nb; idx += nthr) {
-    int t = idx / nb, j = idx - t * nb;
+    int t = dnb.div(idx), j = idx - t * nb;
     const float2* src = in + t * stride;
     float2* dst = out + t * stride;
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-    int k = j % Ns;
+    int k = j - dns.div(j) * Ns;
     if (k) {
 #pragma unroll
       for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * twstep]);
@@ -147,16 +147,17 @@ __device__ __forceinline__ void fft_stage_r(const float2* __restrict__ in, float
 
 __device__ __forceinline__ void fft_stage_generic(const float2* __restrict__ in, float2* __restrict__ out, int n,
                                                   int R, int Ns, int count, int stride,
-                                                  const float2* __restrict__ tw, int tid, int nthr) {
+                                                  const float2* __restrict__ tw, int tid, int nthr, FastDiv dnb,
+                                                  FastDiv dns) {
   const int nb = n / R;
   const int twstep = n / (Ns * R);
   for (int idx = tid; idx < count * nb; idx += nthr) {
-    int t = idx / nb, j = idx - t * nb;
+    int t = dnb.div(idx), j = idx - t * nb;
     const float2* src = in + t * stride;
     float2* dst = out + t * stride;
     float2 v[31];
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-    int k = j % Ns;
+    int k = j - dns.div(j) * Ns;
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(k * r * twstep) % n]);
     dft_generic<31>(v, R, tw, n);
     int base = (j - k) * R + k;
@@ -178,13 +179,13 @@ __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int strid
   for (int s = 0; s < d.nstage; ++s) {
     int R = d.radix[s];
     switch (R) {
-      case 8: fft_stage_r<8>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
-      case 4: fft_stage_r<4>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
-      case 2: fft_stage_r<2>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
-      case 3: fft_stage_r<3>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
-      case 5: fft_stage_r<5>(in, out, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 8: fft_stage_r<8>(in, out, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      case 4: fft_stage_r<4>(in, out, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      case 2: fft_stage_r<2>(in, out, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      case 3: fft_stage_r<3>(in, out, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      case 5: fft_stage_r<5>(in, out, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
       default:
-        if constexpr (GENERIC) fft_stage_generic(in, out, d.n, R, Ns, count, stride, tw, tid, nthr);
+        if constexpr (GENERIC) fft_stage_generic(in, out, d.n, R, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]);
         break;
     }
     __syncthreads();
@@ -204,7 +205,8 @@ __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int strid
 // the kernel, so the in-place form is kept to the two that cover 2^k lengths).
 template <int R, int VMAX>
 __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, int count, int stride,
-                                                  const float2* __restrict__ tw, int tid, int nthr) {
+                                                  const float2* __restrict__ tw, int tid, int nthr, FastDiv dnb,
+                                                  FastDiv dns) {
   constexpr int BM = VMAX / R;
   const int nb = n / R;
   const int total = count * nb;
@@ -214,7 +216,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
   for (int b = 0; b < BM; ++b) {
     int idx = tid + b * nthr;
     if (idx < total) {
-      int t = idx / nb, j = idx - t * nb;
+      int t = dnb.div(idx), j = idx - t * nb;
       const float2* src = buf + t * stride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
@@ -225,8 +227,8 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
   for (int b = 0; b < BM; ++b) {
     int idx = tid + b * nthr;
     if (idx < total) {
-      int t = idx / nb, j = idx - t * nb;
-      int k = j % Ns;
+      int t = dnb.div(idx), j = idx - t * nb;
+      int k = j - dns.div(j) * Ns;
       if (k) {
 #pragma unroll
         for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[k * r * twstep]);
@@ -262,8 +264,8 @@ __device__ inline void fft_lds_inplace(float2* buf, int count, int stride, const
   for (int s = 0; s < d.nstage; ++s) {
     int R = d.radix[s];
     switch (R) {
-      case 8: fft_stage_inplace<8, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr); break;
-      default: fft_stage_inplace<4, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr); break;
+      case 8: fft_stage_inplace<8, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      default: fft_stage_inplace<4, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
     }
     Ns *= R;
   }

@@ -49,13 +49,34 @@ __device__ __forceinline__ void batched_copy(int total, LoadF ld, StoreF stv) {
   }
 }
 
+// Same, over an (outer, inner) index space with inner < INNER <= 64: thread t takes
+// inner = t % INNER and outer = t / INNER + multiples of blockDim / INNER (no division).
+template <int U, int INNER, class LoadF, class StoreF>
+__device__ __forceinline__ void batched_copy2d(int n_outer, int n_inner, LoadF ld, StoreF stv) {
+  const int in = threadIdx.x % INNER, os = blockDim.x / INNER;
+  if (in >= n_inner) return;
+  for (int base = threadIdx.x / INNER; base < n_outer; base += U * os) {
+    decltype(ld(0, 0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int o = base + u * os;
+      if (o < n_outer) v[u] = ld(o, in);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int o = base + u * os;
+      if (o < n_outer) stv(o, in, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // forward rows: images [n][L][L] -> G1 [n][M2][L]   (m2 = -hw..N/2+hw)
 // block: RP row pairs of one image
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g1, const float* __restrict__ deconv,
-                           FftDesc fd, const float2* __restrict__ tw, int L, int M2, int hw, int RP) {
+                           FftDesc fd, const float2* __restrict__ tw, int L, int M2, int hw, int RP, FastDiv dL) {
   extern __shared__ float2 sm[];
   const int N = fd.n, S = N + 1;  // odd stride: the unpack reads all transforms at one frequency
   float2* buf = sm;
@@ -68,40 +89,42 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
   const float* src = img + (size_t)im * L * L;
   for (int i = threadIdx.x; i < RP * S; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
+  // rows a = 2 pair0 + r, r < 2 np; row r goes to transform r / 2, real (r even) or imaginary part
   batched_copy<8>(
       np * 2 * L,
       [&](int i) -> float {
-        int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
-        int a = 2 * (pair0 + p) + which;
+        int r = dL.div(i), b = i - r * L;
+        int a = 2 * pair0 + r;
         return (a < L) ? src[(size_t)a * L + b] * deconv[a] * deconv[b] : 0.f;
       },
       [&](int i, float v) {
-        int p = i / (2 * L), rem = i - p * 2 * L, which = rem / L, b = rem - which * L;
+        int r = dL.div(i), b = i - r * L;
         int pos = x0 + b;
         pos += (pos < 0) ? N : 0;
-        if (which == 0) buf[p * S + pos].x = v;
-        else buf[p * S + pos].y = v;
+        float* slot = (float*)&buf[(r >> 1) * S + pos];
+        slot[r & 1] = v;
       });
   __syncthreads();
   float2* res = run_fft<FORM>(buf, tmp, np, S, fd, tw);
-  // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i)
+  // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i); lanes over the rows
   float2* out = g1 + (size_t)im * M2 * L;
-  for (int i = threadIdx.x; i < M2 * 2 * np; i += blockDim.x) {
-    int mi = i / (2 * np), r = i - mi * 2 * np;
-    int p = r >> 1, which = r & 1;
-    int a = 2 * (pair0 + p) + which;
-    if (a >= L) continue;
-    int m2 = mi - hw;
-    int mp = m2 % N; mp += (mp < 0) ? N : 0;
-    int mn = (-m2) % N; mn += (mn < 0) ? N : 0;
-    float2 z1 = res[p * S + mp], z2 = cconj(res[p * S + mn]);
-    float2 v;
-    if (which == 0) v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
-    else {
-      float2 u = csub(z1, z2);
-      v = make_float2(0.5f * u.y, -0.5f * u.x);
+  const int r = threadIdx.x & 31;
+  const int a = 2 * pair0 + r;
+  if (r < 2 * np && a < L) {
+    const int p = r >> 1, which = r & 1;
+    for (int mi = threadIdx.x >> 5; mi < M2; mi += blockDim.x >> 5) {
+      int m2 = mi - hw;
+      int mp = m2 < 0 ? m2 + N : m2;      // |m2| < N
+      int mn = m2 > 0 ? N - m2 : -m2;
+      float2 z1 = res[p * S + mp], z2 = cconj(res[p * S + mn]);
+      float2 v;
+      if (which == 0) v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+      else {
+        float2 u = csub(z1, z2);
+        v = make_float2(0.5f * u.y, -0.5f * u.x);
+      }
+      out[(size_t)mi * L + a] = v;
     }
-    out[(size_t)mi * L + a] = v;
   }
 }
 
@@ -111,14 +134,14 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g, FftDesc fd,
-                           const float2* __restrict__ tw, int L, int M2, int nimg, int CI) {
+                           const float2* __restrict__ tw, int L, int M2, int nimg, int CI, FastDiv dL) {
   extern __shared__ float2 sm[];
   const int N = fd.n, S = N + 1;
   float2* buf = sm;
   float2* tmp = sm + CI * S;
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int m2 = lin / gridDim.x;             // image groups vary fastest: neighbours share lines
-  const int i0 = (lin % gridDim.x) * CI;
+  const int i0 = (lin - m2 * gridDim.x) * CI;
   const int ni = min(CI, nimg - i0);
   const int x0 = -((L - 1 + 1) / 2);
   for (int i = threadIdx.x; i < CI * S; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
@@ -126,11 +149,11 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
   batched_copy<8>(
       ni * L,
       [&](int i) -> float2 {
-        int c = i / L, a = i - c * L;
+        int c = dL.div(i), a = i - c * L;
         return g1[((size_t)(i0 + c) * M2 + m2) * L + a];
       },
       [&](int i, float2 v) {
-        int c = i / L, a = i - c * L;
+        int c = dL.div(i), a = i - c * L;
         int pos = x0 + a;
         pos += (pos < 0) ? N : 0;
         buf[c * S + pos] = v;
@@ -138,10 +161,9 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
   __syncthreads();
   float2* res = run_fft<FORM>(buf, tmp, ni, S, fd, tw);
   float2* dst = g + (size_t)m2 * N * nimg + i0;
-  for (int i = threadIdx.x; i < N * ni; i += blockDim.x) {
-    int m1 = i / ni, c = i - m1 * ni;
-    dst[(size_t)m1 * nimg + c] = res[c * S + m1];
-  }
+  const int c = threadIdx.x & 15;  // CI <= 16 images in the workgroup
+  if (c < ni)
+    for (int m1 = threadIdx.x >> 4; m1 < N; m1 += blockDim.x >> 4) dst[(size_t)m1 * nimg + c] = res[c * S + m1];
 }
 
 // ---------------------------------------------------------------------------
@@ -208,27 +230,41 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
     for (int i = threadIdx.x; i < nn * WPN; i += blockDim.x) dst[i] = src[i];
   }
   __syncthreads();
-  const int im = threadIdx.x % IG;
-  const int slot = threadIdx.x / IG;
-  constexpr int SLOTS = NT / IG;
-  const bool active = i0 + im < nimg;
+  // each lane interpolates one node for two consecutive images (16-byte LDS reads)
+  constexpr int IP = IG / 2;
+  const int ip = threadIdx.x % IP;
+  const int slot = threadIdx.x / IP;
+  constexpr int SLOTS = NT / IP;
+  const int img = i0 + 2 * ip;
+  const bool pair_ok = img + 1 < nimg && (nimg & 1) == 0;
+  const float4* box4 = (const float4*)box;
   for (int s = slot; s < nn; s += SLOTS) {
     const GatherNode& nd = nodes[s];
-    const float2* b = box + (size_t)nd.off * IG + im;
-    float ax = 0.f, ay = 0.f;
+    const float4* b = box4 + (size_t)nd.off * IP + ip;
+    float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
 #pragma unroll
     for (int bb = 0; bb < W; ++bb) {
-      float rx = 0.f, ry = 0.f;
+      float rx0 = 0.f, ry0 = 0.f, rx1 = 0.f, ry1 = 0.f;
 #pragma unroll
       for (int a = 0; a < W; ++a) {
-        float2 v = b[(bb * BW + a) * IG];
-        rx = fmaf(nd.w1[a], v.x, rx);
-        ry = fmaf(nd.w1[a], v.y, ry);
+        float4 v = b[(bb * BW + a) * IP];
+        rx0 = fmaf(nd.w1[a], v.x, rx0);
+        ry0 = fmaf(nd.w1[a], v.y, ry0);
+        rx1 = fmaf(nd.w1[a], v.z, rx1);
+        ry1 = fmaf(nd.w1[a], v.w, ry1);
       }
-      ax = fmaf(nd.w2[bb], rx, ax);
-      ay = fmaf(nd.w2[bb], ry, ay);
+      ax0 = fmaf(nd.w2[bb], rx0, ax0);
+      ay0 = fmaf(nd.w2[bb], ry0, ay0);
+      ax1 = fmaf(nd.w2[bb], rx1, ax1);
+      ay1 = fmaf(nd.w2[bb], ry1, ay1);
     }
-    if (active) P[(size_t)nd.n * nimg + i0 + im] = make_float2(ax, ay);
+    float2* dst = P + (size_t)nd.n * nimg + img;
+    if (pair_ok) {
+      *(float4*)dst = make_float4(ax0, ay0, ax1, ay1);
+    } else {
+      if (img < nimg) dst[0] = make_float2(ax0, ay0);
+      if (img + 1 < nimg) dst[1] = make_float2(ax1, ay1);
+    }
   }
 }
 
@@ -253,29 +289,28 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
   float2* tmp = sm + AG * S;
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int j = lin / gridDim.x;              // image groups vary fastest: neighbours share lines
-  const int g0 = (lin % gridDim.x) * AG;
+  const int g0 = (lin - j * gridDim.x) * AG;
   const int ng = min(AG, nimg - g0);
   const float2* ring = P + (size_t)j * H * nimg + g0;
   // packed z_m = s_{2m} + i s_{2m+1}, with s_t = u_t + v_t (t < H), u_{t-H} - v_{t-H} (t >= H)
-  batched_copy<8>(
-      ng * H,
-      [&](int i) -> float4 {
-        int m = i / ng, gg = i - m * ng;
+  batched_copy2d<8, 16>(
+      H, ng,
+      [&](int m, int gg) -> float4 {
         int t0 = 2 * m, t1 = 2 * m + 1;
         float2 f0 = ring[(size_t)(t0 < H ? t0 : t0 - H) * nimg + gg];
         float2 f1 = ring[(size_t)(t1 < H ? t1 : t1 - H) * nimg + gg];
         return make_float4(f0.x, f0.y, f1.x, f1.y);
       },
-      [&](int i, float4 f) {
-        int m = i / ng, gg = i - m * ng;
+      [&](int m, int gg, float4 f) {
         float s0 = (2 * m < H) ? (f.x + f.y) : (f.x - f.y);
         float s1 = (2 * m + 1 < H) ? (f.z + f.w) : (f.z - f.w);
         buf[gg * S + m] = make_float2(s0, s1);
       });
   __syncthreads();
   float2* res = run_fft<FORM>(buf, tmp, ng, S, fd, tw);
-  for (int i = threadIdx.x; i < (K + 1) * ng; i += blockDim.x) {
-    int k = i / ng, gg = i - k * ng;
+  const int gg = threadIdx.x & 15;  // AG <= 16 images in the workgroup
+  if (gg < ng)
+  for (int k = threadIdx.x >> 4; k <= K; k += blockDim.x >> 4) {
     float2 zk = res[gg * S + k];
     float2 zc = cconj(res[gg * S + (k == 0 ? 0 : H - k)]);
     // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
@@ -525,13 +560,13 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   dim3 g1((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
   pl.prof.begin(ST_FWD_ROWS, st);
   FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,
-                pl.d_tw, L, pl.M2, pl.hw, fr.count);
+                pl.d_tw, L, pl.M2, pl.hw, fr.count, make_fastdiv(L));
   pl.prof.end(st);
   FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
   dim3 g2((unsigned)((nimg + fc.count - 1) / fc.count), (unsigned)pl.M2);
   pl.prof.begin(ST_FWD_COLS, st);
   FB_LAUNCH_FFT(k_fwd_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufA, bufB, pl.fft_grid, pl.d_tw, L,
-                pl.M2, nimg, fc.count);
+                pl.M2, nimg, fc.count, make_fastdiv(L));
   pl.prof.end(st);
   constexpr int IG = kGatherImages;
   const int nitems = (int)pl.gitems.size();

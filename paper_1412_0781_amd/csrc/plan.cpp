@@ -33,7 +33,13 @@ static void add_fft(FftDesc& d, int n, std::vector<float>& tw) {
   std::vector<int> rad;
   fft_radices(n, rad);
   d.nstage = (int)rad.size();
-  for (int i = 0; i < d.nstage; ++i) d.radix[i] = rad[i];
+  int ns = 1;
+  for (int i = 0; i < d.nstage; ++i) {
+    d.radix[i] = rad[i];
+    d.dnb[i] = make_fastdiv(n / rad[i]);
+    d.dns[i] = make_fastdiv(ns);
+    ns *= rad[i];
+  }
   d.tw_off = (int)(tw.size() / 2);
   for (int t = 0; t < n; ++t) {
     double a = -2.0 * kPi * (double)t / (double)n;

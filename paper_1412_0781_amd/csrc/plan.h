@@ -13,6 +13,28 @@ namespace fb {
 
 constexpr int kMaxRadices = 24;
 
+// Division by a divisor fixed on the host, for 0 <= x < 2^31 and 1 <= d < 2^31:
+// q = floor(x * m / 2^s) with s = 31 + ceil(log2 d) and m = floor(2^s / d) + 1.
+// The error term x (m - 2^s/d) / 2^s is below x / 2^s < 2^-ceil(log2 d) <= 1/d, so
+// the floor equals floor(x / d).  m < 2^32 for every such d.
+struct FastDiv {
+  unsigned m;
+  unsigned s;
+  int d;
+  int pad;
+#ifdef __HIPCC__
+  __host__ __device__
+#endif
+  inline int div(int x) const { return (int)(((unsigned long long)(unsigned)x * m) >> s); }
+};
+inline FastDiv make_fastdiv(int d) {
+  unsigned c = 0;
+  while ((1ull << c) < (unsigned long long)d) ++c;
+  unsigned s = 31 + c;
+  unsigned long long m = ((1ull << s) / (unsigned long long)d) + 1ull;
+  return FastDiv{(unsigned)m, s, d, 0};
+}
+
 // One FFT length: its radix sequence and where its twiddles
 // exp(-2 pi i t / n), t = 0..n-1, start in the plan's twiddle table.
 struct FftDesc {
@@ -21,6 +43,8 @@ struct FftDesc {
   int tw_off;
   int pad;
   int radix[kMaxRadices];
+  FastDiv dnb[kMaxRadices];  // division by n / radix[s]
+  FastDiv dns[kMaxRadices];  // division by radix[0] * ... * radix[s-1]
 };
 
 // Interpolation footprint of one polar node (j, l), l < n_theta/2, on the
