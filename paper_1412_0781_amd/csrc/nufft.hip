@@ -242,21 +242,32 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
     const GatherNode& nd = nodes[s];
     const float4* b = box4 + (size_t)nd.off * IP + ip;
     float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+    // rows of W taps: the next row's loads are issued before this row's products
+    float4 cur[W], nxt[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) cur[a] = b[a * IP];
 #pragma unroll
     for (int bb = 0; bb < W; ++bb) {
+      if (bb + 1 < W) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) nxt[a] = b[((bb + 1) * BW + a) * IP];
+      }
       float rx0 = 0.f, ry0 = 0.f, rx1 = 0.f, ry1 = 0.f;
 #pragma unroll
       for (int a = 0; a < W; ++a) {
-        float4 v = b[(bb * BW + a) * IP];
-        rx0 = fmaf(nd.w1[a], v.x, rx0);
-        ry0 = fmaf(nd.w1[a], v.y, ry0);
-        rx1 = fmaf(nd.w1[a], v.z, rx1);
-        ry1 = fmaf(nd.w1[a], v.w, ry1);
+        rx0 = fmaf(nd.w1[a], cur[a].x, rx0);
+        ry0 = fmaf(nd.w1[a], cur[a].y, ry0);
+        rx1 = fmaf(nd.w1[a], cur[a].z, rx1);
+        ry1 = fmaf(nd.w1[a], cur[a].w, ry1);
       }
       ax0 = fmaf(nd.w2[bb], rx0, ax0);
       ay0 = fmaf(nd.w2[bb], ry0, ay0);
       ax1 = fmaf(nd.w2[bb], rx1, ax1);
       ay1 = fmaf(nd.w2[bb], ry1, ay1);
+      if (bb + 1 < W) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) cur[a] = nxt[a];
+      }
     }
     float2* dst = P + (size_t)nd.n * nimg + img;
     if (pair_ok) {
