@@ -139,11 +139,19 @@ int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, in
  *   S0[q] += sum_i a^i_{0q}                                           (FP64 [p_0])
  *   *count += n                                                       (host int64)
  * G and S0 are device memory owned by the caller (zero them before the first
- * call).  Partial sums are formed in FP32 over at most 256 images and added to
- * FP64 in a fixed order, so results are bitwise reproducible.  Asynchronous.
- * precision selects FB_FP32 or FB_BF16X3 products. */
+ * call).  The n images are cut into at most 16 runs of consecutive images;
+ * within a run, partial sums are formed in FP32 over at most 256 images and
+ * added to FP64 in a fixed order, and the runs' FP64 sums are added into G in
+ * run order, so results are bitwise reproducible.  ws: device scratch of at
+ * least fb_covariance_workspace_bytes(plan, n) bytes, 8-byte aligned, owned by
+ * the caller (contents on entry are ignored).  Asynchronous.  precision selects
+ * FB_FP32 or FB_BF16X3 products.
+ * Errors: FB_ERR_INVALID_ARG (NULL or misaligned pointers, n < 0, bad
+ * precision), FB_ERR_WORKSPACE (ws too small), FB_ERR_NO_DEVICE (host-only plan). */
 int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
-                  int precision, void* stream);
+                  int precision, void* ws, size_t ws_bytes, void* stream);
+/* Scratch bytes fb_covariance needs for n images (0 for n <= 0 or a NULL plan). */
+size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n);
 
 /* Finalise and diagonalise (Algorithm 2, steps 1 and 4), all FP64 on the device:
  *   m = S0 / count;  C^(0) = G^(0)/count - m m^T;  C^(k) = G^(k)/count (k > 0);

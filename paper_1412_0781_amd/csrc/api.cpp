@@ -172,16 +172,22 @@ int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, in
   return FB_OK;
 }
 
+size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n) {
+  if (!plan || n <= 0) return 0;
+  return fb::cov_split(plan->pl, n).bytes;
+}
+
 int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
-                  int precision, void* stream) {
+                  int precision, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || n < 0) return FB_ERR_INVALID_ARG;
   if (precision != FB_FP32 && precision != FB_BF16X3) return FB_ERR_INVALID_ARG;
   if (!G || !S0 || !count) return FB_ERR_INVALID_ARG;
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   if (n == 0) return FB_OK;
-  if (!coeffs) return FB_ERR_INVALID_ARG;
-  int rc = hip_rc(pl, fb::launch_covariance(pl, coeffs, n, G, S0, precision, (hipStream_t)stream));
+  if (!coeffs || !ws || ((uintptr_t)ws & 7)) return FB_ERR_INVALID_ARG;
+  if (ws_bytes < fb::cov_split(pl, n).bytes) return FB_ERR_WORKSPACE;
+  int rc = hip_rc(pl, fb::launch_covariance(pl, coeffs, n, G, S0, precision, ws, (hipStream_t)stream));
   if (rc == FB_OK) *count += n;
   return rc;
 }

@@ -1,0 +1,16 @@
+// Small device helpers shared by the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fb {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap the linear block id so that each XCD walks one contiguous range of work:
+// XCD x receives the ids [x q + min(x, r), ...) of length q + (x < r), where
+// total = 8 q + r.
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  const int q = total >> 3, r = total & 7, x = lin & 7;
+  return x * q + min(x, r) + (lin >> 3);
+}
+
+}  // namespace fb

@@ -9,6 +9,9 @@
 // hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16, accumulated in FP32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "dev_common.h"
 #include "kernels.h"
 
 namespace fb {
@@ -267,73 +270,130 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// covariance accumulation.  grid: work items (k, q-tile, q'-tile) with q'-tile >= q-tile.
-// Each block runs over all n images; FP32 partial sums over 256 images are
-// added into FP64 registers, then into G (and its mirror) in a fixed order.
-// The k = 0 diagonal tiles also accumulate S0.
+// covariance accumulation (Eqs.(ck),(ck_0)), split over image slices.
+// grid: work items (k, 64-row tile m0, 64-column tile n0 >= m0) x S image slices.
+// The K dimension is (image, re/im): X[q][2i + r] = (Re, Im) a^i_{kq}, so
+// Re(A A^*) = X X^T.  A K chunk is 16 images = 32 columns; the next chunk is held in
+// registers while the current one is multiplied.  FP32 tile sums are moved to FP64
+// registers every COV_FLUSH_COLS columns; each block writes its FP64 tile (and the
+// mirrored tile) into its slice's partial copy of G, which k_cov_reduce then adds
+// into G in slice order, so the result does not depend on scheduling.
+// The k = 0 imaginary parts are masked; the k = 0 diagonal tiles also sum S0.
 // ---------------------------------------------------------------------------
 constexpr int COV_FLUSH_COLS = 512;
+constexpr int COV_IMG = 16;                 // images per K chunk
+constexpr int COV_K = 2 * COV_IMG;          // columns per K chunk
+static_assert(COV_K == BKH, "BF16 tiles hold one K chunk");
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ coeffs, double* __restrict__ G,
-                                                    double* __restrict__ S0, const GemmItem* __restrict__ items,
+struct CovSmem;
+template <>
+struct CovSmem<0> {
+  float As[COV_K][BM + 4];
+  float Bs[COV_K][BN + 4];
+};
+template <>
+struct CovSmem<1> {
+  unsigned short Ah[BM][LDH], Al[BM][LDH];
+  unsigned short Bh[BN][LDH], Bl[BN][LDH];
+};
+
+__device__ __forceinline__ void mma_f32_k32(const float (*As)[BM + 4], const float (*Bs)[BN + 4], f32x16& acc,
+                                            int wm, int wn, int lane) {
+#pragma unroll
+  for (int kk = 0; kk < COV_K; kk += 2) {
+    float a = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
+    float b = Bs[kk + (lane >> 5)][wn * 32 + (lane & 31)];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ coeffs, double* __restrict__ partG,
+                                                    double* __restrict__ partS0, const GemmItem* __restrict__ items,
                                                     const int* __restrict__ coef_off, const int* __restrict__ p,
                                                     const long long* __restrict__ cov_off, long long n,
-                                                    long long p_half) {
-  // FP32 path uses As/Bs; BF16 path uses the hi/lo arrays
-  __shared__ float As[PREC ? BKH : BK][BM + 4];
-  __shared__ float Bs[BK][BN + 4];
-  __shared__ __attribute__((aligned(16))) unsigned short Ah[PREC ? BM : 1][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Al[PREC ? BM : 1][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Bh[PREC ? BN : 1][LDH];
-  __shared__ __attribute__((aligned(16))) unsigned short Bl[PREC ? BN : 1][LDH];
-  const GemmItem it = items[blockIdx.x];
+                                                    long long p_half, int nitems, long long per, long long cov_size,
+                                                    int p0) {
+  __shared__ __attribute__((aligned(16))) CovSmem<PREC> S;
+  __shared__ double dred[4][BM];
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int itx = lin % nitems, slice = lin / nitems;  // tiles of one k are neighbours on one XCD
+  const GemmItem it = items[itx];
   const int k = it.k, m0 = it.t0, n0 = it.t1, pk = p[k], off = coef_off[k];
+  const bool diag = (m0 == n0);
+  const bool do_sum = (k == 0 && diag);
+  const long long i0 = (long long)slice * per, i1 = min(n, i0 + per);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  const bool do_sum = (k == 0 && m0 == n0);
-  const long long ncol = 2 * n;
-  const int bk = PREC ? BKH : BK;
+  // loader: thread owns row q = tid & 63 of the tile for images (tid >> 6) + 4u, u < 4
+  const int q = tid & 63, ib = tid >> 6;
+  const bool rowa = m0 + q < pk, rowb = n0 + q < pk;
+  const float2* srcA = (const float2*)coeffs + off + m0 + q;
+  const float2* srcB = (const float2*)coeffs + off + n0 + q;
+  const bool k0 = (k == 0);
+  float2 ra[4], rb[4];
+  auto gload = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      long long img = c0 + ib + 4 * u;
+      bool ok = img < i1;
+      ra[u] = (ok && rowa) ? srcA[img * p_half] : make_float2(0.f, 0.f);
+      if (!diag) rb[u] = (ok && rowb) ? srcB[img * p_half] : make_float2(0.f, 0.f);
+      if (k0) {
+        ra[u].y = 0.f;
+        rb[u].y = 0.f;
+      }
+    }
+  };
+  float ssum = 0.f;
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int col = 2 * (ib + 4 * u);
+      if (do_sum) ssum += ra[u].x;
+      if constexpr (PREC == 0) {
+        S.As[col][q] = ra[u].x;
+        S.As[col + 1][q] = ra[u].y;
+        if (!diag) {
+          S.Bs[col][q] = rb[u].x;
+          S.Bs[col + 1][q] = rb[u].y;
+        }
+      } else {
+        unsigned short h0, l0, h1, l1;
+        split_bf16(ra[u].x, h0, l0);
+        split_bf16(ra[u].y, h1, l1);
+        *(unsigned*)&S.Ah[q][col] = (unsigned)h0 | ((unsigned)h1 << 16);
+        *(unsigned*)&S.Al[q][col] = (unsigned)l0 | ((unsigned)l1 << 16);
+        if (!diag) {
+          split_bf16(rb[u].x, h0, l0);
+          split_bf16(rb[u].y, h1, l1);
+          *(unsigned*)&S.Bh[q][col] = (unsigned)h0 | ((unsigned)h1 << 16);
+          *(unsigned*)&S.Bl[q][col] = (unsigned)l0 | ((unsigned)l1 << 16);
+        }
+      }
+    }
+  };
   f32x16 acc = {};
   double dacc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) dacc[i] = 0.0;
-  float ssum = 0.f;
   double dsum = 0.0;
   int since_flush = 0;
-  for (long long c0 = 0; c0 < ncol; c0 += bk) {
-    // X[q][col] = coeffs[col/2][off + q][col%2]; the k = 0 imaginary parts are masked
-    for (int i = tid; i < BM * bk; i += 256) {
-      int il = i / (2 * BM), rem = i - il * 2 * BM, m = rem >> 1, ri = rem & 1;
-      int kk = 2 * il + ri;
-      long long col = c0 + kk;
-      bool okc = col < ncol && !(k == 0 && ri);
-      size_t base = (size_t)(col >> 1) * 2 * p_half + 2 * (size_t)off + ri;
-      float xa = (okc && m0 + m < pk) ? coeffs[base + 2 * (size_t)(m0 + m)] : 0.f;
-      float xb = (okc && n0 + m < pk) ? coeffs[base + 2 * (size_t)(n0 + m)] : 0.f;
-      if (PREC) {
-        unsigned short h, l;
-        split_bf16(xa, h, l);
-        Ah[m][kk] = h;
-        Al[m][kk] = l;
-        split_bf16(xb, h, l);
-        Bh[m][kk] = h;
-        Bl[m][kk] = l;
-        if (do_sum) As[kk][m] = xa;  // exact values for the k = 0 sums
-      } else {
-        As[kk][m] = xa;
-        Bs[kk][m] = xb;
-      }
+  gload(i0);
+  for (long long c0 = i0; c0 < i1; c0 += COV_IMG) {
+    lstore();
+    __syncthreads();
+    if (c0 + COV_IMG < i1) gload(c0 + COV_IMG);
+    if constexpr (PREC == 0) {
+      mma_f32_k32(S.As, diag ? S.As : S.Bs, acc, wm, wn, lane);
+    } else {
+      if (diag)
+        mma_bf16x3(S.Ah, S.Al, S.Ah, S.Al, acc, wm, wn, lane);
+      else
+        mma_bf16x3(S.Ah, S.Al, S.Bh, S.Bl, acc, wm, wn, lane);
     }
     __syncthreads();
-    if (PREC)
-      mma_bf16x3(Ah, Al, Bh, Bl, acc, wm, wn, lane);
-    else
-      mma_f32(As, Bs, acc, wm, wn, lane);
-    if (do_sum && tid < BM) {
-      for (int kk = 0; kk < bk; kk += 2) ssum += As[kk][tid];
-    }
-    __syncthreads();
-    since_flush += bk;
+    since_flush += COV_K;
     if (since_flush >= COV_FLUSH_COLS) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -348,16 +408,38 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
 #pragma unroll
   for (int i = 0; i < 16; ++i) dacc[i] += (double)acc[i];
   dsum += (double)ssum;
-  double* gk = G + cov_off[k];
+  double* gk = partG + (size_t)slice * cov_size + cov_off[k];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    int q = m0 + wm * 32 + acc_row(i, lane), q2 = n0 + wn * 32 + (lane & 31);
-    if (q < pk && q2 < pk) {
-      gk[(size_t)q * pk + q2] += dacc[i];
-      if (m0 != n0) gk[(size_t)q2 * pk + q] += dacc[i];
+    int r = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
+    if (r < pk && c < pk) {
+      gk[(size_t)r * pk + c] = dacc[i];
+      if (!diag) gk[(size_t)c * pk + r] = dacc[i];
     }
   }
-  if (do_sum && tid < BM && m0 + tid < pk) S0[m0 + tid] += dsum;
+  if (do_sum) {
+    // the four loader threads of row q hold FP64 sums of disjoint images
+    dred[ib][q] = dsum;
+    __syncthreads();
+    if (tid < BM && m0 + tid < pk)
+      partS0[(size_t)slice * p0 + m0 + tid] = ((dred[0][tid] + dred[1][tid]) + dred[2][tid]) + dred[3][tid];
+  }
+}
+
+// G[i] += sum over slices s = 0..S-1 (in that order) of partG[s][i]; the same for S0.
+__global__ void k_cov_reduce(const double* __restrict__ partG, const double* __restrict__ partS0, int S,
+                             long long cov_size, int p0, double* __restrict__ G, double* __restrict__ S0) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cov_size) {
+    double t = 0.0;
+    for (int s = 0; s < S; ++s) t += partG[(size_t)s * cov_size + i];
+    G[i] += t;
+  } else if (i < cov_size + p0) {
+    const int m = (int)(i - cov_size);
+    double t = 0.0;
+    for (int s = 0; s < S; ++s) t += partS0[(size_t)s * p0 + m];
+    S0[m] += t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -387,16 +469,38 @@ hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D,
   return hipGetLastError();
 }
 
+CovSplit cov_split(const Plan& pl, long long n) {
+  CovSplit sp{};
+  if (n <= 0) return sp;
+  long long S = std::min<long long>(kCovMaxSlices, std::max<long long>(1, (n + kCovSliceImages - 1) / kCovSliceImages));
+  long long per = (n + S - 1) / S;
+  per = (per + COV_IMG - 1) / COV_IMG * COV_IMG;
+  sp.per = per;
+  sp.slices = (int)((n + per - 1) / per);
+  sp.bytes_g = (size_t)sp.slices * pl.cov_size * sizeof(double);
+  sp.bytes = sp.bytes_g + (size_t)sp.slices * pl.p0 * sizeof(double);
+  return sp;
+}
+
 hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
-                             hipStream_t st) {
-  dim3 g((unsigned)pl.items_cov.size());
+                             void* ws, hipStream_t st) {
+  const CovSplit sp = cov_split(pl, n);
+  const int nitems = (int)pl.items_cov.size();
+  double* partG = (double*)ws;
+  double* partS0 = (double*)((char*)ws + sp.bytes_g);
+  dim3 g((unsigned)(nitems * sp.slices));
   pl.prof.begin(ST_COVARIANCE, st);
   if (precision == FB_BF16X3)
-    hipLaunchKernelGGL(k_covariance<1>, g, dim3(256), 0, st, coeffs, G, S0, pl.d_items_cov, pl.d_coef_off,
-                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+    hipLaunchKernelGGL(k_covariance<1>, g, dim3(256), 0, st, coeffs, partG, partS0, pl.d_items_cov, pl.d_coef_off,
+                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, (long long)pl.cov_size,
+                       pl.p0);
   else
-    hipLaunchKernelGGL(k_covariance<0>, g, dim3(256), 0, st, coeffs, G, S0, pl.d_items_cov, pl.d_coef_off,
-                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+    hipLaunchKernelGGL(k_covariance<0>, g, dim3(256), 0, st, coeffs, partG, partS0, pl.d_items_cov, pl.d_coef_off,
+                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, (long long)pl.cov_size,
+                       pl.p0);
+  const long long tot = (long long)pl.cov_size + pl.p0;
+  hipLaunchKernelGGL(k_cov_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partG, partS0, sp.slices,
+                     (long long)pl.cov_size, pl.p0, G, S0);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -28,9 +28,20 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
 hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
                                 float* images, hipStream_t st);
 
-// Eqs.(ck),(ck_0) accumulation and the k = 0 sums.
+// Eqs.(ck),(ck_0) accumulation and the k = 0 sums.  The images are split into
+// `slices` runs of `per` images; each run's FP64 partial G (and S0) goes to the
+// workspace and the runs are then added into G in order.
+constexpr int kCovMaxSlices = 16;
+constexpr int kCovSliceImages = 4096;  // images per slice at least, until kCovMaxSlices
+struct CovSplit {
+  long long per = 0;
+  int slices = 0;
+  size_t bytes_g = 0;  // slices * cov_size doubles
+  size_t bytes = 0;    // + slices * p0 doubles
+};
+CovSplit cov_split(const Plan& pl, long long n);
 hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
-                             hipStream_t st);
+                             void* ws, hipStream_t st);
 
 // Algorithm 2, steps 1 and 4 (FP64).
 hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,

@@ -13,22 +13,11 @@
 
 #include <algorithm>
 
+#include "dev_common.h"
 #include "fft_dev.h"
 #include "kernels.h"
 
 namespace fb {
-
-__device__ __forceinline__ float es_eval(float z, float beta) {
-  float t = 1.0f - z * z;
-  return t > 0.f ? __expf(beta * (sqrtf(t) - 1.0f)) : 0.f;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
-// Remap the linear block id so that each XCD walks one contiguous range of work.
-__device__ __forceinline__ int xcd_remap(int lin, int total) {
-  if (total % 8) return lin;
-  return (lin % 8) * (total / 8) + lin / 8;
-}
 
 // Copy `total` elements with every thread issuing U global loads before it stores
 // any of them, so that the loads of one thread are in flight together.
@@ -170,8 +159,9 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
 // forward gather: G [M2][N][n] -> P [n_xi * H][n]
 // block = (work item: one grid cell and up to kGatherChunk of its nodes, group of IG images).
 // The cell's (CS + W - 1)^2 box of grid points is staged in LDS for the IG images (each
-// point's IG values are one contiguous 8*IG-byte run in G), then every (node, image)
-// lane interpolates its W x W taps from LDS with the node's precomputed weights.
+// point's IG values are one contiguous 8*IG-byte run in G), then every (node, image pair)
+// lane interpolates its W x W taps from LDS with the node's precomputed weights.  Items
+// hold up to kGatherChunk nodes, so the box fill is paid once for many nodes.
 // ---------------------------------------------------------------------------
 template <int W, int CS, int IG, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P,
@@ -184,7 +174,6 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   constexpr int PER = (NV4 + NT - 1) / NT;  // float4 loads per thread
   extern __shared__ float4 lds4[];
   float2* box = (float2*)lds4;                               // [NPT][IG]
-  GatherNode* nodes = (GatherNode*)(lds4 + NV4);             // [kGatherChunk]
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   // cells vary fastest inside one image group: an XCD then walks neighbouring cells,
   // whose boxes overlap by the halo, while those rows are still in its L2
@@ -223,12 +212,6 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
       box[i] = v;
     }
   }
-  {
-    const int* src = (const int*)(gn + it.s0);
-    int* dst = (int*)nodes;
-    constexpr int WPN = sizeof(GatherNode) / 4;
-    for (int i = threadIdx.x; i < nn * WPN; i += blockDim.x) dst[i] = src[i];
-  }
   __syncthreads();
   // each lane interpolates one node for two consecutive images (16-byte LDS reads)
   constexpr int IP = IG / 2;
@@ -238,8 +221,26 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   const int img = i0 + 2 * ip;
   const bool pair_ok = img + 1 < nimg && (nimg & 1) == 0;
   const float4* box4 = (const float4*)box;
+  // node records come straight from global memory (the eight lanes of one node share
+  // each 64-byte line); the next record is in flight while the current node is summed
+  union NodeRegs {
+    float4 v[4];
+    GatherNode g;
+  };
+  static_assert(sizeof(GatherNode) == 4 * sizeof(float4), "node record is four 16-byte words");
+  const float4* gn4 = (const float4*)(gn + it.s0);
+  NodeRegs nxt_nd;
+  if (slot < nn) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nxt_nd.v[q] = gn4[slot * 4 + q];
+  }
   for (int s = slot; s < nn; s += SLOTS) {
-    const GatherNode& nd = nodes[s];
+    NodeRegs cur_nd = nxt_nd;
+    if (s + SLOTS < nn) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nxt_nd.v[q] = gn4[(s + SLOTS) * 4 + q];
+    }
+    const GatherNode& nd = cur_nd.g;
     const float4* b = box4 + (size_t)nd.off * IP + ip;
     float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
     // rows of W taps: the next row's loads are issued before this row's products
@@ -283,7 +284,7 @@ constexpr int kGatherImages = 16;   // images per gather workgroup: one 128-byte
 constexpr int kGatherThreads = 512;
 size_t gather_lds_bytes() {
   constexpr int BW = kGatherCell + kGatherW - 1;
-  return (size_t)BW * BW * kGatherImages * sizeof(float2) + kGatherChunk * sizeof(GatherNode);
+  return (size_t)BW * BW * kGatherImages * sizeof(float2);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,7 @@ struct NodeTap {
 // interpolates its nodes from there.
 constexpr int kGatherCell = 16;
 constexpr int kGatherW = 7;                       // kernel width the gather kernels are built for
-constexpr int kGatherChunk = 128;                 // nodes per work item at most
+constexpr int kGatherChunk = 1024;                // nodes per work item at most
 struct GatherNode {
   int n;                 // polar node j * H + l
   int off;               // tap origin inside the cell box: row * (cell + w - 1) + col

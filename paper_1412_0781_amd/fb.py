@@ -158,8 +158,11 @@ class Plan:
         if state is None:
             state = self.new_covariance()
         cnt = ctypes.c_int64(state.count)
+        wsb = int(lib().fb_covariance_workspace_bytes(self._h, n))
+        ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=coeffs.device)
         check(lib().fb_covariance(self._h, coeffs.data_ptr(), n, state.G.data_ptr(), state.S0.data_ptr(),
-                                  ctypes.byref(cnt), _prec(precision), _stream_ptr(coeffs.device)), self._h)
+                                  ctypes.byref(cnt), _prec(precision), ws.data_ptr(), wsb,
+                                  _stream_ptr(coeffs.device)), self._h)
         state.count = int(cnt.value)
         return state
 
