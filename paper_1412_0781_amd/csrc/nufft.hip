@@ -516,7 +516,7 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
 // (count * S complex values), the ping-pong forms two; either stays within
 // kLdsBudget bytes so that two workgroups share one CU's 160 KiB of LDS.
 constexpr int kLdsBudget = 72 * 1024;
-constexpr int kFftThreads = 512;
+constexpr int kFftThreads = 1024;
 constexpr int kMaxTransforms = 16;
 struct FftLaunch {
   int count;
