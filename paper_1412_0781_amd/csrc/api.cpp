@@ -25,6 +25,10 @@ int64_t split_workspace(const fb::PassLayout& lay, void* ws, size_t ws_bytes, in
   size_t avail = ws_bytes - skip - kAlign;
   int64_t nb = std::min<int64_t>({n, (int64_t)(avail / lay.per_image), kMaxPassImages});
   if (nb < 1) return 0;
+  // The pass buffers keep images innermost with a row stride of nb images.  A stride
+  // that is a multiple of 2 KiB puts every row of a workgroup's tile on the same HBM
+  // channels; 16 images fewer (still a whole 128-byte line) spreads them.
+  if (nb >= 512 && nb % 256 == 0) nb -= 16;
   *a = (float2*)base;
   size_t off_b = (lay.bytes_a * (size_t)nb + kAlign - 1) & ~(kAlign - 1);
   *b = (float2*)(base + off_b);

@@ -211,7 +211,9 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
   const int nb = n / R;
   const int total = count * nb;
   const int twstep = n / (Ns * R);
-  float2 v[BM][R];
+  // the butterfly inputs and their twiddles are both loaded before the barrier, so the
+  // twiddle-table latency overlaps the wait for the other waves
+  float2 v[BM][R], w[BM][R];
 #pragma unroll
   for (int b = 0; b < BM; ++b) {
     int idx = tid + b * nthr;
@@ -220,6 +222,9 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       const float2* src = buf + t * stride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
+      int k = j - dns.div(j) * Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[b][r] = tw[k * r * twstep];
     }
   }
   __syncthreads();
@@ -229,10 +234,8 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
     if (idx < total) {
       int t = dnb.div(idx), j = idx - t * nb;
       int k = j - dns.div(j) * Ns;
-      if (k) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[k * r * twstep]);
-      }
+      for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);  // tw[0] = 1 when k = 0
       Dft<R>::run(v[b], tw, n, R);
       float2* dst = buf + t * stride;
       int base = (j - k) * R + k;
@@ -243,7 +246,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
   __syncthreads();
 }
 
-constexpr int kFftVmax = 16;
+constexpr int kFftVmax = 8;  // values per thread: one radix-8 butterfly or two radix-4
 
 // Largest count * n the in-place FFT can take with nthr threads (0 if a radix is unsupported).
 inline int fft_inplace_capacity(const FftDesc& d, int nthr) {
