@@ -110,9 +110,10 @@ int fb_plan_tables(fb_plan_t plan, int32_t* k, int32_t* q, int32_t* p, int64_t* 
  *   radial  [p_half * n_xi]  row (k,q): N_{k,q} J_k(R_{k,q} xi_j / c) xi_j w_j (Eq.(a)) */
 int fb_plan_host_tables(fb_plan_t plan, double* roots, double* norms, double* xi, double* w, double* radial);
 
-/* Workspace bytes that make fb_expand / fb_adjoint process `batch` images per
- * internal pass (any workspace of at least fb_workspace_bytes(plan, 1, ...) works;
- * larger ones let the library use larger passes). */
+/* Workspace bytes that make fb_expand / fb_adjoint process up to `batch` images
+ * per internal pass (any workspace of at least fb_workspace_bytes(plan, 1, ...)
+ * works; larger ones let the library use larger passes).  Pass buffers hold
+ * images in groups of 16, so the size is that of ceil(batch / 16) * 16 images. */
 size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision);
 
 /* a = T* I (Algorithm 1, steps 3-4) for n images.  images and coeffs as in

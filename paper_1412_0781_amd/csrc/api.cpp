@@ -17,20 +17,24 @@ namespace {
 constexpr int64_t kMaxPassImages = 16384;  // gridDim.y of the per-image kernels stays far below 65535
 constexpr size_t kAlign = 256;             // both pass buffers start on 256-byte boundaries
 
-// Images per pass that fit the workspace, and the two pass buffers inside it.
+int64_t round_group(int64_t m) { return (m + fb::kImgGroup - 1) / fb::kImgGroup * fb::kImgGroup; }
+
+// Images per pass that fit the workspace, and the two pass buffers inside it.  A pass
+// of nb images uses round_group(nb) image slots in each buffer.
 int64_t split_workspace(const fb::PassLayout& lay, void* ws, size_t ws_bytes, int64_t n, float2** a, float2** b) {
   uintptr_t base = ((uintptr_t)ws + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
   size_t skip = base - (uintptr_t)ws;
   if (ws_bytes < skip + kAlign) return 0;
   size_t avail = ws_bytes - skip - kAlign;
-  int64_t nb = std::min<int64_t>({n, (int64_t)(avail / lay.per_image), kMaxPassImages});
+  int64_t slots = (int64_t)(avail / lay.per_image) / fb::kImgGroup * fb::kImgGroup;
+  int64_t nb = std::min<int64_t>({n, slots, kMaxPassImages});
   if (nb < 1) return 0;
   // The pass buffers keep images innermost with a row stride of nb images.  A stride
   // that is a multiple of 2 KiB puts every row of a workgroup's tile on the same HBM
   // channels; 16 images fewer (still a whole 128-byte line) spreads them.
   if (nb >= 512 && nb % 256 == 0) nb -= 16;
   *a = (float2*)base;
-  size_t off_b = (lay.bytes_a * (size_t)nb + kAlign - 1) & ~(kAlign - 1);
+  size_t off_b = (lay.bytes_a * (size_t)round_group(nb) + kAlign - 1) & ~(kAlign - 1);
   *b = (float2*)(base + off_b);
   return nb;
 }
@@ -124,7 +128,7 @@ int fb_plan_host_tables(fb_plan_t plan, double* roots, double* norms, double* xi
 size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision) {
   (void)precision;
   if (!plan || batch < 1) return 0;
-  return fb::pass_layout(plan->pl).per_image * (size_t)std::min<int64_t>(batch, kMaxPassImages) + kAlign;
+  return fb::pass_layout(plan->pl).per_image * (size_t)round_group(std::min<int64_t>(batch, kMaxPassImages)) + kAlign;
 }
 
 int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision, void* ws,

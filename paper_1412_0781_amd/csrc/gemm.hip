@@ -66,7 +66,9 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 
 // ---------------------------------------------------------------------------
 // radial quadrature.  grid: (column tiles of 64 = 32 images, work items (k, 128-row tile))
-// Fh: float [K+1][n_xi][ncol], ncol = 2 * images (re, im interleaved)
+// Fh: complex [K+1][group][n_xi][16] (images in groups of 16); as a real matrix per k,
+// column 2 i + r (r = re, im) of row j sits at float ((group * n_xi + j) * 32 + (2 i + r) % 32).
+// ncol = 2 * images.
 // coeffs: float [image][p_half][2]
 // A wave owns 32 rows x 64 columns (two 32x32 MFMA tiles).  The next K chunk is
 // loaded into registers while the current one is multiplied from LDS; the output
@@ -104,8 +106,9 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
   const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
   const int n0 = blockIdx.x * RBN;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
-  const float* fk = Fh + (size_t)k * n_xi * ncol;
-  const bool vec = ((n_xi & 3) == 0) && ((ncol & 3) == 0);
+  const int ngrp = (ncol / 2 + kImgGroup - 1) / kImgGroup;
+  const float* fk = Fh + (size_t)k * ngrp * n_xi * (2 * kImgGroup);
+  const bool vec = (n_xi & 3) == 0;
   float4 ra[4], rb[2];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -125,9 +128,9 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
 #pragma unroll
     for (int u = 0; u < 2; ++u) {  // B: 32 k x 64 columns, four consecutive columns per thread
       int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
-      int kc = k0 + kk, col = n0 + nq;
-      const float* src = fk + (size_t)kc * ncol + col;
-      if (kc < n_xi && vec && col + 3 < ncol) {
+      int kc = k0 + kk, col = n0 + nq;  // col % 4 == 0: the four columns share one group
+      const float* src = fk + ((size_t)(col / (2 * kImgGroup)) * n_xi + kc) * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
+      if (kc < n_xi && col + 3 < ncol) {
         rb[u] = *(const float4*)src;
       } else {
         float t[4];

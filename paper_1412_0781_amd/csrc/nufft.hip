@@ -118,12 +118,13 @@ __global__ void k_fwd_rows(const float* __restrict__ img, float2* __restrict__ g
 }
 
 // ---------------------------------------------------------------------------
-// forward cols: G1 [n][M2][L] -> G [M2][N][n]   (image index innermost)
-// block: one stored row m2 for CI consecutive images; LDS transforms padded to N+1
+// forward cols: G1 [n][M2][L] -> G [M2][group][N][kImgGroup]   (images innermost, grouped)
+// block: one stored row m2 for CI (<= kImgGroup) consecutive image slots; LDS
+// transforms padded to N+1.  Slots past nimg are written as zeros.
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g, FftDesc fd,
-                           const float2* __restrict__ tw, int L, int M2, int nimg, int CI, FastDiv dL) {
+                           const float2* __restrict__ tw, int L, int M2, int nimg, int ngrp, int CI, FastDiv dL) {
   extern __shared__ float2 sm[];
   const int N = fd.n, S = N + 1;
   float2* buf = sm;
@@ -131,7 +132,8 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int m2 = lin / gridDim.x;             // image groups vary fastest: neighbours share lines
   const int i0 = (lin - m2 * gridDim.x) * CI;
-  const int ni = min(CI, nimg - i0);
+  const int ni = max(0, min(CI, nimg - i0));           // images with data
+  const int nw = min(CI, ngrp * kImgGroup - i0);       // slots written
   const int x0 = -((L - 1 + 1) / 2);
   for (int i = threadIdx.x; i < CI * S; i += blockDim.x) buf[i] = make_float2(0.f, 0.f);
   __syncthreads();
@@ -149,14 +151,18 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
       });
   __syncthreads();
   float2* res = run_fft<FORM>(buf, tmp, ni, S, fd, tw);
-  float2* dst = g + (size_t)m2 * N * nimg + i0;
-  const int c = threadIdx.x & 15;  // CI <= 16 images in the workgroup
-  if (c < ni)
-    for (int m1 = threadIdx.x >> 4; m1 < N; m1 += blockDim.x >> 4) dst[(size_t)m1 * nimg + c] = res[c * S + m1];
+  const int c = threadIdx.x & (kImgGroup - 1);  // CI <= kImgGroup slots in the workgroup
+  if (c < nw) {
+    const int i = i0 + c;
+    float2* dst = g + ((size_t)m2 * ngrp + (i / kImgGroup)) * N * kImgGroup + (i & (kImgGroup - 1));
+    const bool live = c < ni;
+    for (int m1 = threadIdx.x / kImgGroup; m1 < N; m1 += blockDim.x / kImgGroup)
+      dst[(size_t)m1 * kImgGroup] = live ? res[c * S + m1] : make_float2(0.f, 0.f);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// forward gather: G [M2][N][n] -> P [n_xi * H][n]
+// forward gather: G [M2][group][N][16] -> P [n_xi][group][H][16]
 // block = (work item: one grid cell and up to kGatherChunk of its nodes, group of IG images).
 // The cell's (CS + W - 1)^2 box of grid points is staged in LDS for the IG images (each
 // point's IG values are one contiguous 8*IG-byte run in G), then every (node, image pair)
@@ -167,7 +173,8 @@ template <int W, int CS, int IG, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g, float2* __restrict__ P,
                                                     const GatherItem* __restrict__ items,
                                                     const GatherNode* __restrict__ gn, int nitems, int N,
-                                                    int M2, int nimg) {
+                                                    int M2, int H, int ngrp) {
+  static_assert(IG == kImgGroup, "a gather workgroup takes one image group");
   constexpr int BW = CS + W - 1;
   constexpr int NPT = BW * BW;            // grid points in the box
   constexpr int NV4 = NPT * IG / 2;       // float4 = two images of one point
@@ -178,11 +185,14 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   // cells vary fastest inside one image group: an XCD then walks neighbouring cells,
   // whose boxes overlap by the halo, while those rows are still in its L2
   const int itx = lin % nitems;
-  const int i0 = (lin / nitems) * IG;
+  const int grp = lin / nitems;
   const GatherItem it = items[itx];
   const int nn = it.s1 - it.s0;
-  if (i0 + IG <= nimg && (nimg & 1) == 0) {
-    // full group, 16-byte aligned: issue every load of this thread before the LDS stores
+  {
+    // every group is whole (padded): issue every load of this thread before the LDS stores;
+    // a box row of one group is one contiguous run of BW * IG values in G
+    const float2* gg = g + (size_t)grp * N * IG;
+    const size_t row_stride = (size_t)ngrp * N * IG;
     float4 v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -193,23 +203,13 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
         int r = pt / BW, cc = pt - r * BW;
         int row = it.c2 + r, col = it.c1 + cc;
         col = col >= N ? col - N : col;
-        if (row < M2) v[u] = *(const float4*)(g + ((size_t)row * N + col) * nimg + i0 + 2 * h);
+        if (row < M2) v[u] = *(const float4*)(gg + row * row_stride + (size_t)col * IG + 2 * h);
       }
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       int i = threadIdx.x + u * NT;
       if (i < NV4) lds4[i] = v[u];
-    }
-  } else {
-    for (int i = threadIdx.x; i < NPT * IG; i += blockDim.x) {
-      int pt = i / IG, im = i - pt * IG;
-      int r = pt / BW, cc = pt - r * BW;
-      int row = it.c2 + r, col = it.c1 + cc;
-      col = col >= N ? col - N : col;
-      float2 v = make_float2(0.f, 0.f);
-      if (row < M2 && i0 + im < nimg) v = g[((size_t)row * N + col) * nimg + i0 + im];
-      box[i] = v;
     }
   }
   __syncthreads();
@@ -218,8 +218,6 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   const int ip = threadIdx.x % IP;
   const int slot = threadIdx.x / IP;
   constexpr int SLOTS = NT / IP;
-  const int img = i0 + 2 * ip;
-  const bool pair_ok = img + 1 < nimg && (nimg & 1) == 0;
   const float4* box4 = (const float4*)box;
   // node records come straight from global memory (the eight lanes of one node share
   // each 64-byte line); the next record is in flight while the current node is summed
@@ -270,17 +268,12 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
         for (int a = 0; a < W; ++a) cur[a] = nxt[a];
       }
     }
-    float2* dst = P + (size_t)nd.n * nimg + img;
-    if (pair_ok) {
-      *(float4*)dst = make_float4(ax0, ay0, ax1, ay1);
-    } else {
-      if (img < nimg) dst[0] = make_float2(ax0, ay0);
-      if (img + 1 < nimg) dst[1] = make_float2(ax1, ay1);
-    }
+    float2* dst = P + (((size_t)nd.j * ngrp + grp) * H + nd.l) * IG + 2 * ip;
+    *(float4*)dst = make_float4(ax0, ay0, ax1, ay1);
   }
 }
 
-constexpr int kGatherImages = 16;   // images per gather workgroup: one 128-byte line per grid point
+constexpr int kGatherImages = kImgGroup;  // one image group per gather workgroup
 constexpr int kGatherThreads = 512;
 size_t gather_lds_bytes() {
   constexpr int BW = kGatherCell + kGatherW - 1;
@@ -288,13 +281,13 @@ size_t gather_lds_bytes() {
 }
 
 // ---------------------------------------------------------------------------
-// forward angular: P [n_xi][H][n] -> Fh [K+1][n_xi][n] (complex; ncol = 2 n floats per row)
-// block: ring j for AG consecutive images; LDS transforms padded to H+1
+// forward angular: P [n_xi][group][H][16] -> Fh [K+1][group][n_xi][16] (complex)
+// block: ring j for AG (<= kImgGroup) consecutive image slots; LDS transforms padded to H+1
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__ Fh, FftDesc fd,
                               const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
-                              int nimg, int AG, float scale) {
+                              int ngrp, int AG, float scale) {
   extern __shared__ float2 sm[];
   const int H = fd.n, S = H + 1;
   float2* buf = sm;
@@ -302,15 +295,20 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int j = lin / gridDim.x;              // image groups vary fastest: neighbours share lines
   const int g0 = (lin - j * gridDim.x) * AG;
-  const int ng = min(AG, nimg - g0);
-  const float2* ring = P + (size_t)j * H * nimg + g0;
+  const int ng = min(AG, ngrp * kImgGroup - g0);
+  // image slot g0 + gg of ring j: group (g0 + gg) / 16, lane (g0 + gg) % 16
+  auto slot_base = [&](int outer, int inner, int gg) -> size_t {
+    const int i = g0 + gg;
+    return (((size_t)outer * ngrp + i / kImgGroup) * inner) * kImgGroup + (i & (kImgGroup - 1));
+  };
   // packed z_m = s_{2m} + i s_{2m+1}, with s_t = u_t + v_t (t < H), u_{t-H} - v_{t-H} (t >= H)
   batched_copy2d<8, 16>(
       H, ng,
       [&](int m, int gg) -> float4 {
         int t0 = 2 * m, t1 = 2 * m + 1;
-        float2 f0 = ring[(size_t)(t0 < H ? t0 : t0 - H) * nimg + gg];
-        float2 f1 = ring[(size_t)(t1 < H ? t1 : t1 - H) * nimg + gg];
+        const float2* ring = P + slot_base(j, H, gg);
+        float2 f0 = ring[(size_t)(t0 < H ? t0 : t0 - H) * kImgGroup];
+        float2 f1 = ring[(size_t)(t1 < H ? t1 : t1 - H) * kImgGroup];
         return make_float4(f0.x, f0.y, f1.x, f1.y);
       },
       [&](int m, int gg, float4 f) {
@@ -331,7 +329,7 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
     float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
     float2 Sk = cadd(e, cmul(angtw[k], o));
     float2 F = (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale);
-    Fh[((size_t)k * n_xi + j) * nimg + g0 + gg] = F;
+    Fh[slot_base(k, n_xi, gg) + (size_t)j * kImgGroup] = F;
   }
 }
 
@@ -518,6 +516,7 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
 constexpr int kLdsBudget = 72 * 1024;
 constexpr int kFftThreads = 1024;
 constexpr int kMaxTransforms = 16;
+static_assert(kMaxTransforms <= kImgGroup, "an FFT workgroup's image slots map to lanes of one group");
 struct FftLaunch {
   int count;
   int form;
@@ -574,30 +573,32 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,
                 pl.d_tw, L, pl.M2, pl.hw, fr.count, make_fastdiv(L));
   pl.prof.end(st);
+  const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
   FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
-  dim3 g2((unsigned)((nimg + fc.count - 1) / fc.count), (unsigned)pl.M2);
+  dim3 g2((unsigned)((ngrp * kImgGroup + fc.count - 1) / fc.count), (unsigned)pl.M2);
   pl.prof.begin(ST_FWD_COLS, st);
   FB_LAUNCH_FFT(k_fwd_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufA, bufB, pl.fft_grid, pl.d_tw, L,
-                pl.M2, nimg, fc.count, make_fastdiv(L));
+                pl.M2, nimg, ngrp, fc.count, make_fastdiv(L));
   pl.prof.end(st);
   constexpr int IG = kGatherImages;
   const int nitems = (int)pl.gitems.size();
-  dim3 g3((unsigned)nitems, (unsigned)((nimg + IG - 1) / IG));
+  dim3 g3((unsigned)nitems, (unsigned)ngrp);
   pl.prof.begin(ST_FWD_GATHER, st);
   hipLaunchKernelGGL((k_fwd_gather<kGatherW, kGatherCell, IG, kGatherThreads>), g3, dim3(kGatherThreads),
                      gather_lds_bytes(), st, bufB, bufA,
-                     pl.d_gitems, pl.d_gnodes, nitems, N, pl.M2, nimg);
+                     pl.d_gitems, pl.d_gnodes, nitems, N, pl.M2, pl.H, ngrp);
   pl.prof.end(st);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
+  const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
   FftLaunch fa = fft_launch(pl.fft_ang, pl.H + 1);
-  dim3 g((unsigned)((nimg + fa.count - 1) / fa.count), (unsigned)pl.n_xi);
+  dim3 g((unsigned)((ngrp * kImgGroup + fa.count - 1) / fa.count), (unsigned)pl.n_xi);
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_FWD_ANGULAR, st);
   FB_LAUNCH_FFT(k_fwd_angular, fa.form, g, dim3(kFftThreads), fa.lds, st, P, Fh, pl.fft_ang, pl.d_tw, pl.d_angtw,
-                pl.n_xi, pl.k_max, nimg, fa.count, scale);
+                pl.n_xi, pl.k_max, ngrp, fa.count, scale);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -143,6 +143,7 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
   for (int a = 0; a < L; ++a) pl.deconv[a] = 1.0 / es_kernel_ft((double)(x0 + a) / pl.N, pl.w, pl.beta);
 
   // polar half-ring nodes theta_l = 2 pi l / n_theta, l < n_theta / 2
+  if (pl.n_xi > 65535 || pl.H > 65535) return FB_ERR_UNSUPPORTED;  // node records hold 16-bit j, l
   pl.nodes.resize((size_t)pl.n_xi * pl.H);
   for (int j = 0; j < pl.n_xi; ++j)
     for (int l = 0; l < pl.H; ++l) {
@@ -187,7 +188,8 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
             double b1 = std::ceil(t1 - pl.w / 2.0), b2 = std::ceil(t2 - pl.w / 2.0);
             const NodeTap& t = pl.nodes[n];
             GatherNode g;
-            g.n = n;
+            g.j = (unsigned short)j;
+            g.l = (unsigned short)l;
             g.off = (t.b2 - cy * CS) * BW + (t.b1 - cx * CS);
             for (int a2 = 0; a2 < pl.w; ++a2) {
               g.w1[a2] = (float)es_kernel(2.0 * (t1 - (b1 + a2)) / pl.w, pl.beta);

@@ -63,10 +63,15 @@ struct NodeTap {
 // (kGatherCell + w - 1)^2 grid points (for a group of images) in LDS and
 // interpolates its nodes from there.
 constexpr int kGatherCell = 16;
+// Pass buffers that keep images innermost store them in groups of kImgGroup:
+// X[outer][group][inner][kImgGroup], a pass of m images using ceil(m / kImgGroup)
+// groups (the slots past m hold zeros).  One group of one (outer, inner) entry is a
+// 128-byte line, and a workgroup's tile of one group is one contiguous run.
+constexpr int kImgGroup = 16;
 constexpr int kGatherW = 7;                       // kernel width the gather kernels are built for
 constexpr int kGatherChunk = 1024;                // nodes per work item at most
 struct GatherNode {
-  int n;                 // polar node j * H + l
+  unsigned short j, l;   // polar node: ring j, angle l (< H)
   int off;               // tap origin inside the cell box: row * (cell + w - 1) + col
   float w1[kGatherW];    // weights along the first grid axis (i1 / x)
   float w2[kGatherW];    // weights along the second grid axis (i2 / y)

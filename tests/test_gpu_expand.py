@@ -66,12 +66,12 @@ def test_expand_L256(precision):
 
 
 def test_multi_pass_matches_single_pass():
-    # a workspace for 3 images forces passes of 3, 3, 3, 1
+    # a workspace for 16 images (one image group) forces passes of 16, 16, 8
     L = 32
     po = oracle.plan(L, 0.5, 16)
-    img = torch.tensor(structured_images(po, 10, seed=3), device="cuda")
+    img = torch.tensor(structured_images(po, 40, seed=3), device="cuda")
     plan = Plan(L, 0.5, 16)
-    a1 = plan.expand(img, batch=3).clone()
+    a1 = plan.expand(img, batch=16).clone()
     a2 = plan.expand(img, batch=64)
     torch.cuda.synchronize()
     assert torch.equal(a1, a2)
