@@ -31,6 +31,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "images/s (FB coeffs + covariance) at L=256, BF16x3 vs FP32, ≤1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA on the vector ALUs without packed (two-wide) FP32 instructions, which this
+# library does not emit: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.  (The
+# published 157.3 TFLOP/s counts the packed FMA.)
+ALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_FP32_PUBLISHED_TFLOPS = 157.3
+PROFILES = os.path.join(ROOT, "profiles")
+# sources whose change invalidates stored HBM counter readings of the forward kernels
+KERNEL_SOURCES = ["paper_1412_0781_amd/csrc/" + f for f in
+                  ("nufft.hip", "fft_dev.h", "dev_common.h", "plan.h", "plan.cpp", "gemm.hip", "api.cpp")]
 
 
 def log(msg):
@@ -56,6 +65,43 @@ def algorithmic_bytes_per_image(plan) -> dict:
         "radial_fwd": fh + co,
         "covariance": co,
     }
+
+
+def algorithmic_flops_per_image(plan) -> dict:
+    """Vector-ALU flops of the separable W x W interpolation (the gather): per polar node and
+    image, W rows of W complex-by-real products plus W row combinations, as FMAs."""
+    W = plan.kernel_w
+    return {"fwd_gather": plan.n_xi * (plan.n_theta // 2) * (2 * W * W + 2 * W) * 2}
+
+
+def source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic_per_image(stage: str, L: int):
+    """HBM bytes per image of `stage` from the committed counter summary (rocprofv3 FETCH_SIZE /
+    WRITE_SIZE, scaled by the plain-copy calibration), or None if the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(PROFILES, f"{stage}_hbm_counters_L{L}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_image"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_images(plan, n, seed, snr, chunk=4096):
@@ -233,11 +279,25 @@ def main():
         stages[name] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / max(cnt, 1)}
     dom = max((s for s in stages if s in bpi), key=lambda s: stages[s]["total_ms"])
     per_launch_images = args.n * args.steps / stages[dom]["launches"]
+    sec = stages[dom]["avg_ms"] * 1e-3
     alg_bytes = bpi[dom] * per_launch_images
-    achieved = alg_bytes / (stages[dom]["avg_ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": int(alg_bytes), "avg_launch_ms": round(stages[dom]["avg_ms"], 4)}
+    hbm_achieved = alg_bytes / sec / 1e9
+    fpi = algorithmic_flops_per_image(plan)
+    tpi = stored_traffic_per_image(dom, L)
+    traffic = round(tpi * per_launch_images) if tpi is not None else None
+    flops = fpi.get(dom, 0) * per_launch_images
+    if flops / alg_bytes > (ALU_FP32_PEAK_TFLOPS * 1e12) / (HBM_PEAK_GBS * 1e9):
+        # arithmetic intensity above the ridge point: bound by the FP32 vector ALUs
+        ach = flops / sec / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": round(ALU_FP32_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(ach / ALU_FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "flops_per_launch": int(flops), "frac_of_published_fp32_peak": round(ach / ALU_FP32_PUBLISHED_TFLOPS, 4),
+                    "hbm_algorithmic_GBps": round(hbm_achieved, 1), "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roofline.update({"bytes_per_launch": int(alg_bytes), "images_per_launch": round(per_launch_images, 1),
+                     "avg_launch_ms": round(stages[dom]["avg_ms"], 4)})
 
     # accuracy on a host-generated sample, and the CPU oracle baseline
     accuracy = None
