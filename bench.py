@@ -105,31 +105,16 @@ def stored_traffic_per_image(stage: str, L: int):
 
 
 def make_images(plan, n, seed, snr, chunk=4096):
-    import numpy as np
     import torch
 
-    from paper_1412_0781_amd import synth
-    from paper_1412_0781_amd.fb import synth_normals
+    from paper_1412_0781_amd.workload import noise_sigma, synthetic_images
 
-    dev = plan.device
-    k = plan.k.astype(np.float64)
-    q = plan.q.astype(np.float64)
-    v = synth.coef_variance(k, q)
-    sc = np.zeros((plan.p_half, 2), np.float32)
-    sc[:, 0] = np.where(k == 0, np.sqrt(v), np.sqrt(v / 2))
-    sc[:, 1] = np.where(k == 0, 0.0, np.sqrt(v / 2))
-    scale = torch.tensor(sc, device=dev)
-    sigma = math.sqrt(synth.noise_sigma2(k, q, plan.L, snr))
-    images = torch.empty((n, plan.L, plan.L), dtype=torch.float32, device=dev)
+    images = torch.empty((n, plan.L, plan.L), dtype=torch.float32, device=plan.device)
     for s in range(0, n, chunk):
         m = min(chunk, n - s)
-        a = synth_normals(seed, synth.STREAM_COEF, s, m, 2 * plan.p_half, 1.0, dev).view(m, plan.p_half, 2)
-        a.mul_(scale)
-        plan.adjoint(a, out=images[s:s + m], batch=min(m, 2048))
-        images[s:s + m].add_(synth_normals(seed, synth.STREAM_NOISE, s, m, plan.L * plan.L, sigma, dev)
-                             .view(m, plan.L, plan.L))
+        synthetic_images(plan, s, m, seed, snr, out=images[s:s + m])
     torch.cuda.synchronize()
-    return images, sigma
+    return images, noise_sigma(plan, snr)
 
 
 def time_form(plan, images, coeffs, precision, steps, warmup, pass_images):

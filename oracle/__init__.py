@@ -34,9 +34,11 @@ from .fb import (  # noqa: F401
     pixel_coords,
     polar_nodes,
     nudft_polar,
+    nudft_polar_sparse,
     angular_dft,
     radial_quadrature,
     expand,
+    expand_sparse,
     expand_stages,
     mean_and_covariance,
     covariance_blocks,

@@ -174,6 +174,24 @@ def nudft_polar(images: np.ndarray, pl: Plan, node_block: int = 4096) -> np.ndar
     return out.reshape(n, pl.n_xi, pl.n_theta)
 
 
+def nudft_polar_sparse(pixels, pl: Plan) -> np.ndarray:
+    """Eq.(nufft) for images given by their nonzero pixels.
+
+    pixels: a list with one entry per image, each a tuple (r, c, v) of equal-length
+    arrays: array row index r (axis 0, i1), column index c (axis 1, i2) and value v.
+    Every other pixel is zero, so the double sum over the L x L grid reduces to the
+    sum over the listed pixels; it is evaluated term by term.  Returns complex128
+    [n, n_xi, n_theta] like nudft_polar.
+    """
+    x = pixel_coords(pl.L)
+    xi1, xi2 = polar_nodes(pl)
+    out = np.zeros((len(pixels), pl.n_xi, pl.n_theta), dtype=np.complex128)
+    for i, (r, c, v) in enumerate(pixels):
+        for rr, cc, vv in zip(np.asarray(r), np.asarray(c), np.asarray(v, dtype=np.float64)):
+            out[i] += vv * np.exp(-1j * TWO_PI * (xi1 * x[rr] + xi2 * x[cc]))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 1, step 4: Eq.(1DFFT) then Eq.(a)
 # ----------------------------------------------------------------------------
@@ -222,6 +240,14 @@ def expand(images: np.ndarray, pl: Plan, chunk: int = 64) -> np.ndarray:
     out = np.empty((images.shape[0], pl.p_half), dtype=np.complex128)
     for s in range(0, images.shape[0], chunk):
         out[s:s + chunk] = radial_quadrature(angular_dft(nudft_polar(images[s:s + chunk], pl), pl), pl)
+    return out
+
+
+def expand_sparse(pixels, pl: Plan) -> np.ndarray:
+    """a = T* I for images given by their nonzero pixels (see nudft_polar_sparse)."""
+    out = np.empty((len(pixels), pl.p_half), dtype=np.complex128)
+    for i in range(len(pixels)):
+        out[i:i + 1] = radial_quadrature(angular_dft(nudft_polar_sparse(pixels[i:i + 1], pl), pl), pl)
     return out
 
 

@@ -31,3 +31,19 @@ def rel_l2(x, ref):
 def as_complex(coeffs_t):
     c = coeffs_t.detach().cpu().numpy().astype(np.float64)
     return c[..., 0] + 1j * c[..., 1]
+
+
+def sparse_images(L, n, npix, seed):
+    """n images with npix nonzero pixels each (positions anywhere on the L x L grid,
+    values N(0,1) rounded to float32), as a dense float32 array and as the pixel lists
+    the oracle's sparse evaluation takes.  numpy's seeded generator; host only."""
+    rng = np.random.default_rng(seed)
+    dense = np.zeros((n, L, L), np.float32)
+    pix = []
+    for i in range(n):
+        flat = rng.choice(L * L, size=npix, replace=False)
+        r, c = flat // L, flat % L
+        v = rng.standard_normal(npix).astype(np.float32)
+        dense[i, r, c] = v
+        pix.append((r, c, v.astype(np.float64)))
+    return dense, pix

@@ -131,3 +131,38 @@ def test_stages_agree_with_expand():
     # real images: F on the opposite ray is the conjugate (Sec. II-B)
     h = pl.n_theta // 2
     assert np.max(np.abs(F[:, :, h:] - np.conj(F[:, :, :h]))) <= 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("L", [15, 24])
+def test_sparse_evaluation_matches_dense(L):
+    # the sparse form drops only zero terms of the Eq.(nufft) double sum
+    po = oracle.plan(L, 0.5, L / 2)
+    rng = np.random.default_rng(7)
+    dense = np.zeros((3, L, L))
+    pix = []
+    for i in range(3):
+        flat = rng.choice(L * L, size=6, replace=False)
+        r, c = flat // L, flat % L
+        v = rng.standard_normal(6)
+        dense[i, r, c] = v
+        pix.append((r, c, v))
+    F_dense = oracle.nudft_polar(dense, po)
+    F_sparse = oracle.nudft_polar_sparse(pix, po)
+    assert np.abs(F_sparse - F_dense).max() <= 1e-12 * np.abs(F_dense).max()
+    a_dense = oracle.expand(dense, po)
+    a_sparse = oracle.expand_sparse(pix, po)
+    assert np.linalg.norm(a_sparse - a_dense) <= 1e-12 * np.linalg.norm(a_dense)
+
+
+def test_single_pixel_closed_form():
+    # one unit pixel at (x0, y0): F(xi, theta) = exp(-2 pi i xi (x0 cos theta + y0 sin theta))
+    L = 20
+    po = oracle.plan(L, 0.5, 10)
+    x = oracle.pixel_coords(L)
+    r, c = 3, 14
+    F = oracle.nudft_polar_sparse([(np.array([r]), np.array([c]), np.array([1.0]))], po)[0]
+    xi1, xi2 = oracle.polar_nodes(po)
+    for j, l in [(0, 0), (5, 17), (po.n_xi - 1, po.n_theta - 1)]:
+        ph = -2 * mpmath.pi * (mpmath.mpf(xi1[j, l]) * x[r] + mpmath.mpf(xi2[j, l]) * x[c])
+        want = complex(mpmath.cos(ph), mpmath.sin(ph))
+        assert abs(F[j, l] - want) <= 1e-13
