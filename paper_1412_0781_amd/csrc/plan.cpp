@@ -177,7 +177,18 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     const int BW = CS + pl.w - 1;
     for (int cy = 0; cy < ncy; ++cy)
       for (int cx = 0; cx < ncx; ++cx) {
-        const std::vector<int>& lst = cell[cy * ncx + cx];
+        // Interleave nodes whose tap origin is on even and odd box columns: neighbouring
+        // nodes are read by neighbouring lanes, and 128-byte rows of opposite parity fall
+        // in opposite halves of the LDS banks.
+        std::vector<int> lst;
+        {
+          std::vector<int> ev, od;
+          for (int n : cell[cy * ncx + cx]) (((pl.nodes[n].b1 - cx * CS) & 1) ? od : ev).push_back(n);
+          for (size_t i = 0; i < std::max(ev.size(), od.size()); ++i) {
+            if (i < ev.size()) lst.push_back(ev[i]);
+            if (i < od.size()) lst.push_back(od[i]);
+          }
+        }
         for (size_t a0 = 0; a0 < lst.size(); a0 += kGatherChunk) {
           GatherItem it{cx * CS, cy * CS, (int)pl.gnodes.size(), 0};
           for (size_t a = a0; a < std::min(lst.size(), a0 + kGatherChunk); ++a) {
