@@ -62,7 +62,7 @@ struct NodeTap {
 // holding their tap origin.  A workgroup stages the cell's box of
 // (kGatherCell + w - 1)^2 grid points (for a group of images) in LDS and
 // interpolates its nodes from there.
-constexpr int kGatherCell = 16;
+constexpr int kGatherCell = 14;
 // Pass buffers that keep images innermost store them in groups of kImgGroup:
 // X[outer][group][inner][kImgGroup], a pass of m images using ceil(m / kImgGroup)
 // groups (the slots past m hold zeros).  One group of one (outer, inner) entry is a
