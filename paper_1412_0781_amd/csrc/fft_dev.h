@@ -203,7 +203,19 @@ __device__ inline float2* fft_lds(float2* buf, float2* tmp, int count, int strid
 // the caller guarantees count * n <= fft_inplace_capacity(d, nthreads) and that
 // every radix of d is 4 or 8 (each supported radix adds its register arrays to
 // the kernel, so the in-place form is kept to the two that cover 2^k lengths).
-template <int R, int VMAX>
+// Barrier between FFT stages.  The plain form is __syncthreads().  The LDS-only form
+// waits for this wave's LDS operations and meets the other waves, without waiting
+// for its outstanding global memory operations (used while a copy from HBM into
+// another LDS buffer is in flight; the caller's twiddles must then be in LDS too).
+template <bool LDS_ONLY>
+__device__ __forceinline__ void stage_barrier() {
+  if constexpr (LDS_ONLY)
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else
+    __syncthreads();
+}
+
+template <int R, int VMAX, bool LDS_ONLY = false>
 __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, int count, int stride,
                                                   const float2* __restrict__ tw, int tid, int nthr, FastDiv dnb,
                                                   FastDiv dns) {
@@ -211,9 +223,10 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
   const int nb = n / R;
   const int total = count * nb;
   const int twstep = n / (Ns * R);
-  // the butterfly inputs and their twiddles are both loaded before the barrier, so the
-  // twiddle-table latency overlaps the wait for the other waves
-  float2 v[BM][R], w[BM][R];
+  // Global twiddle tables are loaded before the barrier, so their latency overlaps the
+  // wait for the other waves; LDS tables (LDS_ONLY) are read after it, saving registers.
+  constexpr int WR = LDS_ONLY ? 1 : R;
+  float2 v[BM][R], w[BM][WR];
 #pragma unroll
   for (int b = 0; b < BM; ++b) {
     int idx = tid + b * nthr;
@@ -222,12 +235,14 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       const float2* src = buf + t * stride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
-      int k = j - dns.div(j) * Ns;
+      if constexpr (!LDS_ONLY) {
+        int k = j - dns.div(j) * Ns;
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[b][r] = tw[k * r * twstep];
+        for (int r = 1; r < R; ++r) w[b][r] = tw[k * r * twstep];
+      }
     }
   }
-  __syncthreads();
+  stage_barrier<LDS_ONLY>();
 #pragma unroll
   for (int b = 0; b < BM; ++b) {
     int idx = tid + b * nthr;
@@ -235,7 +250,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       int t = dnb.div(idx), j = idx - t * nb;
       int k = j - dns.div(j) * Ns;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);  // tw[0] = 1 when k = 0
+      for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], LDS_ONLY ? tw[k * r * twstep] : w[b][r % WR]);  // tw[0] = 1
       Dft<R>::run(v[b], tw, n, R);
       float2* dst = buf + t * stride;
       int base = (j - k) * R + k;
@@ -243,7 +258,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[b][r];
     }
   }
-  __syncthreads();
+  stage_barrier<LDS_ONLY>();
 }
 
 constexpr int kFftVmax = 8;  // values per thread: one radix-8 butterfly or two radix-4
@@ -259,19 +274,29 @@ inline int fft_inplace_capacity(const FftDesc& d, int nthr) {
   return cap;
 }
 
-__device__ inline void fft_lds_inplace(float2* buf, int count, int stride, const FftDesc& d,
-                                       const float2* __restrict__ tw_all) {
-  const float2* tw = tw_all + d.tw_off;
+// tw: the twiddle table of this transform length (tw_all + d.tw_off).
+template <bool LDS_ONLY = false>
+__device__ inline void fft_lds_inplace_tw(float2* buf, int count, int stride, const FftDesc& d,
+                                          const float2* __restrict__ tw) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   int Ns = 1;
   for (int s = 0; s < d.nstage; ++s) {
     int R = d.radix[s];
     switch (R) {
-      case 8: fft_stage_inplace<8, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
-      default: fft_stage_inplace<4, kFftVmax>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]); break;
+      case 8:
+        fft_stage_inplace<8, kFftVmax, LDS_ONLY>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]);
+        break;
+      default:
+        fft_stage_inplace<4, kFftVmax, LDS_ONLY>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]);
+        break;
     }
     Ns *= R;
   }
+}
+
+__device__ inline void fft_lds_inplace(float2* buf, int count, int stride, const FftDesc& d,
+                                       const float2* __restrict__ tw_all) {
+  fft_lds_inplace_tw<false>(buf, count, stride, d, tw_all + d.tw_off);
 }
 
 // FFT forms, chosen per plan on the host and compiled as separate kernels so that

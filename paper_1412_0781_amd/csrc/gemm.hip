@@ -65,9 +65,10 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 }
 
 // ---------------------------------------------------------------------------
-// radial quadrature.  grid: (column tiles of 64 = 32 images, work items (k, 128-row tile))
-// Fh: complex [K+1][group][n_xi][16] (images in groups of 16); as a real matrix per k,
-// column 2 i + r (r = re, im) of row j sits at float ((group * n_xi + j) * 32 + (2 i + r) % 32).
+// radial quadrature.  grid: (work items (k, 128-row tile), column tiles of 64 = 32 images)
+// Fh: complex [group][n_xi][nk][16] (images in groups of 16, nk = K+1); as a real matrix
+// per k, column 2 i + r (r = re, im) of row j sits at float
+// ((group * n_xi + j) * nk + k) * 32 + (2 i + r) % 32.
 // ncol = 2 * images.
 // coeffs: float [image][p_half][2]
 // A wave owns 32 rows x 64 columns (two 32x32 MFMA tiles).  The next K chunk is
@@ -97,17 +98,16 @@ template <int PREC>
 __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ radial, const float* __restrict__ Fh,
                                                     float* __restrict__ coeffs, const GemmItem* __restrict__ items,
                                                     const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                    int n_xi, int ncol, long long p_half) {
+                                                    int n_xi, int nk, int ncol, long long p_half) {
   constexpr size_t SZ = sizeof(RadialSmem<PREC>) > sizeof(RadialOut) ? sizeof(RadialSmem<PREC>) : sizeof(RadialOut);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SZ];
   RadialSmem<PREC>& S = *reinterpret_cast<RadialSmem<PREC>*>(smem);
   RadialOut& O = *reinterpret_cast<RadialOut*>(smem);
-  const GemmItem it = items[blockIdx.y];
+  const GemmItem it = items[blockIdx.x];  // k varies fastest: neighbouring workgroups read neighbouring lines of Fh
   const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
-  const int n0 = blockIdx.x * RBN;
+  const int n0 = blockIdx.y * RBN;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
-  const int ngrp = (ncol / 2 + kImgGroup - 1) / kImgGroup;
-  const float* fk = Fh + (size_t)k * ngrp * n_xi * (2 * kImgGroup);
+  const float* fk = Fh + (size_t)k * (2 * kImgGroup);
   const bool vec = (n_xi & 3) == 0;
   float4 ra[4], rb[2];
   auto gload = [&](int k0) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
     for (int u = 0; u < 2; ++u) {  // B: 32 k x 64 columns, four consecutive columns per thread
       int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
       int kc = k0 + kk, col = n0 + nq;  // col % 4 == 0: the four columns share one group
-      const float* src = fk + ((size_t)(col / (2 * kImgGroup)) * n_xi + kc) * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
+      const float* src = fk + ((size_t)(col / (2 * kImgGroup)) * n_xi + kc) * nk * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
       if (kc < n_xi && col + 3 < ncol) {
         rb[u] = *(const float4*)src;
       } else {
@@ -449,14 +449,15 @@ __global__ void k_cov_reduce(const double* __restrict__ partG, const double* __r
 hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs, int nimg, int precision,
                                  hipStream_t st) {
   const int ncol = 2 * nimg;
-  dim3 g((unsigned)((ncol + RBN - 1) / RBN), (unsigned)pl.items_fwd.size());
+  dim3 g((unsigned)pl.items_fwd.size(), (unsigned)((ncol + RBN - 1) / RBN));
+  const int nk = pl.k_max + 1;
   pl.prof.begin(ST_RADIAL_FWD, st);
   if (precision == FB_BF16X3)
     hipLaunchKernelGGL(k_radial_fwd<1>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
-                       pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
+                       pl.d_coef_off, pl.d_p, pl.n_xi, nk, ncol, (long long)pl.p_half);
   else
     hipLaunchKernelGGL(k_radial_fwd<0>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
-                       pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half);
+                       pl.d_coef_off, pl.d_p, pl.n_xi, nk, ncol, (long long)pl.p_half);
   pl.prof.end(st);
   return hipGetLastError();
 }

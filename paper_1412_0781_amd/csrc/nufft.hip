@@ -281,7 +281,8 @@ size_t gather_lds_bytes() {
 }
 
 // ---------------------------------------------------------------------------
-// forward angular: P [n_xi][group][H][16] -> Fh [K+1][group][n_xi][16] (complex)
+// forward angular: P [n_xi][group][H][16] -> Fh [group][n_xi][K+1][16] (complex); a
+// workgroup's output for all k is one contiguous run
 // block: ring j for AG (<= kImgGroup) consecutive image slots; LDS transforms padded to H+1
 // ---------------------------------------------------------------------------
 template <int FORM>
@@ -329,7 +330,85 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
     float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
     float2 Sk = cadd(e, cmul(angtw[k], o));
     float2 F = (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale);
-    Fh[slot_base(k, n_xi, gg) + (size_t)j * kImgGroup] = F;
+    const int i = g0 + gg;
+    Fh[((((size_t)(i / kImgGroup) * n_xi + j) * (K + 1)) + k) * kImgGroup + (i & (kImgGroup - 1))] = F;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward angular, streaming form (in-place FFT with radices 8/4, H % 8 == 0, H <= 512,
+// one group of 16 images per unit).  Same result as k_fwd_angular.  Each workgroup runs
+// U consecutive (ring, group) units; the polar samples of the next unit are loaded into
+// registers before the current unit is transformed and written, and the FFT reads its
+// twiddles from LDS and meets at LDS-only barriers, so those loads stay in flight
+// through the transform and HBM traffic overlaps the FFT.
+// ---------------------------------------------------------------------------
+constexpr int kAngStreamH = 512;  // largest angular half length of the streaming form
+
+__global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __restrict__ P, float2* __restrict__ Fh,
+                                                             FftDesc fd, const float2* __restrict__ tw,
+                                                             const float2* __restrict__ angtw, int n_xi, int K,
+                                                             int ngrp, int U, float scale) {
+  constexpr int G = kImgGroup;
+  constexpr int PF = kAngStreamH * G / 2 / 1024;  // (m, gg) items per thread at H = 512
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (kAngStreamH + 1)];  // packed transforms [G][H+1]
+  __shared__ float2 s_tw[kAngStreamH];
+  __shared__ float2 s_angtw[kAngStreamH];
+  const int H = fd.n, S = H + 1, Hh = H / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int total = n_xi * ngrp;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int nitem = G * Hh;
+  for (int i = tid; i < H; i += nthr) s_tw[i] = tw[fd.tw_off + i];
+  for (int i = tid; i <= K; i += nthr) s_angtw[i] = angtw[i];
+  __syncthreads();
+  // unit u = (ring j, group): groups vary fastest, so consecutive units are consecutive in P.
+  // Item e = (gg, m) of a unit holds lane gg's samples t = 2m and 2m + 1.
+  float4 pre[PF];
+  auto load = [&](int u) {
+    const float2* src = P + (size_t)u * H * G;
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int e = tid + p * nthr;
+      if (e < nitem) {
+        const int gg = e & (G - 1), m = e / G;
+        const float2 f0 = src[(2 * m) * G + gg], f1 = src[(2 * m + 1) * G + gg];
+        pre[p] = make_float4(f0.x, f0.y, f1.x, f1.y);
+      }
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    // packed z_m = s_{2m} + i s_{2m+1}, s_t = Re P_t + Im P_t and s_{t+H} = Re P_t - Im P_t (t < H)
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int e = tid + p * nthr;
+      if (e < nitem) {
+        const int gg = e & (G - 1), m = e / G;
+        const float4 f = pre[p];
+        s_buf[gg * S + m] = make_float2(f.x + f.y, f.z + f.w);
+        s_buf[gg * S + m + Hh] = make_float2(f.x - f.y, f.z - f.w);
+      }
+    }
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
+    fft_lds_inplace_tw<true>(s_buf, G, S, fd, s_tw);
+    const int j = u / ngrp, grp = u - j * ngrp;
+    const int gg = tid & (G - 1);
+    float2* dst = Fh + (((size_t)grp * n_xi + j) * (K + 1)) * G + gg;
+    for (int k = tid / G; k <= K; k += nthr / G) {
+      float2 zk = s_buf[gg * S + k];
+      float2 zc = cconj(s_buf[gg * S + (k == 0 ? 0 : H - k)]);
+      // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
+      float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+      float2 d = csub(zk, zc);
+      float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
+      float2 Sk = cadd(e, cmul(s_angtw[k], o));
+      dst[(size_t)k * G] =
+          (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale);
+    }
+    stage_barrier<true>();  // s_buf is rewritten by the next unit
   }
 }
 
@@ -516,6 +595,7 @@ __global__ void k_adj_rows(const float2* __restrict__ Zc, float* __restrict__ im
 constexpr int kLdsBudget = 72 * 1024;
 constexpr int kFftThreads = 1024;
 constexpr int kMaxTransforms = 16;
+constexpr int kAngularUnits = 16;                  // (ring, group) units per streaming angular workgroup
 static_assert(kMaxTransforms <= kImgGroup, "an FFT workgroup's image slots map to lanes of one group");
 struct FftLaunch {
   int count;
@@ -593,9 +673,20 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
 
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
+  const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+  const bool stream_ok = pl.H % 8 == 0 && pl.H <= kAngStreamH && pl.k_max < pl.H &&
+                         fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
+  if (stream_ok) {
+    const int units = pl.n_xi * ngrp;
+    const int U = kAngularUnits;
+    pl.prof.begin(ST_FWD_ANGULAR, st);
+    hipLaunchKernelGGL(k_fwd_angular_stream, dim3((unsigned)((units + U - 1) / U)), dim3(1024), 0, st, P,
+                       Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, ngrp, U, scale);
+    pl.prof.end(st);
+    return hipGetLastError();
+  }
   FftLaunch fa = fft_launch(pl.fft_ang, pl.H + 1);
   dim3 g((unsigned)((ngrp * kImgGroup + fa.count - 1) / fa.count), (unsigned)pl.n_xi);
-  const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_FWD_ANGULAR, st);
   FB_LAUNCH_FFT(k_fwd_angular, fa.form, g, dim3(kFftThreads), fa.lds, st, P, Fh, pl.fft_ang, pl.d_tw, pl.d_angtw,
                 pl.n_xi, pl.k_max, ngrp, fa.count, scale);
