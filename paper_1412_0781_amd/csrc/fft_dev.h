@@ -215,7 +215,20 @@ __device__ __forceinline__ void stage_barrier() {
     __syncthreads();
 }
 
-template <int R, int VMAX, bool LDS_ONLY = false>
+// Padded LDS layout of one transform: element i sits at fpad(i), one spare slot after every
+// 32 and every 64 elements.  The radix-8 stages read with a stride of n/8 elements and
+// write with strides of 8 and 64; in the plain layout those writes put 16 and 8 lanes on
+// one bank, in the padded one at most 3 (the least for 64 lanes of 8 bytes is 2).
+__host__ __device__ constexpr int fpad(int i) { return i + (i >> 5) + (i >> 6); }
+template <bool PAD>
+__device__ __forceinline__ int fidx(int i) {
+  if constexpr (PAD)
+    return fpad(i);
+  else
+    return i;
+}
+
+template <int R, int VMAX, bool LDS_ONLY = false, bool PAD = false>
 __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, int count, int stride,
                                                   const float2* __restrict__ tw, int tid, int nthr, FastDiv dnb,
                                                   FastDiv dns) {
@@ -234,7 +247,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       int t = dnb.div(idx), j = idx - t * nb;
       const float2* src = buf + t * stride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = src[j + r * nb];
+      for (int r = 0; r < R; ++r) v[b][r] = src[fidx<PAD>(j + r * nb)];
       if constexpr (!LDS_ONLY) {
         int k = j - dns.div(j) * Ns;
 #pragma unroll
@@ -255,7 +268,7 @@ __device__ __forceinline__ void fft_stage_inplace(float2* buf, int n, int Ns, in
       float2* dst = buf + t * stride;
       int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[b][r];
+      for (int r = 0; r < R; ++r) dst[fidx<PAD>(base + r * Ns)] = v[b][r];
     }
   }
   stage_barrier<LDS_ONLY>();
@@ -275,7 +288,7 @@ inline int fft_inplace_capacity(const FftDesc& d, int nthr) {
 }
 
 // tw: the twiddle table of this transform length (tw_all + d.tw_off).
-template <bool LDS_ONLY = false>
+template <bool LDS_ONLY = false, bool PAD = false>
 __device__ inline void fft_lds_inplace_tw(float2* buf, int count, int stride, const FftDesc& d,
                                           const float2* __restrict__ tw) {
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -284,10 +297,12 @@ __device__ inline void fft_lds_inplace_tw(float2* buf, int count, int stride, co
     int R = d.radix[s];
     switch (R) {
       case 8:
-        fft_stage_inplace<8, kFftVmax, LDS_ONLY>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]);
+        fft_stage_inplace<8, kFftVmax, LDS_ONLY, PAD>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s],
+                                                      d.dns[s]);
         break;
       default:
-        fft_stage_inplace<4, kFftVmax, LDS_ONLY>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s], d.dns[s]);
+        fft_stage_inplace<4, kFftVmax, LDS_ONLY, PAD>(buf, d.n, Ns, count, stride, tw, tid, nthr, d.dnb[s],
+                                                      d.dns[s]);
         break;
     }
     Ns *= R;

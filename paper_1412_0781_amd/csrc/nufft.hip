@@ -162,6 +162,161 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
 }
 
 // ---------------------------------------------------------------------------
+// Streaming forms of the two grid passes (in-place FFT with radices 8/4, N <= 512,
+// 1024 threads, 16 transforms per unit).  Same results as k_fwd_rows / k_fwd_cols.
+// A workgroup runs U consecutive units; the next unit's inputs are loaded into
+// registers before the current unit is transformed and written, the FFT reads its
+// twiddles from LDS and meets at LDS-only barriers, so those loads stay in flight.
+// ---------------------------------------------------------------------------
+constexpr int kGridStreamN = 512;   // largest grid side of the streaming forms
+constexpr int kGridStreamPF = 8;    // input values per thread held for the next unit
+
+// rows: unit = (image, 16 row pairs); rows a = 2 p0 .. 2 p0 + 31 of the image
+__global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
+                                                             const float* __restrict__ deconv, FftDesc fd,
+                                                             const float2* __restrict__ tw, int L, int M2, int hw,
+                                                             int nimg, int U, FastDiv dL4) {
+  constexpr int RP = 16;
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
+  __shared__ float2 s_tw[kGridStreamN];
+  __shared__ float s_dec[kGridStreamN / 2];
+  const int N = fd.n, S = fpad(N - 1) + 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nrb = ((L + 1) / 2 + RP - 1) / RP;  // row blocks per image
+  const int total = nimg * nrb;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int x0 = -((L - 1 + 1) / 2);  // -ceil((L-1)/2)
+  for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
+  for (int i = tid; i < L; i += nthr) s_dec[i] = deconv[i];
+  __syncthreads();
+  // one item = four consecutive pixels of a row (L % 4 == 0); rows past L read as zero
+  constexpr int PF = kGridStreamPF / 4;
+  const int L4 = L / 4, nval = 2 * RP * L4;
+  float4 pre[PF];
+  auto load = [&](int u) {
+    const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
+    const float4* src = (const float4*)(img + (size_t)im * L * L);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      const int r = dL4.div(e), a = a0 + r;
+      pre[q] = (e < nval && a < L) ? src[(size_t)a * L4 + (e - r * L4)] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
+    // row a0 + r goes to transform r / 2, real part (r even) or imaginary part (r odd),
+    // deconvolved and centred; the N - L padded columns of every transform are zero
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nval) {
+        const int r = dL4.div(e), b0 = 4 * (e - r * L4), a = a0 + r;
+        const float da = (a < L) ? s_dec[a] : 0.f;
+        const float vv[4] = {pre[q].x, pre[q].y, pre[q].z, pre[q].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int pos = x0 + b0 + i;
+          pos += (pos < 0) ? N : 0;
+          ((float*)&s_buf[(r >> 1) * S + fpad(pos)])[r & 1] = vv[i] * da * s_dec[b0 + i];
+        }
+      }
+    }
+    for (int e = tid; e < RP * (N - L); e += nthr) {
+      const int t = e / (N - L), z = e - t * (N - L);
+      int pos = x0 + L + z;  // columns past the image, wrapped
+      pos -= (pos >= N) ? N : 0;
+      pos += (pos < 0) ? N : 0;
+      s_buf[t * S + fpad(pos)] = make_float2(0.f, 0.f);
+    }
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);
+    fft_lds_inplace_tw<true, true>(s_buf, RP, S, fd, s_tw);
+    // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i); lanes over the rows
+    float2* out = g1 + (size_t)im * M2 * L;
+    const int r = tid & 31, a = a0 + r;
+    if (a < L) {
+      const int pp = r >> 1, which = r & 1;
+      for (int mi = tid >> 5; mi < M2; mi += nthr >> 5) {
+        int m2 = mi - hw;
+        int mp = m2 < 0 ? m2 + N : m2;
+        int mn = m2 > 0 ? N - m2 : -m2;
+        float2 z1 = s_buf[pp * S + fpad(mp)], z2 = cconj(s_buf[pp * S + fpad(mn)]);
+        float2 v;
+        if (which == 0) {
+          v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
+        } else {
+          float2 dd = csub(z1, z2);
+          v = make_float2(0.5f * dd.y, -0.5f * dd.x);
+        }
+        out[(size_t)mi * L + a] = v;
+      }
+    }
+    stage_barrier<true>();
+  }
+}
+
+// columns: unit = (stored row m2, image group); output G [M2][group][N][16]
+__global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
+                                                             FftDesc fd, const float2* __restrict__ tw, int L,
+                                                             int M2, int nimg, int ngrp, int U, FastDiv dL) {
+  constexpr int G = kImgGroup;
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
+  __shared__ float2 s_tw[kGridStreamN];
+  const int N = fd.n, S = fpad(N - 1) + 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int total = M2 * ngrp;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int x0 = -((L - 1 + 1) / 2);
+  for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
+  __syncthreads();
+  constexpr int PF = kGridStreamPF / 2;
+  const int nval = G * L;
+  float2 pre[PF];
+  // unit u = (m2, group): groups vary fastest, so consecutive units write consecutive runs of G
+  auto load = [&](int u) {
+    const int m2 = u / ngrp, i0 = (u - m2 * ngrp) * G;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      const int c = dL.div(e), a = e - c * L;
+      pre[q] = (e < nval && i0 + c < nimg) ? g1[((size_t)(i0 + c) * M2 + m2) * L + a] : make_float2(0.f, 0.f);
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    const int m2 = u / ngrp, grp = u - m2 * ngrp;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nval) {
+        const int c = dL.div(e), a = e - c * L;
+        int pos = x0 + a;
+        pos += (pos < 0) ? N : 0;
+        s_buf[c * S + fpad(pos)] = pre[q];
+      }
+    }
+    for (int e = tid; e < G * (N - L); e += nthr) {
+      const int t = e / (N - L), z = e - t * (N - L);
+      int pos = x0 + L + z;
+      pos -= (pos >= N) ? N : 0;
+      pos += (pos < 0) ? N : 0;
+      s_buf[t * S + fpad(pos)] = make_float2(0.f, 0.f);
+    }
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);
+    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    const int c = tid & (G - 1);
+    float2* dst = g + ((size_t)m2 * ngrp + grp) * N * G + c;
+    for (int m1 = tid / G; m1 < N; m1 += nthr / G) dst[(size_t)m1 * G] = s_buf[c * S + fpad(m1)];
+    stage_barrier<true>();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // forward gather: G [M2][group][N][16] -> P [n_xi][group][H][16]
 // block = (work item: one grid cell and up to kGatherChunk of its nodes, group of IG images).
 // The cell's (CS + W - 1)^2 box of grid points is staged in LDS for the IG images (each
@@ -351,10 +506,10 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
                                                              int ngrp, int U, float scale) {
   constexpr int G = kImgGroup;
   constexpr int PF = kAngStreamH * G / 2 / 1024;  // (m, gg) items per thread at H = 512
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (kAngStreamH + 1)];  // packed transforms [G][H+1]
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];  // packed transforms, padded
   __shared__ float2 s_tw[kAngStreamH];
   __shared__ float2 s_angtw[kAngStreamH];
-  const int H = fd.n, S = H + 1, Hh = H / 2;
+  const int H = fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -387,19 +542,19 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
       if (e < nitem) {
         const int gg = e & (G - 1), m = e / G;
         const float4 f = pre[p];
-        s_buf[gg * S + m] = make_float2(f.x + f.y, f.z + f.w);
-        s_buf[gg * S + m + Hh] = make_float2(f.x - f.y, f.z - f.w);
+        s_buf[gg * S + fpad(m)] = make_float2(f.x + f.y, f.z + f.w);
+        s_buf[gg * S + fpad(m + Hh)] = make_float2(f.x - f.y, f.z - f.w);
       }
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
-    fft_lds_inplace_tw<true>(s_buf, G, S, fd, s_tw);
+    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
     const int j = u / ngrp, grp = u - j * ngrp;
     const int gg = tid & (G - 1);
     float2* dst = Fh + (((size_t)grp * n_xi + j) * (K + 1)) * G + gg;
     for (int k = tid / G; k <= K; k += nthr / G) {
-      float2 zk = s_buf[gg * S + k];
-      float2 zc = cconj(s_buf[gg * S + (k == 0 ? 0 : H - k)]);
+      float2 zk = s_buf[gg * S + fpad(k)];
+      float2 zc = cconj(s_buf[gg * S + fpad(k == 0 ? 0 : H - k)]);
       // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
       float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
       float2 d = csub(zk, zc);
@@ -596,6 +751,7 @@ constexpr int kLdsBudget = 72 * 1024;
 constexpr int kFftThreads = 1024;
 constexpr int kMaxTransforms = 16;
 constexpr int kAngularUnits = 16;                  // (ring, group) units per streaming angular workgroup
+constexpr int kGridUnits = 16;                     // units per streaming row / column workgroup
 static_assert(kMaxTransforms <= kImgGroup, "an FFT workgroup's image slots map to lanes of one group");
 struct FftLaunch {
   int count;
@@ -647,19 +803,38 @@ hipError_t configure_kernels() {
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
                                 hipStream_t st) {
   const int N = pl.N, L = pl.L;
-  FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
-  dim3 g1((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
-  pl.prof.begin(ST_FWD_ROWS, st);
-  FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,
-                pl.d_tw, L, pl.M2, pl.hw, fr.count, make_fastdiv(L));
-  pl.prof.end(st);
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
-  FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
-  dim3 g2((unsigned)((ngrp * kImgGroup + fc.count - 1) / fc.count), (unsigned)pl.M2);
-  pl.prof.begin(ST_FWD_COLS, st);
-  FB_LAUNCH_FFT(k_fwd_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufA, bufB, pl.fft_grid, pl.d_tw, L,
-                pl.M2, nimg, ngrp, fc.count, make_fastdiv(L));
-  pl.prof.end(st);
+  // streaming forms: 16 transforms of length N <= 512 in place with 1024 threads, and the
+  // inputs of one unit (32 rows or 16 columns of L values) in kGridStreamPF values per thread
+  const bool stream_ok = N <= kGridStreamN && fft_inplace_capacity(pl.fft_grid, 1024) >= 16 * N &&
+                         32 * L <= kGridStreamPF * 1024 && L % 4 == 0;
+  if (stream_ok) {
+    const int nrb = ((L + 1) / 2 + 15) / 16;
+    const long long ur = (long long)nimg * nrb;
+    pl.prof.begin(ST_FWD_ROWS, st);
+    hipLaunchKernelGGL(k_fwd_rows_stream, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
+                       images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, kGridUnits,
+                       make_fastdiv(L / 4));
+    pl.prof.end(st);
+    const long long uc = (long long)pl.M2 * ngrp;
+    pl.prof.begin(ST_FWD_COLS, st);
+    hipLaunchKernelGGL(k_fwd_cols_stream, dim3((unsigned)((uc + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
+                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, kGridUnits, make_fastdiv(L));
+    pl.prof.end(st);
+  } else {
+    FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
+    dim3 g1((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);
+    pl.prof.begin(ST_FWD_ROWS, st);
+    FB_LAUNCH_FFT(k_fwd_rows, fr.form, g1, dim3(kFftThreads), fr.lds, st, images, bufA, pl.d_deconv, pl.fft_grid,
+                  pl.d_tw, L, pl.M2, pl.hw, fr.count, make_fastdiv(L));
+    pl.prof.end(st);
+    FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
+    dim3 g2((unsigned)((ngrp * kImgGroup + fc.count - 1) / fc.count), (unsigned)pl.M2);
+    pl.prof.begin(ST_FWD_COLS, st);
+    FB_LAUNCH_FFT(k_fwd_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufA, bufB, pl.fft_grid, pl.d_tw, L,
+                  pl.M2, nimg, ngrp, fc.count, make_fastdiv(L));
+    pl.prof.end(st);
+  }
   constexpr int IG = kGatherImages;
   const int nitems = (int)pl.gitems.size();
   dim3 g3((unsigned)nitems, (unsigned)ngrp);
