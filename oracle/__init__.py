@@ -46,3 +46,4 @@ from .fb import (  # noqa: F401
     adjoint,
     coeff_inner,
 )
+from . import spca  # noqa: F401,E402
