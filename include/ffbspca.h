@@ -168,6 +168,36 @@ int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, dou
            double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream);
 size_t fb_eig_workspace_bytes(fb_plan_t plan);
 
+/* Steerable PCA back end (Algorithm 2, steps 5-6, and Sec. V), on the eigenpairs of
+ * fb_eig.  All arrays are device memory owned by the caller; asynchronous on `stream`.
+ *
+ * fb_spca_select: component selection of Eq.(compselect) and the coefficient filter.
+ *   For each k, component l is selected when lambda_l^(k) > sigma2 (1 + sqrt(gamma_k))^2
+ *   with gamma_0 = p_0 / count and gamma_k = p_k / (2 count) (the Marcenko-Pastur edge);
+ *   n_sel [k_max + 1] (int32) receives the number selected per k; weights [p_half] (FP64,
+ *   at coef_off[k] + l) receives ell / (ell + sigma2), ell = (lambda - sigma2)_+ (the
+ *   first-order soft threshold of the eigenvalues), for selected components and 0 for
+ *   the others.  evals as written by fb_eig; count = the number of images; sigma2 >= 0
+ *   the noise variance (estimated by the caller).
+ * fb_spca_coeffs: c^i_{k,l} = sum_q (a^i_{k,q} - m_q [k = 0]) u_l^(k)(q) (Eq.(sPCAcoeff)
+ *   with the mean of Algorithm 2 step 1 removed); coeffs and out float32 [n][p_half][2]
+ *   (l in place of q, same layout), evecs and mean as written by fb_eig.  FP32 products.
+ * fb_spca_reconstruct: a^i_{k,q} = sum_l u_l^(k)(q) w_{k,l} c^i_{k,l} + m_q [k = 0]; weights
+ *   nullable (then w = 1, the inverse of fb_spca_coeffs).  With the weights of
+ *   fb_spca_select, fb_adjoint of the result gives the denoised images.
+ * fb_spca_radial: f^{k,l}(xi_j) = sum_q N_{k,q} J_k(R_{k,q} xi_j / c) u_l^(k)(q)
+ *   (Eq.(sPCArad)) at the Gauss-Legendre nodes; f float32, block k at n_xi * coef_off[k],
+ *   [n_xi][p_k] row-major.
+ * Errors: FB_ERR_INVALID_ARG (NULL pointers, in-place out, count <= 0, sigma2 < 0),
+ * FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+int fb_spca_select(fb_plan_t plan, const double* evals, int64_t count, double sigma2, int32_t* n_sel,
+                   double* weights, void* stream);
+int fb_spca_coeffs(fb_plan_t plan, const float* coeffs, int64_t n, const double* evecs, const double* mean,
+                   float* out, void* stream);
+int fb_spca_reconstruct(fb_plan_t plan, const float* c, int64_t n, const double* evecs, const double* mean,
+                        const double* weights, float* out, void* stream);
+int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream);
+
 /* Seeded synthetic inputs on the device (not part of the method): Philox-4x32-10
  * (Salmon et al., SC'11) words with counter (word_block, index_lo, index_hi,
  * stream) and key (seed_lo, seed_hi), Box-Muller normals on word pairs.
@@ -188,7 +218,7 @@ int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int6
  * the number of stages (FB_NUM_STAGES) or a negative FB_ERR_* code.  Stage
  * names come from fb_stage_name.  Not for concurrent use of one plan from
  * several streams while enabled. */
-#define FB_NUM_STAGES 12
+#define FB_NUM_STAGES 13
 int fb_profile_enable(fb_plan_t plan, int enable);
 int fb_profile_read(fb_plan_t plan, double* total_ms, int64_t* launches, int max_stages, int reset);
 const char* fb_stage_name(int stage);

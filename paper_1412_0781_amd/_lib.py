@@ -51,6 +51,10 @@ SIGNATURES = [
     ("fb_eig", c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                        c_void_p, c_size_t, c_void_p]),
     ("fb_eig_workspace_bytes", c_size_t, [c_void_p]),
+    ("fb_spca_select", c_int, [c_void_p, c_void_p, c_int64, c_double, c_void_p, c_void_p, c_void_p]),
+    ("fb_spca_coeffs", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("fb_spca_reconstruct", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("fb_spca_radial", c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_synth_normals", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_float, c_void_p, c_void_p]),
     ("fb_synth_words", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_void_p, c_void_p]),
     ("fb_profile_enable", c_int, [c_void_p, c_int]),

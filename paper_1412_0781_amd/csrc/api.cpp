@@ -211,6 +211,41 @@ int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, dou
   return hip_rc(pl, fb::launch_eig(pl, G, S0, count, evals, evecs, C_out, mean_out, (double*)ws, (hipStream_t)stream));
 }
 
+int fb_spca_select(fb_plan_t plan, const double* evals, int64_t count, double sigma2, int32_t* n_sel,
+                   double* weights, void* stream) {
+  if (!plan || !evals || !n_sel || !weights || count <= 0 || !(sigma2 >= 0.0)) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  return hip_rc(pl, fb::launch_spca_select(pl, evals, count, sigma2, n_sel, weights, (hipStream_t)stream));
+}
+
+int fb_spca_coeffs(fb_plan_t plan, const float* coeffs, int64_t n, const double* evecs, const double* mean,
+                   float* out, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (n == 0) return FB_OK;
+  if (!coeffs || !evecs || !mean || !out || (const void*)coeffs == (const void*)out) return FB_ERR_INVALID_ARG;
+  return hip_rc(pl, fb::launch_spca_apply(pl, 0, coeffs, n, evecs, mean, nullptr, out, (hipStream_t)stream));
+}
+
+int fb_spca_reconstruct(fb_plan_t plan, const float* c, int64_t n, const double* evecs, const double* mean,
+                        const double* weights, float* out, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (n == 0) return FB_OK;
+  if (!c || !evecs || !mean || !out || (const void*)c == (const void*)out) return FB_ERR_INVALID_ARG;
+  return hip_rc(pl, fb::launch_spca_apply(pl, 1, c, n, evecs, mean, weights, out, (hipStream_t)stream));
+}
+
+int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream) {
+  if (!plan || !evecs || !f) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  return hip_rc(pl, fb::launch_spca_radial(pl, evecs, f, (hipStream_t)stream));
+}
+
 int fb_synth_normals(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per, float scale,
                      float* out, void* stream) {
   if (n < 0 || n_per < 0 || first_index < 0) return FB_ERR_INVALID_ARG;

@@ -48,6 +48,14 @@ hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long lo
                       double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st);
 size_t eig_workspace_bytes(const Plan& pl);
 
+// Steerable PCA back end (Algorithm 2 steps 5-6; Sec. V selection and shrinkage).
+hipError_t launch_spca_select(const Plan& pl, const double* evals, long long count, double sigma2, int* n_sel,
+                              double* weights, hipStream_t st);
+// mode 0: c = (a - m) U per k; mode 1: a = U (w c) + m per k (weights may be null only in mode 0)
+hipError_t launch_spca_apply(const Plan& pl, int mode, const float* in, long long n, const double* evecs,
+                             const double* mean, const double* weights, float* out, hipStream_t st);
+hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hipStream_t st);
+
 // seeded inputs
 hipError_t launch_synth_normals(unsigned long long seed, unsigned rng_stream, long long first, long long n,
                                 long long n_per, float scale, float* out, hipStream_t st);

@@ -13,21 +13,6 @@ namespace fb {
 
 static const double kPi = 3.14159265358979323846;
 
-static uint16_t float_to_bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
-  uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
-}
-static float bf16_to_float(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-
 static void add_fft(FftDesc& d, int n, std::vector<float>& tw) {
   d.n = n;
   std::vector<int> rad;
@@ -272,7 +257,9 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
   pl.items_fwd.clear();
   pl.items_adj.clear();
   pl.items_cov.clear();
+  pl.items_spca.clear();
   for (int k = 0; k <= pl.k_max; ++k) {
+    for (int n0 = 0; n0 < pl.p[k]; n0 += 64) pl.items_spca.push_back(GemmItem{k, n0, 0, 0});
     for (int m0 = 0; m0 < pl.p[k]; m0 += kRadialRows) pl.items_fwd.push_back(GemmItem{k, m0, 0, 0});
     for (int j0 = 0; j0 < pl.n_xi; j0 += pl.bm) pl.items_adj.push_back(GemmItem{k, j0, 0, 0});
     for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm)
@@ -304,17 +291,11 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(configure_kernels());
   size_t nb = (size_t)pl.p_half * pl.n_xi;
   std::vector<float> r32(nb);
-  std::vector<uint16_t> rhi(nb), rlo(nb);
-  for (size_t i = 0; i < nb; ++i) {
-    double v = pl.radial[i];
-    r32[i] = (float)v;
-    uint16_t h = float_to_bf16_rne((float)v);
-    rhi[i] = h;
-    rlo[i] = float_to_bf16_rne((float)(v - (double)bf16_to_float(h)));
-  }
+  for (size_t i = 0; i < nb; ++i) r32[i] = (float)pl.radial[i];
   FB_HIP_TRY(upload(&pl.d_radial, r32.data(), nb));
-  FB_HIP_TRY(upload(&pl.d_radial_hi, rhi.data(), nb));
-  FB_HIP_TRY(upload(&pl.d_radial_lo, rlo.data(), nb));
+  std::vector<float> xw(pl.n_xi);
+  for (int j = 0; j < pl.n_xi; ++j) xw[j] = (float)(pl.xi[j] * pl.wq[j]);
+  FB_HIP_TRY(upload(&pl.d_xw, xw.data(), xw.size()));
   std::vector<int> off32(pl.coef_off.begin(), pl.coef_off.end());
   FB_HIP_TRY(upload(&pl.d_coef_off, off32.data(), off32.size()));
   FB_HIP_TRY(upload(&pl.d_p, pl.p.data(), pl.p.size()));
@@ -331,19 +312,21 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_items_fwd, pl.items_fwd.data(), pl.items_fwd.size()));
   FB_HIP_TRY(upload(&pl.d_items_adj, pl.items_adj.data(), pl.items_adj.size()));
   FB_HIP_TRY(upload(&pl.d_items_cov, pl.items_cov.data(), pl.items_cov.size()));
+  FB_HIP_TRY(upload(&pl.d_items_spca, pl.items_spca.data(), pl.items_spca.size()));
   pl.has_device = true;
   return FB_OK;
 }
 
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
-  void* ptrs[] = {pl.d_radial, pl.d_radial_hi, pl.d_radial_lo, pl.d_coef_off, pl.d_p, pl.d_cov_off,
-                  pl.d_deconv, pl.d_gnodes, pl.d_gitems, pl.d_tw, pl.d_angtw, pl.d_csr_ptr, pl.d_csr,
-                  pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov};
+  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_coef_off,  pl.d_p,         pl.d_cov_off,
+                  pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
+                  pl.d_csr_ptr,   pl.d_csr,       pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov,
+                  pl.d_items_spca};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
-  pl.d_radial_hi = pl.d_radial_lo = nullptr;
+  pl.d_xw = nullptr;
   pl.d_coef_off = pl.d_p = nullptr;
   pl.d_cov_off = nullptr;
   pl.d_deconv = nullptr;
@@ -352,14 +335,15 @@ void free_device(Plan& pl) {
   pl.d_tw = pl.d_angtw = nullptr;
   pl.d_csr_ptr = nullptr;
   pl.d_csr = nullptr;
-  pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = nullptr;
+  pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = pl.d_items_spca = nullptr;
   pl.has_device = false;
 }
 
 const char* stage_name(int s) {
   static const char* names[ST_COUNT] = {"fwd_rows",    "fwd_cols",   "fwd_gather", "fwd_angular",
                                         "radial_fwd",  "covariance", "radial_adj", "adj_angular",
-                                        "adj_spread",  "adj_cols",   "adj_rows",   "eig"};
+                                        "adj_spread",  "adj_cols",   "adj_rows",   "eig",
+                                        "spca"};
   return (s >= 0 && s < ST_COUNT) ? names[s] : "unknown";
 }
 

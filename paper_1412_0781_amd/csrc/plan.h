@@ -103,6 +103,7 @@ enum Stage {
   ST_ADJ_COLS,
   ST_ADJ_ROWS,
   ST_EIG,
+  ST_SPCA,
   ST_COUNT
 };
 const char* stage_name(int s);
@@ -166,7 +167,7 @@ struct Plan {
   std::vector<float> angtw;        // exp(-2 pi i k / n_theta), k = 0..H, interleaved
   std::vector<int> csr_ptr;        // N * (N/2 + 1) + 1
   std::vector<SpreadEntry> csr;    // spreading entries
-  std::vector<GemmItem> items_fwd, items_adj, items_cov;
+  std::vector<GemmItem> items_fwd, items_adj, items_cov, items_spca;
   int bm = 64, bn = 64;            // GEMM tile
 
   mutable Profiler prof;
@@ -176,8 +177,7 @@ struct Plan {
   int device = -1;
   hipError_t last_hip = hipSuccess;
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
-  uint16_t* d_radial_hi = nullptr;    // BF16 hi part
-  uint16_t* d_radial_lo = nullptr;    // BF16 lo part (radial - hi, rounded)
+  float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
   int* d_coef_off = nullptr;          // k_max + 2 (fits int32)
   int* d_p = nullptr;                 // k_max + 1
   long long* d_cov_off = nullptr;     // k_max + 2
@@ -191,6 +191,7 @@ struct Plan {
   GemmItem* d_items_fwd = nullptr;
   GemmItem* d_items_adj = nullptr;
   GemmItem* d_items_cov = nullptr;
+  GemmItem* d_items_spca = nullptr;   // (k, 64-wide column tile) of the steerable-PCA products
 };
 
 // Build host tables; returns FB_OK or an FB_ERR_* code.

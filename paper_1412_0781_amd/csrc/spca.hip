@@ -1,0 +1,155 @@
+// Steerable PCA back end on the device (Algorithm 2, steps 5-6, and the component
+// selection and eigenvalue shrinkage of Sec. V), from the eigenpairs of fb_eig:
+//   selection  lambda_l^(k) > sigma^2 (1 + sqrt(gamma_k))^2, gamma_0 = p_0/n,
+//              gamma_k = p_k/(2n) (Eq.(compselect)); filter ell/(ell + sigma^2) with
+//              ell = (lambda - sigma^2)_+ on the selected components, 0 elsewhere
+//   project    c_{k,.} = (a_{k,.} - m delta_{k0}) U^(k)               (Eq.(sPCAcoeff))
+//   rebuild    a_{k,.} = U^(k) (w_k * c_{k,.}) + m delta_{k0}
+//   radial     f^{k,l}(xi_j) = sum_q N_{k,q} J_k(R_{k,q} xi_j / c) u_l^(k)(q)  (Eq.(sPCArad))
+// The two coefficient maps are per-k products of the complex coefficients (real and
+// imaginary parts as separate rows) with the real p_k x p_k matrix U^(k), on
+// v_mfma_f32_32x32x2f32 in 64 x 64 tiles (FP32 products and sums; U rounded to FP32).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace fb {
+
+typedef float f32x16_s __attribute__((ext_vector_type(16)));
+
+__global__ void k_spca_select(const double* __restrict__ evals, const int* __restrict__ coef_off,
+                              const int* __restrict__ p, double n, double sigma2, int* __restrict__ n_sel,
+                              double* __restrict__ weights) {
+  const int k = blockIdx.x, pk = p[k], off = coef_off[k];
+  const double gamma = (k == 0) ? pk / n : pk / (2.0 * n);
+  const double edge = sigma2 * (1.0 + sqrt(gamma)) * (1.0 + sqrt(gamma));
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int l = threadIdx.x; l < pk; l += blockDim.x) {
+    const double lam = evals[off + l];
+    const bool sel = lam > edge;
+    const double ell = lam > sigma2 ? lam - sigma2 : 0.0;
+    weights[off + l] = sel ? ell / (ell + sigma2) : 0.0;
+    if (sel) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) n_sel[k] = cnt;
+}
+
+// MODE 0 (project): out[i][off + l] = sum_q (a[i][off + q] - m_q [k = 0, re]) U[q][l]
+// MODE 1 (rebuild): out[i][off + q] = sum_l U[q][l] w[off + l] c[i][off + l] + m_q [k = 0, re]
+// grid: (image tiles of 32, work items (k, 64-wide output tile)); rows of a tile are
+// (image, re/im) pairs.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_spca_apply(const float* __restrict__ in, float* __restrict__ out,
+                                                    const double* __restrict__ evecs,
+                                                    const double* __restrict__ mean,
+                                                    const double* __restrict__ weights,
+                                                    const GemmItem* __restrict__ items,
+                                                    const int* __restrict__ coef_off, const int* __restrict__ p,
+                                                    const long long* __restrict__ cov_off, long long n,
+                                                    long long p_half) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ float As[TK][TM + 4];
+  __shared__ float Bs[TK][TN + 4];
+  const GemmItem it = items[blockIdx.y];
+  const int k = it.k, n0 = it.t0, pk = p[k], off = coef_off[k];
+  const long long i0 = (long long)blockIdx.x * (TM / 2);
+  const double* U = evecs + cov_off[k];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  f32x16_s acc = {};
+  for (int k0 = 0; k0 < pk; k0 += TK) {
+    for (int e = tid; e < TK * TM; e += 256) {
+      const int kk = e / TM, m = e - kk * TM;
+      const long long img = i0 + (m >> 1);
+      const int ri = m & 1, q = k0 + kk;
+      float v = 0.f;
+      if (img < n && q < pk) {
+        v = in[(size_t)img * 2 * p_half + 2 * (size_t)(off + q) + ri];
+        if (MODE == 0 && k == 0 && ri == 0) v -= (float)mean[q];
+      }
+      As[kk][m] = v;
+    }
+    for (int e = tid; e < TK * TN; e += 256) {
+      const int kk = e / TN, nn = e - kk * TN;
+      const int r = k0 + kk, c = n0 + nn;
+      float v = 0.f;
+      if (r < pk && c < pk) {
+        if (MODE == 0)
+          v = (float)U[(size_t)r * pk + c];                            // U[q = r][l = c]
+        else
+          v = (float)(U[(size_t)c * pk + r] * (weights ? weights[off + r] : 1.0));  // U[q = c][l = r] w_l
+      }
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 2) {
+      float a = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
+      float b = Bs[kk + (lane >> 5)][wn * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int m = wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+    const int c = n0 + wn * 32 + (lane & 31);
+    const long long img = i0 + (m >> 1);
+    const int ri = m & 1;
+    if (img < n && c < pk) {
+      float v = acc[i];
+      if (MODE == 1 && k == 0 && ri == 0) v += (float)mean[c];
+      out[(size_t)img * 2 * p_half + 2 * (size_t)(off + c) + ri] = v;
+    }
+  }
+}
+
+// f [sum_k n_xi p_k]: block k at n_xi * coef_off[k], [n_xi][p_k] row-major
+__global__ void k_spca_radial(const float* __restrict__ radial, const float* __restrict__ xw,
+                              const double* __restrict__ evecs, const int* __restrict__ coef_off,
+                              const int* __restrict__ p, const long long* __restrict__ cov_off, int n_xi,
+                              float* __restrict__ f) {
+  const int k = blockIdx.x, pk = p[k], off = coef_off[k];
+  const double* U = evecs + cov_off[k];
+  for (int e = threadIdx.x; e < n_xi * pk; e += blockDim.x) {
+    const int j = e / pk, l = e - j * pk;
+    double s = 0.0;
+    for (int q = 0; q < pk; ++q) s += (double)radial[(size_t)(off + q) * n_xi + j] * U[(size_t)q * pk + l];
+    f[(size_t)n_xi * off + e] = (float)(s / (double)xw[j]);
+  }
+}
+
+hipError_t launch_spca_select(const Plan& pl, const double* evals, long long count, double sigma2, int* n_sel,
+                              double* weights, hipStream_t st) {
+  pl.prof.begin(ST_SPCA, st);
+  hipLaunchKernelGGL(k_spca_select, dim3((unsigned)(pl.k_max + 1)), dim3(256), 0, st, evals, pl.d_coef_off, pl.d_p,
+                     (double)count, sigma2, n_sel, weights);
+  pl.prof.end(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_spca_apply(const Plan& pl, int mode, const float* in, long long n, const double* evecs,
+                             const double* mean, const double* weights, float* out, hipStream_t st) {
+  dim3 g((unsigned)((n + 31) / 32), (unsigned)pl.items_spca.size());
+  pl.prof.begin(ST_SPCA, st);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_spca_apply<0>, g, dim3(256), 0, st, in, out, evecs, mean, weights, pl.d_items_spca,
+                       pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+  else
+    hipLaunchKernelGGL(k_spca_apply<1>, g, dim3(256), 0, st, in, out, evecs, mean, weights, pl.d_items_spca,
+                       pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+  pl.prof.end(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hipStream_t st) {
+  pl.prof.begin(ST_SPCA, st);
+  hipLaunchKernelGGL(k_spca_radial, dim3((unsigned)(pl.k_max + 1)), dim3(256), 0, st, pl.d_radial, pl.d_xw, evecs,
+                     pl.d_coef_off, pl.d_p, pl.d_cov_off, pl.n_xi, f);
+  pl.prof.end(st);
+  return hipGetLastError();
+}
+
+}  // namespace fb

@@ -182,6 +182,56 @@ class Plan:
                            _stream_ptr(dev)), self._h)
         return evals, evecs, C, mean
 
+    # -- steerable PCA back end (Algorithm 2 steps 5-6, Sec. V) ------------------
+    def spca_select(self, evals: torch.Tensor, count: int, sigma2: float):
+        """Components above the Marcenko-Pastur edge per k (Eq.(compselect)) and the coefficient
+        filter ell / (ell + sigma2), ell = (lambda - sigma2)_+.  Returns (n_sel int32 [k_max+1],
+        weights FP64 [p_half]) on the device."""
+        _need(evals, torch.float64, (self.p_half,), "evals")
+        n_sel = torch.empty(self.k_max + 1, dtype=torch.int32, device=evals.device)
+        w = torch.empty(self.p_half, dtype=torch.float64, device=evals.device)
+        check(lib().fb_spca_select(self._h, evals.data_ptr(), int(count), float(sigma2), n_sel.data_ptr(),
+                                   w.data_ptr(), _stream_ptr(evals.device)), self._h)
+        return n_sel, w
+
+    def spca_coeffs(self, coeffs: torch.Tensor, evecs: torch.Tensor, mean: torch.Tensor) -> torch.Tensor:
+        """c_{k,.} = (a_{k,.} - m [k = 0]) U^(k) (Eq.(sPCAcoeff)); float32 [n, p_half, 2]."""
+        n = coeffs.shape[0]
+        _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
+        _need(evecs, torch.float64, (self.cov_size,), "evecs")
+        _need(mean, torch.float64, (self.p0,), "mean")
+        out = torch.empty_like(coeffs)
+        check(lib().fb_spca_coeffs(self._h, coeffs.data_ptr(), n, evecs.data_ptr(), mean.data_ptr(), out.data_ptr(),
+                                   _stream_ptr(coeffs.device)), self._h)
+        return out
+
+    def spca_reconstruct(self, c: torch.Tensor, evecs: torch.Tensor, mean: torch.Tensor,
+                         weights: torch.Tensor | None = None) -> torch.Tensor:
+        """a_{k,.} = U^(k) (w_k c_{k,.}) + m [k = 0]; float32 [n, p_half, 2]."""
+        n = c.shape[0]
+        _need(c, torch.float32, (n, self.p_half, 2), "c")
+        _need(evecs, torch.float64, (self.cov_size,), "evecs")
+        _need(mean, torch.float64, (self.p0,), "mean")
+        if weights is not None:
+            _need(weights, torch.float64, (self.p_half,), "weights")
+        out = torch.empty_like(c)
+        check(lib().fb_spca_reconstruct(self._h, c.data_ptr(), n, evecs.data_ptr(), mean.data_ptr(),
+                                        weights.data_ptr() if weights is not None else None, out.data_ptr(),
+                                        _stream_ptr(c.device)), self._h)
+        return out
+
+    def spca_radial(self, evecs: torch.Tensor) -> torch.Tensor:
+        """Radial parts f^{k,l}(xi_j) of the steerable principal components (Eq.(sPCArad)), float32
+        [n_xi * p_half]: block k at n_xi * coef_off[k], [n_xi][p_k]."""
+        _need(evecs, torch.float64, (self.cov_size,), "evecs")
+        f = torch.empty(self.n_xi * self.p_half, dtype=torch.float32, device=evecs.device)
+        check(lib().fb_spca_radial(self._h, evecs.data_ptr(), f.data_ptr(), _stream_ptr(evecs.device)), self._h)
+        return f
+
+    def radial_blocks(self, f: torch.Tensor | np.ndarray):
+        return [f[self.n_xi * self.coef_off[k]:self.n_xi * self.coef_off[k + 1]].reshape(self.n_xi, self.p[k])
+                for k in range(self.k_max + 1)]
+
     # -- per-kernel timing ---------------------------------------------------
     def profile(self, enable: bool = True):
         check(lib().fb_profile_enable(self._h, 1 if enable else 0))
