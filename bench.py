@@ -252,9 +252,30 @@ def main():
     # eigendecomposition of the accumulated covariance (outside images/s)
     torch.cuda.synchronize()
     te = time.perf_counter()
-    plan.eig(st)
+    evals, evecs, _, mean = plan.eig(st)
     torch.cuda.synchronize()
     eig_ms = 1e3 * (time.perf_counter() - te)
+
+    # steerable-PCA back end (outside images/s): selection with the workload's noise variance,
+    # sPCA coefficients of every image, filtered reconstruction of their FB coefficients
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        r = fn()
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    n_sel, w = plan.spca_select(evals, args.n, sigma * sigma)
+    plan.spca_coeffs(coeffs[:64], evecs, mean)  # warm-up
+    cs, c_ms = timed(lambda: plan.spca_coeffs(coeffs, evecs, mean))
+    _, r_ms = timed(lambda: plan.spca_reconstruct(cs, evecs, mean, w))
+    del cs
+    spca_bytes = 2 * 8 * plan.p_half * args.n
+    spca = {"selected_components": int(n_sel.sum().item()), "coeffs_ms": round(c_ms, 3),
+            "reconstruct_ms": round(r_ms, 3), "coeffs_images_per_s": round(args.n / (c_ms * 1e-3), 1),
+            "coeffs_hbm_GBps": round(spca_bytes / (c_ms * 1e-3) / 1e9, 1)}
+    log(f"spca back end: {spca}")
 
     # per-kernel figures of the headline form; dominant kernel against the HBM roofline
     prof = profs[head]
@@ -321,6 +342,7 @@ def main():
         "stages": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                    for k, v in stages.items()},
         "eig_ms": round(eig_ms, 2),
+        "spca": spca,
         "plan_s": round(plan_s, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
