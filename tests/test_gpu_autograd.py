@@ -67,3 +67,40 @@ def test_gradient_matches_central_differences(L, n):
         print(f"  direction {t}: finite difference {fd:.8e} autograd {an:.8e} err/scale "
               f"{abs(fd - an) / scale:.2e}", flush=True)
         assert abs(fd - an) <= 1e-4 * scale
+
+
+def test_gradient_at_full_size():
+    # the differentiation configuration's shape: L = 128 and 64 images, the images and the
+    # clean references generated on the device from the seed (no oracle is involved: both
+    # sides of the check are the library's own gradient and loss)
+    from paper_1412_0781_amd.workload import noise_sigma, synthetic_images
+    L, n, seed, snr = 128, 64, 13, 1 / 20
+    print(f"[autograd] L={L} n={n} (device inputs)", flush=True)
+    plan = Plan(L, 0.5, L / 2)
+    noisy = synthetic_images(plan, 0, n, seed, snr)
+    a = synth.random_coefficients(seed, np.arange(n), plan.k.astype(np.int64), plan.q.astype(np.int64))
+    at = torch.tensor(np.stack([a.real, a.imag], -1).astype(np.float32), device="cuda")
+    Ic = plan.adjoint(at)
+    v = synth.coef_variance(plan.k.astype(np.float64), plan.q.astype(np.float64))
+    sigma2 = noise_sigma(plan, snr) ** 2
+    H = torch.tensor((v / (v + sigma2)).astype(np.float32), device="cuda")[None, :, None]
+
+    def loss(I):
+        rec = fb_synth(fb_expand(I, plan) * H, plan)
+        return ((rec.double() - Ic.double()) ** 2).sum()
+
+    I = noisy.clone().requires_grad_(True)
+    loss(I).backward()
+    grad = I.grad.double()
+    step = 1e-3
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    dirs = [(grad / grad.pow(2).mean().sqrt()).float(),
+            torch.randn(noisy.shape, generator=gen, device="cuda")]
+    for t, d in enumerate(dirs):
+        with torch.no_grad():
+            fd = (float(loss(I.detach() + step * d)) - float(loss(I.detach() - step * d))) / (2 * step)
+        an = float((grad * d.double()).sum())
+        scale = abs(an) if t == 0 else max(abs(an), float(grad.norm() * d.double().norm()) / np.sqrt(noisy.numel()))
+        print(f"  direction {t}: finite difference {fd:.8e} autograd {an:.8e} err/scale "
+              f"{abs(fd - an) / scale:.2e}", flush=True)
+        assert abs(fd - an) <= 1e-4 * scale

@@ -166,3 +166,57 @@ def test_single_pixel_closed_form():
         ph = -2 * mpmath.pi * (mpmath.mpf(xi1[j, l]) * x[r] + mpmath.mpf(xi2[j, l]) * x[c])
         want = complex(mpmath.cos(ph), mpmath.sin(ph))
         assert abs(F[j, l] - want) <= 1e-13
+
+
+def test_brute_force_8x8_in_mpmath():
+    # Algorithm 1 for an 8 x 8 image evaluated from scratch at 30 digits: Bessel roots,
+    # normalisations, Gauss-Legendre nodes and weights, the polar Fourier sum, the angular
+    # sum and the radial quadrature all in mpmath; only the (k, q) list comes from the oracle
+    with mpmath.workdps(30):
+        _brute_force_8x8()
+
+
+def _brute_force_8x8():
+    L, c, R = 8, 0.5, 4.0
+    po = oracle.plan(L, c, R)
+    rng = np.random.default_rng(8)
+    img = rng.standard_normal((L, L))
+    got = oracle.expand(img[None], po)[0]
+    mc = mpmath.mpf(c)
+    nxi, nth = po.n_xi, po.n_theta
+    # Gauss-Legendre on [-1, 1] by Newton on P_n, then mapped to [0, c]
+    nodes, weights = [], []
+    for i in range(1, nxi + 1):
+        x = mpmath.cos(mpmath.pi * (i - mpmath.mpf(1) / 4) / (nxi + mpmath.mpf(1) / 2))
+        for _ in range(50):
+            p0, p1 = mpmath.mpf(1), x
+            for m in range(2, nxi + 1):
+                p0, p1 = p1, ((2 * m - 1) * x * p1 - (m - 1) * p0) / m
+            dp = nxi * (x * p1 - p0) / (x * x - 1)
+            dx = p1 / dp
+            x -= dx
+            if abs(dx) < mpmath.mpf(10) ** -28:
+                break
+        nodes.append(mc * (x + 1) / 2)
+        weights.append(mc / ((1 - x * x) * dp * dp))
+    pix = [mpmath.mpf(v) for v in oracle.pixel_coords(L)]
+    F = {}
+    for j in range(nxi):
+        for l in range(nth):
+            th = 2 * mpmath.pi * l / nth
+            u1, u2 = nodes[j] * mpmath.cos(th), nodes[j] * mpmath.sin(th)
+            F[j, l] = mpmath.fsum(img[a, b] * mpmath.expjpi(-2 * (u1 * pix[a] + u2 * pix[b]))
+                                  for a in range(L) for b in range(L))
+    want = np.zeros(po.p_half, complex)
+    for idx, (k, q) in enumerate(po.kq):
+        k, q = int(k), int(q)
+        root = mpmath.besseljzero(k, q)
+        norm = 1 / (mc * mpmath.sqrt(mpmath.pi) * abs(mpmath.besselj(k + 1, root)))
+        s = mpmath.mpc(0)
+        for j in range(nxi):
+            fh = 2 * mpmath.pi / nth * mpmath.fsum(F[j, l] * mpmath.expjpi(-2 * mpmath.mpf(k * l) / nth)
+                                                   for l in range(nth))
+            s += norm * mpmath.besselj(k, root * nodes[j] / mc) * fh * nodes[j] * weights[j]
+        want[idx] = complex(s)
+    want[:po.p[0]] = want[:po.p[0]].real
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
