@@ -277,6 +277,13 @@ def main():
             "coeffs_hbm_GBps": round(spca_bytes / (c_ms * 1e-3) / 1e9, 1)}
     log(f"spca back end: {spca}")
 
+    # adjoint synthesis T a (the differentiation and reconstruction path), outside images/s
+    na = min(args.n, 16384)
+    plan.adjoint(coeffs[:64], batch=args.pass_images)  # warm-up
+    _, adj_ms = timed(lambda: plan.adjoint(coeffs[:na], batch=args.pass_images))
+    adjoint = {"images": na, "ms": round(adj_ms, 3), "images_per_s": round(na / (adj_ms * 1e-3), 1)}
+    log(f"adjoint: {adjoint}")
+
     # per-kernel figures of the headline form; dominant kernel against the HBM roofline
     prof = profs[head]
     bpi = algorithmic_bytes_per_image(plan)
@@ -343,6 +350,7 @@ def main():
                    for k, v in stages.items()},
         "eig_ms": round(eig_ms, 2),
         "spca": spca,
+        "adjoint": adjoint,
         "plan_s": round(plan_s, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,

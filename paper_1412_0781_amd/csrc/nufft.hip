@@ -568,28 +568,30 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
 }
 
 // ---------------------------------------------------------------------------
-// adjoint angular: D [K+1][n_xi][ncol] -> Q [n][n_xi][H]
+// adjoint angular: D [K+1][n_xi][ncol] -> Q [n_xi][group][H][16] (grouped like P)
 // Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H}),  s'_t = Re sum_{k<=K} E_k e^{2 pi i k t / n_theta},
-// E_k = c D_k (k even), -i c D_k (k odd)
+// E_k = c D_k (k even), -i c D_k (k odd).  Images vary fastest in both loops (coalesced
+// reads of D and writes of Q); transforms padded to H+1.
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__ Q, FftDesc fd,
                               const float2* __restrict__ tw, const float2* __restrict__ angtw, int n_xi, int K,
-                              int nimg, int AG, float scale) {
+                              int nimg, int ngrp, int AG, float scale) {
   extern __shared__ float2 sm[];
-  const int H = fd.n;
+  const int H = fd.n, S = H + 1;
   float2* buf = sm;
-  float2* tmp = sm + AG * H;
+  float2* tmp = sm + AG * S;
   const int j = blockIdx.x;
   const int g0 = blockIdx.y * AG;
-  const int ng = min(AG, nimg - g0);
+  const int ng = min(AG, ngrp * kImgGroup - g0);  // slots past nimg read zeros
   auto Ek = [&](int k, int gg) -> float2 {
+    if (g0 + gg >= nimg) return make_float2(0.f, 0.f);
     float2 d = D[((size_t)k * n_xi + j) * nimg + g0 + gg];
     return (k & 1) ? make_float2(d.y * scale, -d.x * scale) : make_float2(d.x * scale, d.y * scale);
   };
   // Zin(k') = (Y_k' + Y_{k'+H}) + i e^{+i pi k'/H} (Y_k' - Y_{k'+H}); stored conjugated for the forward FFT
   for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
-    int gg = i / H, kp = i - gg * H;
+    int kp = i / ng, gg = i - kp * ng;
     float2 y0 = make_float2(0.f, 0.f), y1 = make_float2(0.f, 0.f);
     if (kp == 0) {
       y0 = make_float2(Ek(0, gg).x, 0.f);
@@ -605,88 +607,175 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
     float2 ze = cadd(y0, y1);
     float2 zo = cmul(cconj(angtw[kp]), csub(y0, y1));
     float2 zin = make_float2(ze.x - zo.y, ze.y + zo.x);
-    buf[gg * H + kp] = cconj(zin);
+    buf[gg * S + kp] = cconj(zin);
   }
   __syncthreads();
-  float2* res = run_fft<FORM>(buf, tmp, ng, H, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, ng, S, fd, tw);
   // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1}
   for (int i = threadIdx.x; i < ng * H; i += blockDim.x) {
-    int gg = i / H, l = i - gg * H;
+    int l = i / ng, gg = i - l * ng;
     auto sp = [&](int t) -> float {
-      float2 z = res[gg * H + (t >> 1)];
+      float2 z = res[gg * S + (t >> 1)];
       return (t & 1) ? -z.y : z.x;
     };
     float a = sp(l), b = sp(l + H);
-    Q[((size_t)(g0 + gg) * n_xi + j) * H + l] = make_float2(a + b, a - b);
+    const int sl = g0 + gg;
+    Q[(((size_t)j * ngrp + sl / kImgGroup) * H + l) * kImgGroup + (sl & (kImgGroup - 1))] = make_float2(a + b, a - b);
   }
 }
 
 // ---------------------------------------------------------------------------
-// adjoint spread (gather form): Q [n][n_xi*H] -> Y [n][N/2+1][N]
-// one wavefront per grid point, lanes split its entries, fixed-order reduction
+// adjoint spread (gather form, tiled): Q [n_xi][group][H][16] -> Y [N/2+1][group][N][16]
+// workgroup = (cell of kSpreadCell^2 output points, one of its nsub workgroups, slice of
+// kSpreadSlice image groups); it walks its (image group, chunk) steps with the next step's
+// node values (one 128-byte line per node: 16 images) and, when the chunk changes, entries
+// already on their way into registers.  Per step the values and entries sit in LDS and
+// lane (point, image pair) sums the point's entries in their fixed order, so the result is
+// the same on every run.  A point's entries come in aligned batches of kSpreadBatch.
 // ---------------------------------------------------------------------------
-template <int IG>
-__global__ void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y, const int* __restrict__ ptr,
-                             const SpreadEntry* __restrict__ ent, int nrows, int nnodes, int nimg) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= nrows) return;
-  const int i0 = blockIdx.y * IG;
-  const int ni = min(IG, nimg - i0);
-  float ax[IG], ay[IG];
+template <int C, int NT>
+__global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y,
+                                                      const SpreadTile* __restrict__ tiles,
+                                                      const SpreadBlock* __restrict__ blocks,
+                                                      const SpreadChunk* __restrict__ chunks,
+                                                      const int* __restrict__ snodes, const int* __restrict__ sseg,
+                                                      const SpreadLocal* __restrict__ sent, int N, int Nh, int H,
+                                                      int ngrp, int nsl) {
+  constexpr int G = kImgGroup, IP = G / 2, PC = C * C;
+  constexpr int KQ = kSpreadNodes * IP / NT, KE = kSpreadEntries / 2 / NT;
+  static_assert(NT == PC * IP, "one lane per (point, image pair)");
+  static_assert(KQ * NT == kSpreadNodes * IP && KE * NT * 2 == kSpreadEntries, "staging slots per lane");
+  static_assert(sizeof(SpreadLocal) == 8 && kSpreadBatch == 8, "a batch is four 16-byte vectors");
+  __shared__ __attribute__((aligned(16))) float4 s_q[kSpreadNodes * IP];
+  __shared__ __attribute__((aligned(16))) uint4 s_e[kSpreadEntries / 2];
+  const int tid = threadIdx.x, ip = tid & (IP - 1), p = tid / IP;
+  const int slice = (int)(blockIdx.x % (unsigned)nsl);
+  const SpreadBlock bk = blocks[blockIdx.x / (unsigned)nsl];
+  const SpreadTile t = tiles[bk.tile];
+  const int nch = t.c1 - t.c0;
+  const int gb = slice * kSpreadSlice + bk.sub, ge = min(ngrp, (slice + 1) * kSpreadSlice);
+  const int m2 = t.m2 + p / C, m1 = t.m1 + p % C;
+  const bool out = m2 < Nh && m1 < N;
+  float4* Y4 = (float4*)Y;
+  auto yidx = [&](int g) { return (((size_t)m2 * ngrp + g) * N + m1) * IP + ip; };
+  if (nch == 0) {  // no node reaches this cell
+    for (int g = gb; g < ge; g += t.nsub)
+      if (out) Y4[yidx(g)] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const int ng = gb < ge ? (ge - gb + t.nsub - 1) / t.nsub : 0;
+  const int nsteps = ng * nch;
+  const float4* Q4 = (const float4*)Q;
+  const uint4* E4 = (const uint4*)sent;
+  const size_t gstride = (size_t)H * IP;  // float4s between image groups of one node
+  // next step's chunk data, held in registers
+  int nl_n = 0, ne_n = 0, e0_n = 0, e1_n = 0;
+  size_t qoff[KQ];
+  uint4 er[KE];
+  float4 qr[KQ];
+  auto load_meta = [&](int c) {
+    const SpreadChunk ch = chunks[c];
+    nl_n = ch.n1 - ch.n0;
+    const int base = sseg[ch.seg];
+    ne_n = sseg[ch.seg + PC] - base;
+    e0_n = sseg[ch.seg + p] - base;
+    e1_n = sseg[ch.seg + p + 1] - base;
 #pragma unroll
-  for (int g = 0; g < IG; ++g) ax[g] = ay[g] = 0.f;
-  const int e0 = ptr[row], e1 = ptr[row + 1];
-  for (int e = e0 + lane; e < e1; e += 64) {
-    SpreadEntry en = ent[e];
-    uint32_t nd = en.node & 0x7fffffffu;
-    float sg = (en.node & 0x80000000u) ? -1.f : 1.f;
+    for (int k = 0; k < KE; ++k) {
+      const int i = tid + k * NT;
+      if (i < ne_n / 2) er[k] = E4[base / 2 + i];
+    }
 #pragma unroll
-    for (int g = 0; g < IG; ++g) {
-      if (g < ni) {
-        float2 q = Q[(size_t)(i0 + g) * nnodes + nd];
-        ax[g] = fmaf(en.weight, q.x, ax[g]);
-        ay[g] = fmaf(en.weight * sg, q.y, ay[g]);
+    for (int k = 0; k < KQ; ++k) {
+      const int i = tid + k * NT;
+      qoff[k] = 0;
+      if (i < nl_n * IP) {
+        const int jl = snodes[ch.n0 + i / IP];
+        qoff[k] = ((size_t)(jl >> 16) * ngrp * H + (jl & 0xffff)) * IP + (i & (IP - 1));
       }
     }
+  };
+  auto load_q = [&](int g) {
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+      if (tid + k * NT < nl_n * IP) qr[k] = Q4[qoff[k] + (size_t)g * gstride];
+  };
+  float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+  auto acc = [&](unsigned key, unsigned wbits) {
+    const float4 q = s_q[(key & 0xffffu) * IP + ip];
+    const float w = __uint_as_float(wbits), wy = (key >> 16) ? -w : w;
+    ax0 = fmaf(w, q.x, ax0);
+    ay0 = fmaf(wy, q.y, ay0);
+    ax1 = fmaf(w, q.z, ax1);
+    ay1 = fmaf(wy, q.w, ay1);
+  };
+  if (nsteps > 0) {
+    load_meta(t.c0);
+    load_q(gb);
   }
+  for (int s = 0; s < nsteps; ++s) {
+    const int ci = s % nch;
+    const int g = gb + (s / nch) * t.nsub;
+    __syncthreads();  // the previous step's readers are done with LDS
 #pragma unroll
-  for (int g = 0; g < IG; ++g) {
+    for (int k = 0; k < KQ; ++k)
+      if (tid + k * NT < nl_n * IP) s_q[tid + k * NT] = qr[k];
+    if (nch > 1 || s == 0) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      ax[g] += __shfl_xor(ax[g], off, 64);
-      ay[g] += __shfl_xor(ay[g], off, 64);
+      for (int k = 0; k < KE; ++k)
+        if (tid + k * NT < ne_n / 2) s_e[tid + k * NT] = er[k];
     }
-  }
-  if (lane == 0) {
-    for (int g = 0; g < ni; ++g) Y[(size_t)(i0 + g) * nrows + row] = make_float2(ax[g], ay[g]);
+    const int e0 = e0_n, e1 = e1_n;
+    __syncthreads();
+    const bool more = s + 1 < nsteps;
+    const int gn = ci + 1 == nch ? g + t.nsub : g;
+    if (more) {
+      if (nch == 1) load_q(gn);
+      else load_meta(t.c0 + (ci + 1 == nch ? 0 : ci + 1));
+    }
+    if (ci == 0) ax0 = ay0 = ax1 = ay1 = 0.f;
+    for (int e = e0 / 2; e < e1 / 2; e += kSpreadBatch / 2) {
+      uint4 v[kSpreadBatch / 2];
+#pragma unroll
+      for (int u = 0; u < kSpreadBatch / 2; ++u) v[u] = s_e[e + u];
+#pragma unroll
+      for (int u = 0; u < kSpreadBatch / 2; ++u) {
+        acc(v[u].x, v[u].y);
+        acc(v[u].z, v[u].w);
+      }
+    }
+    if (more && nch > 1) load_q(gn);
+    if (ci == nch - 1 && out) Y4[yidx(g)] = make_float4(ax0, ay0, ax1, ay1);
   }
 }
 
 // ---------------------------------------------------------------------------
-// adjoint cols: Y [n][N/2+1][N] -> Zc [n][N/2+1][L]: inverse FFT along m1, keep x1 in the pixel range
+// adjoint cols: Y [N/2+1][group][N][16] -> Zc [n][N/2+1][L]: inverse FFT along m1, keep x1 in
+// the pixel range.  workgroup = (row m2, CP consecutive image slots); transforms padded to N+1
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_adj_cols(const float2* __restrict__ Y, float2* __restrict__ Zc, FftDesc fd,
-                           const float2* __restrict__ tw, int L, int CP) {
+                           const float2* __restrict__ tw, int L, int nimg, int ngrp, int CP) {
   extern __shared__ float2 sm[];
-  const int N = fd.n, Nh = N / 2 + 1;
+  const int N = fd.n, Nh = N / 2 + 1, S = N + 1;
   float2* buf = sm;
-  float2* tmp = sm + CP * N;
-  const int im = blockIdx.y;
-  const int r0 = blockIdx.x * CP;
-  const int nc = min(CP, Nh - r0);
-  const float2* src = Y + ((size_t)im * Nh + r0) * N;
-  for (int i = threadIdx.x; i < nc * N; i += blockDim.x) buf[i] = cconj(src[i]);
+  float2* tmp = sm + CP * S;
+  const int m2 = blockIdx.y;
+  const int i0 = blockIdx.x * CP;
+  const int nc = min(CP, nimg - i0);
+  // slot i0 + c of row m2: group (i0 + c) / 16, lane (i0 + c) % 16; slots vary fastest
+  for (int i = threadIdx.x; i < nc * N; i += blockDim.x) {
+    const int m1 = i / nc, c = i - m1 * nc, sl = i0 + c;
+    buf[c * S + m1] = cconj(Y[(((size_t)m2 * ngrp + sl / kImgGroup) * N + m1) * kImgGroup + (sl & (kImgGroup - 1))]);
+  }
   __syncthreads();
-  float2* res = run_fft<FORM>(buf, tmp, nc, N, fd, tw);
+  float2* res = run_fft<FORM>(buf, tmp, nc, S, fd, tw);
   const int x0 = -((L - 1 + 1) / 2);
-  float2* dst = Zc + ((size_t)im * Nh + r0) * L;
   for (int i = threadIdx.x; i < nc * L; i += blockDim.x) {
     int cidx = i / L, a = i - cidx * L;
     int pos = x0 + a;
     pos += (pos < 0) ? N : 0;
-    dst[(size_t)cidx * L + a] = cconj(res[cidx * N + pos]);
+    Zc[((size_t)(i0 + cidx) * Nh + m2) * L + a] = cconj(res[cidx * S + pos]);
   }
 }
 
@@ -870,12 +959,13 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
 }
 
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st) {
-  FftLaunch fa = fft_launch(pl.fft_ang, pl.H);
-  dim3 g((unsigned)pl.n_xi, (unsigned)((nimg + fa.count - 1) / fa.count));
+  const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
+  FftLaunch fa = fft_launch(pl.fft_ang, pl.H + 1);
+  dim3 g((unsigned)pl.n_xi, (unsigned)((ngrp * kImgGroup + fa.count - 1) / fa.count));
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
   pl.prof.begin(ST_ADJ_ANGULAR, st);
   FB_LAUNCH_FFT(k_adj_angular, fa.form, g, dim3(kFftThreads), fa.lds, st, D, Q, pl.fft_ang, pl.d_tw, pl.d_angtw,
-                pl.n_xi, pl.k_max, nimg, fa.count, scale);
+                pl.n_xi, pl.k_max, nimg, ngrp, fa.count, scale);
   pl.prof.end(st);
   return hipGetLastError();
 }
@@ -883,19 +973,20 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
 hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
                                 float* images, hipStream_t st) {
   const int N = pl.N, L = pl.L, Nh = N / 2 + 1;
-  const int nrows = N * Nh;
-  const int nnodes = pl.n_xi * pl.H;
-  constexpr int IG = 4;
-  dim3 g1((unsigned)((nrows + 3) / 4), (unsigned)((nimg + IG - 1) / IG));
+  const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
+  constexpr int C = kSpreadCell, NT = kSpreadCell * kSpreadCell * kImgGroup / 2;
+  const int nsl = (ngrp + kSpreadSlice - 1) / kSpreadSlice;
+  const size_t nblk = pl.sblocks.size() * (size_t)nsl;
+  if (nblk > 0x7fffffffu) return hipErrorInvalidValue;
   pl.prof.begin(ST_ADJ_SPREAD, st);
-  hipLaunchKernelGGL(k_adj_spread<IG>, g1, dim3(256), 0, st, Q, bufB, pl.d_csr_ptr, pl.d_csr, nrows, nnodes,
-                     nimg);
+  hipLaunchKernelGGL((k_adj_spread<C, NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
+                     pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sent, N, Nh, pl.H, ngrp, nsl);
   pl.prof.end(st);
-  FftLaunch fc = fft_launch(pl.fft_grid, N);
-  dim3 g2((unsigned)((Nh + fc.count - 1) / fc.count), (unsigned)nimg);
+  FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
+  dim3 g2((unsigned)((nimg + fc.count - 1) / fc.count), (unsigned)Nh);
   pl.prof.begin(ST_ADJ_COLS, st);
-  FB_LAUNCH_FFT(k_adj_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufB, bufA, pl.fft_grid, pl.d_tw, L,
-                fc.count);
+  FB_LAUNCH_FFT(k_adj_cols, fc.form, g2, dim3(kFftThreads), fc.lds, st, bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg,
+                ngrp, fc.count);
   pl.prof.end(st);
   FftLaunch fr = fft_launch(pl.fft_grid, N);
   dim3 g3((unsigned)(((L + 1) / 2 + fr.count - 1) / fr.count), (unsigned)nimg);

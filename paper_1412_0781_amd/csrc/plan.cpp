@@ -251,6 +251,99 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     pl.csr.resize(pl.csr_ptr[nrows]);
     std::vector<int> fill(pl.csr_ptr.begin(), pl.csr_ptr.end() - 1);
     for_each_tap([&](size_t row, uint32_t node, float om) { pl.csr[fill[row]++] = SpreadEntry{node, om}; });
+
+    // tiled form: per output cell, the distinct nodes of its points' entries in chunks
+    const int C = kSpreadCell, PC = C * C;
+    const int ncy = (Nh + C - 1) / C, ncx = (N + C - 1) / C;
+    pl.stiles.clear();
+    pl.sblocks.clear();
+    pl.schunks.clear();
+    pl.snodes.clear();
+    pl.sseg.clear();
+    pl.sent.clear();
+    pl.sent.reserve(pl.csr.size() + pl.csr.size() / 4);
+    std::vector<int> where(pl.nodes.size(), -1);  // node -> index in the cell's node list
+    std::vector<int> cell_nodes;
+    std::vector<std::vector<uint8_t>> node_pts;   // points reached by each listed node
+    std::vector<int> pcnt(PC);
+    auto padded = [](int n) { return (n + kSpreadBatch - 1) / kSpreadBatch * kSpreadBatch; };
+    for (int cy = 0; cy < ncy; ++cy)
+      for (int cx = 0; cx < ncx; ++cx) {
+        cell_nodes.clear();
+        for (int p = 0; p < PC; ++p) {
+          int m2 = cy * C + p / C, m1 = cx * C + p % C;
+          if (m2 >= Nh || m1 >= N) continue;
+          size_t row = (size_t)m2 * N + m1;
+          for (int e = pl.csr_ptr[row]; e < pl.csr_ptr[row + 1]; ++e) {
+            int nd = (int)(pl.csr[e].node & 0x7fffffffu);
+            if (where[nd] < 0) {
+              where[nd] = (int)cell_nodes.size();
+              cell_nodes.push_back(nd);
+              if (node_pts.size() < cell_nodes.size()) node_pts.resize(cell_nodes.size());
+              node_pts[where[nd]].clear();
+            }
+            node_pts[where[nd]].push_back((uint8_t)p);
+          }
+        }
+        SpreadTile t{cy * C, cx * C, (int)pl.schunks.size(), 0, 1, {0, 0, 0}};
+        const int nn = (int)cell_nodes.size();
+        for (int a0 = 0; a0 < nn;) {
+          // greedy chunk: as many nodes as fit kSpreadNodes and, padded, kSpreadEntries
+          std::fill(pcnt.begin(), pcnt.end(), 0);
+          int a1 = a0, total = 0;
+          while (a1 < nn && a1 - a0 < kSpreadNodes) {
+            int grow = 0;
+            for (uint8_t p : node_pts[a1]) {
+              grow += padded(pcnt[p] + 1) - padded(pcnt[p]);
+              pcnt[p]++;
+            }
+            if (total + grow > kSpreadEntries) {
+              for (uint8_t p : node_pts[a1]) pcnt[p]--;
+              break;
+            }
+            total += grow;
+            ++a1;
+          }
+          SpreadChunk ch{(int)pl.snodes.size(), 0, (int)pl.sseg.size(), 0};
+          for (int a = a0; a < a1; ++a) {
+            int nd = cell_nodes[a];
+            pl.snodes.push_back(((nd / pl.H) << 16) | (nd % pl.H));
+          }
+          ch.n1 = (int)pl.snodes.size();
+          for (int p = 0; p < PC; ++p) {
+            pl.sseg.push_back((int)pl.sent.size());
+            int m2 = cy * C + p / C, m1 = cx * C + p % C;
+            if (m2 >= Nh || m1 >= N) continue;
+            size_t row = (size_t)m2 * N + m1;
+            for (int e = pl.csr_ptr[row]; e < pl.csr_ptr[row + 1]; ++e) {
+              int nd = (int)(pl.csr[e].node & 0x7fffffffu);
+              int li = where[nd];
+              if (li < a0 || li >= a1) continue;
+              pl.sent.push_back(SpreadLocal{(uint16_t)(li - a0), (uint16_t)(pl.csr[e].node >> 31),
+                                            pl.csr[e].weight});
+            }
+            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0, 0, 0.f});
+          }
+          pl.sseg.push_back((int)pl.sent.size());
+          pl.schunks.push_back(ch);
+          a0 = a1;
+        }
+        t.c1 = (int)pl.schunks.size();
+        t.nsub = std::max(1, std::min(kSpreadSlice, t.c1 - t.c0));
+        pl.stiles.push_back(t);
+        for (int nd : cell_nodes) where[nd] = -1;
+      }
+    // workgroups of one slice: cells with the most chunks first, then in grid order
+    std::vector<int> order(pl.stiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return pl.stiles[x].c1 - pl.stiles[x].c0 > pl.stiles[y].c1 - pl.stiles[y].c0;
+    });
+    for (int ti : order)
+      for (int r = 0; r < pl.stiles[ti].nsub; ++r) pl.sblocks.push_back(SpreadBlock{ti, r});
+    // the tiled form replaces the per-point lists
+    std::vector<int>().swap(pl.csr_ptr);
+    std::vector<SpreadEntry>().swap(pl.csr);
   }
 
   // grouped-GEMM work items
@@ -307,8 +400,12 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_gitems, pl.gitems.data(), pl.gitems.size()));
   FB_HIP_TRY(upload(&pl.d_tw, (const float2*)pl.tw.data(), pl.tw.size() / 2));
   FB_HIP_TRY(upload(&pl.d_angtw, (const float2*)pl.angtw.data(), pl.angtw.size() / 2));
-  FB_HIP_TRY(upload(&pl.d_csr_ptr, pl.csr_ptr.data(), pl.csr_ptr.size()));
-  FB_HIP_TRY(upload(&pl.d_csr, pl.csr.data(), pl.csr.size()));
+  FB_HIP_TRY(upload(&pl.d_stiles, pl.stiles.data(), pl.stiles.size()));
+  FB_HIP_TRY(upload(&pl.d_sblocks, pl.sblocks.data(), pl.sblocks.size()));
+  FB_HIP_TRY(upload(&pl.d_schunks, pl.schunks.data(), pl.schunks.size()));
+  FB_HIP_TRY(upload(&pl.d_snodes, pl.snodes.data(), pl.snodes.size()));
+  FB_HIP_TRY(upload(&pl.d_sseg, pl.sseg.data(), pl.sseg.size()));
+  FB_HIP_TRY(upload(&pl.d_sent, pl.sent.data(), pl.sent.size()));
   FB_HIP_TRY(upload(&pl.d_items_fwd, pl.items_fwd.data(), pl.items_fwd.size()));
   FB_HIP_TRY(upload(&pl.d_items_adj, pl.items_adj.data(), pl.items_adj.size()));
   FB_HIP_TRY(upload(&pl.d_items_cov, pl.items_cov.data(), pl.items_cov.size()));
@@ -321,8 +418,8 @@ void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
   void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_coef_off,  pl.d_p,         pl.d_cov_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
-                  pl.d_csr_ptr,   pl.d_csr,       pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov,
-                  pl.d_items_spca};
+                  pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
+                  pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
@@ -333,8 +430,12 @@ void free_device(Plan& pl) {
   pl.d_gnodes = nullptr;
   pl.d_gitems = nullptr;
   pl.d_tw = pl.d_angtw = nullptr;
-  pl.d_csr_ptr = nullptr;
-  pl.d_csr = nullptr;
+  pl.d_stiles = nullptr;
+  pl.d_sblocks = nullptr;
+  pl.d_schunks = nullptr;
+  pl.d_snodes = nullptr;
+  pl.d_sseg = nullptr;
+  pl.d_sent = nullptr;
   pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = pl.d_items_spca = nullptr;
   pl.has_device = false;
 }

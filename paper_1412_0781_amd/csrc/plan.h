@@ -88,6 +88,40 @@ struct SpreadEntry {
   uint32_t node;
   float weight;
 };
+// Tiled adjoint spread: the folded half-plane grid is cut into kSpreadCell x kSpreadCell
+// output cells.  The nodes that reach a cell are listed once (packed j << 16 | l) and
+// split into chunks of at most kSpreadNodes nodes and kSpreadEntries entries; a workgroup
+// stages one chunk's node values (one image group) and entries in LDS, and every output
+// point sums its entries of that chunk (local index, weight, conjugate flag), in the order
+// of the point's spreading entries.  Each point's entries of a chunk are padded with
+// zero-weight entries to a multiple of kSpreadBatch, so that they are read in aligned
+// batches.  A cell with several chunks is split over nsub workgroups per slice of
+// kSpreadSlice image groups (workgroup r of the cell takes groups r, r + nsub, ...).
+constexpr int kSpreadCell = 8;
+constexpr int kSpreadNodes = 256;
+constexpr int kSpreadEntries = 6144;
+constexpr int kSpreadBatch = 8;
+constexpr int kSpreadSlice = 16;
+struct SpreadTile {
+  int m2, m1;    // cell origin (row m2 of the half plane, column m1)
+  int c0, c1;    // chunk range
+  int nsub;      // workgroups per slice of image groups
+  int pad[3];
+};
+struct SpreadBlock {
+  int tile;      // index into the cell list
+  int sub;       // 0 .. nsub-1
+};
+struct SpreadChunk {
+  int n0, n1;    // node range in the chunk node list
+  int seg;       // kSpreadCell^2 + 1 entry offsets of this chunk's points start here
+  int pad;
+};
+struct SpreadLocal {
+  uint16_t li;    // node index within the chunk
+  uint16_t conj;  // 1: the conjugate of the node value
+  float weight;
+};
 
 // Kernel stages, in launch order (names in stage_name()).
 enum Stage {
@@ -166,7 +200,13 @@ struct Plan {
   std::vector<float> tw;           // interleaved (re, im) twiddles of both FFT lengths
   std::vector<float> angtw;        // exp(-2 pi i k / n_theta), k = 0..H, interleaved
   std::vector<int> csr_ptr;        // N * (N/2 + 1) + 1
-  std::vector<SpreadEntry> csr;    // spreading entries
+  std::vector<SpreadEntry> csr;    // spreading entries, by grid point
+  std::vector<SpreadTile> stiles;  // tiled form of the same entries
+  std::vector<SpreadBlock> sblocks; // workgroups of one image-group slice, heaviest cells first
+  std::vector<SpreadChunk> schunks;
+  std::vector<int> snodes;         // j << 16 | l
+  std::vector<int> sseg;
+  std::vector<SpreadLocal> sent;
   std::vector<GemmItem> items_fwd, items_adj, items_cov, items_spca;
   int bm = 64, bn = 64;            // GEMM tile
 
@@ -186,8 +226,12 @@ struct Plan {
   GatherItem* d_gitems = nullptr;
   float2* d_tw = nullptr;
   float2* d_angtw = nullptr;
-  int* d_csr_ptr = nullptr;
-  SpreadEntry* d_csr = nullptr;
+  SpreadTile* d_stiles = nullptr;
+  SpreadBlock* d_sblocks = nullptr;
+  SpreadChunk* d_schunks = nullptr;
+  int* d_snodes = nullptr;
+  int* d_sseg = nullptr;
+  SpreadLocal* d_sent = nullptr;
   GemmItem* d_items_fwd = nullptr;
   GemmItem* d_items_adj = nullptr;
   GemmItem* d_items_cov = nullptr;
