@@ -627,11 +627,13 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
 // ---------------------------------------------------------------------------
 // adjoint spread (gather form, tiled): Q [n_xi][group][H][16] -> Y [N/2+1][group][N][16]
 // workgroup = (cell of kSpreadCell^2 output points, one of its nsub workgroups, slice of
-// kSpreadSlice image groups); it walks its (image group, chunk) steps with the next step's
-// node values (one 128-byte line per node: 16 images) and, when the chunk changes, entries
-// already on their way into registers.  Per step the values and entries sit in LDS and
+// kSpreadSlice image groups); it walks its (chunk, image group) steps, chunks outer, with
+// the next step's node values (one 128-byte line per node: 16 images) and, when the chunk
+// changes, entries on their way into registers.  A cell of several chunks keeps the partial
+// sums of its (at most kSpreadHeavyGroups) image groups in registers, added in chunk order.  Per step the values and entries sit in LDS and
 // lane (point, image pair) sums the point's entries in their fixed order, so the result is
 // the same on every run.  A point's entries come in aligned batches of kSpreadBatch.
+// Spreading weights are non-negative, so an entry carries the conjugate flag as its sign.
 // ---------------------------------------------------------------------------
 template <int C, int NT>
 __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y,
@@ -646,6 +648,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   static_assert(NT == PC * IP, "one lane per (point, image pair)");
   static_assert(KQ * NT == kSpreadNodes * IP && KE * NT * 2 == kSpreadEntries, "staging slots per lane");
   static_assert(sizeof(SpreadLocal) == 8 && kSpreadBatch == 8, "a batch is four 16-byte vectors");
+  static_assert(kSpreadHeavyGroups == 4, "four partial-sum registers");
   __shared__ __attribute__((aligned(16))) float4 s_q[kSpreadNodes * IP];
   __shared__ __attribute__((aligned(16))) uint4 s_e[kSpreadEntries / 2];
   const int tid = threadIdx.x, ip = tid & (IP - 1), p = tid / IP;
@@ -663,6 +666,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
       if (out) Y4[yidx(g)] = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
+  // image groups of this workgroup; a cell of several chunks has nsub >= 4, so ng <= 4
   const int ng = gb < ge ? (ge - gb + t.nsub - 1) / t.nsub : 0;
   const int nsteps = ng * nch;
   const float4* Q4 = (const float4*)Q;
@@ -701,39 +705,39 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
       if (tid + k * NT < nl_n * IP) qr[k] = Q4[qoff[k] + (size_t)g * gstride];
   };
   float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
-  auto acc = [&](unsigned key, unsigned wbits) {
-    const float4 q = s_q[(key & 0xffffu) * IP + ip];
-    const float w = __uint_as_float(wbits), wy = (key >> 16) ? -w : w;
+  // entry: byte offset of the node row in s_q, weight signed by the conjugate flag
+  const char* s_lane = (const char*)s_q + ip * sizeof(float4);
+  auto acc = [&](unsigned off, unsigned wbits) {
+    const float4 q = *(const float4*)(s_lane + off);
+    const float ws = __uint_as_float(wbits), w = fabsf(ws);
     ax0 = fmaf(w, q.x, ax0);
-    ay0 = fmaf(wy, q.y, ay0);
+    ay0 = fmaf(ws, q.y, ay0);
     ax1 = fmaf(w, q.z, ax1);
-    ay1 = fmaf(wy, q.w, ay1);
+    ay1 = fmaf(ws, q.w, ay1);
   };
   if (nsteps > 0) {
     load_meta(t.c0);
     load_q(gb);
   }
+  float4 P0 = make_float4(0.f, 0.f, 0.f, 0.f), P1 = P0, P2 = P0, P3 = P0;
   for (int s = 0; s < nsteps; ++s) {
-    const int ci = s % nch;
-    const int g = gb + (s / nch) * t.nsub;
+    const int ci = s / ng, gi = s - ci * ng;
+    const int g = gb + gi * t.nsub;
     __syncthreads();  // the previous step's readers are done with LDS
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
       if (tid + k * NT < nl_n * IP) s_q[tid + k * NT] = qr[k];
-    if (nch > 1 || s == 0) {
+    if (gi == 0) {
 #pragma unroll
       for (int k = 0; k < KE; ++k)
         if (tid + k * NT < ne_n / 2) s_e[tid + k * NT] = er[k];
     }
     const int e0 = e0_n, e1 = e1_n;
     __syncthreads();
-    const bool more = s + 1 < nsteps;
-    const int gn = ci + 1 == nch ? g + t.nsub : g;
-    if (more) {
-      if (nch == 1) load_q(gn);
-      else load_meta(t.c0 + (ci + 1 == nch ? 0 : ci + 1));
-    }
-    if (ci == 0) ax0 = ay0 = ax1 = ay1 = 0.f;
+    const bool same_chunk = gi + 1 < ng;
+    if (same_chunk) load_q(g + t.nsub);
+    else if (ci + 1 < nch) load_meta(t.c0 + ci + 1);
+    ax0 = ay0 = ax1 = ay1 = 0.f;
     for (int e = e0 / 2; e < e1 / 2; e += kSpreadBatch / 2) {
       uint4 v[kSpreadBatch / 2];
 #pragma unroll
@@ -744,8 +748,19 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
         acc(v[u].z, v[u].w);
       }
     }
-    if (more && nch > 1) load_q(gn);
-    if (ci == nch - 1 && out) Y4[yidx(g)] = make_float4(ax0, ay0, ax1, ay1);
+    if (!same_chunk && ci + 1 < nch) load_q(gb);
+    float4 r = make_float4(ax0, ay0, ax1, ay1);
+    if (nch > 1) {
+      auto upd = [&](float4& P) {
+        if (ci > 0) r = make_float4(P.x + r.x, P.y + r.y, P.z + r.z, P.w + r.w);
+        P = r;
+      };
+      if (gi == 0) upd(P0);
+      else if (gi == 1) upd(P1);
+      else if (gi == 2) upd(P2);
+      else upd(P3);
+    }
+    if (ci == nch - 1 && out) Y4[yidx(g)] = r;
   }
 }
 

@@ -319,17 +319,19 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
               int nd = (int)(pl.csr[e].node & 0x7fffffffu);
               int li = where[nd];
               if (li < a0 || li >= a1) continue;
-              pl.sent.push_back(SpreadLocal{(uint16_t)(li - a0), (uint16_t)(pl.csr[e].node >> 31),
-                                            pl.csr[e].weight});
+              const float wt = pl.csr[e].weight;
+              pl.sent.push_back(SpreadLocal{(uint32_t)(li - a0) * kImgGroup * 8u,
+                                            (pl.csr[e].node >> 31) ? -wt : wt});
             }
-            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0, 0, 0.f});
+            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0u, 0.f});
           }
           pl.sseg.push_back((int)pl.sent.size());
           pl.schunks.push_back(ch);
           a0 = a1;
         }
         t.c1 = (int)pl.schunks.size();
-        t.nsub = std::max(1, std::min(kSpreadSlice, t.c1 - t.c0));
+        const int nch = t.c1 - t.c0;
+        t.nsub = nch <= 1 ? 1 : std::min(kSpreadSlice, std::max(kSpreadSlice / kSpreadHeavyGroups, nch));
         pl.stiles.push_back(t);
         for (int nd : cell_nodes) where[nd] = -1;
       }

@@ -92,16 +92,19 @@ struct SpreadEntry {
 // output cells.  The nodes that reach a cell are listed once (packed j << 16 | l) and
 // split into chunks of at most kSpreadNodes nodes and kSpreadEntries entries; a workgroup
 // stages one chunk's node values (one image group) and entries in LDS, and every output
-// point sums its entries of that chunk (local index, weight, conjugate flag), in the order
+// point sums its entries of that chunk (LDS offset, signed weight), in the order
 // of the point's spreading entries.  Each point's entries of a chunk are padded with
 // zero-weight entries to a multiple of kSpreadBatch, so that they are read in aligned
-// batches.  A cell with several chunks is split over nsub workgroups per slice of
-// kSpreadSlice image groups (workgroup r of the cell takes groups r, r + nsub, ...).
+// batches.  A cell with several chunks is split over nsub >= kSpreadSlice / kSpreadHeavyGroups
+// workgroups per slice of kSpreadSlice image groups (workgroup r of the cell takes groups
+// r, r + nsub, ...), each walking the chunks in order with the next image group's values
+// prefetched and per-group partial sums in registers.
 constexpr int kSpreadCell = 8;
 constexpr int kSpreadNodes = 256;
 constexpr int kSpreadEntries = 6144;
 constexpr int kSpreadBatch = 8;
 constexpr int kSpreadSlice = 16;
+constexpr int kSpreadHeavyGroups = 4;
 struct SpreadTile {
   int m2, m1;    // cell origin (row m2 of the half plane, column m1)
   int c0, c1;    // chunk range
@@ -118,9 +121,8 @@ struct SpreadChunk {
   int pad;
 };
 struct SpreadLocal {
-  uint16_t li;    // node index within the chunk
-  uint16_t conj;  // 1: the conjugate of the node value
-  float weight;
+  uint32_t off;   // byte offset of the node's values (one image group) in the chunk's LDS copy
+  float weight;   // spreading weight (>= 0), negated when the conjugate of the node value is taken
 };
 
 // Kernel stages, in launch order (names in stage_name()).
