@@ -1,5 +1,6 @@
 """Plain FP64 restatement of the steerable PCA back end (Algorithm 2, steps 5-6, and the
-component selection and eigenvalue shrinkage of Sec. V) — test oracle.
+component selection and eigenvalue shrinkage of Sec. V) and of the real-space
+eigenimages of Sec. VI-B — test oracle.
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, never by the product path.
 
@@ -14,7 +15,7 @@ import math
 import numpy as np
 from scipy import special
 
-from .fb import Plan
+from .fb import Plan, pixel_coords
 
 
 def mp_ratio(pl: Plan, n: int) -> np.ndarray:
@@ -94,3 +95,43 @@ def reconstruct(c: np.ndarray, mean0: np.ndarray, U: list, w: list | None, pl: P
         a[:, o:o + pl.p[k]] = ck @ U[k].T
     a[:, :pl.p[0]] += mean0[None, :]
     return a
+
+
+# distance |2 pi c r - R_{k,q}| below which a term of Eq.(IFT_FB) takes its limit
+ROOT_GUARD = 1e-8
+
+
+def eigenimage_radial(pl: Plan, k: int, u: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Radial factor of the real-space steerable principal component with coefficient
+    vector u (column u_l^(k) of the eigenvectors) at z = 2 pi c r:
+
+        2 c sqrt(pi) J_k(z) sum_q (-1)^q R_{k,q} u(q) / (z^2 - R_{k,q}^2)
+
+    (the sum over q of Eq.(IFT_FB) with the angular factor left out).  Where z lies within
+    ROOT_GUARD of R_{k,q}, J_k(z) / (z^2 - R_{k,q}^2) is replaced by its limit
+    -J_{k+1}(z) / (z + R_{k,q}) (J_k(R_{k,q}) = 0 and J_k' = -J_{k+1} there)."""
+    z = np.asarray(z, dtype=np.float64)
+    jk = special.jv(k, z)
+    jk1 = special.jv(k + 1, z)
+    acc = np.zeros_like(z)
+    for q in range(1, pl.p[k] + 1):
+        R = pl.roots[k][q - 1]
+        d = z - R
+        near = np.abs(d) < ROOT_GUARD
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.where(near, -jk1 / (z + R), jk / (d * (z + R)))
+        acc += ((-1) ** q) * R * u[q - 1] * t
+    return 2.0 * pl.c * math.sqrt(math.pi) * acc
+
+
+def eigenimages(U: list, pl: Plan, k: int, ls) -> np.ndarray:
+    """Real-space steerable principal components g^{k,l} on the L x L pixel grid (axis 0 =
+    x, axis 1 = y): E^{k,l}(x) = sum_q u_l^(k)(q) F^{-1}(psi_c^{k,q})(x), the linear
+    combination of the closed-form inverse transforms of Eq.(IFT_FB) that Sec. VI-B
+    evaluates instead of an inverse polar transform, with i^k in the numerator (the
+    printed 1/i^k has the wrong sign for odd k).  Complex [len(ls)][L][L]."""
+    x = pixel_coords(pl.L)
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    z = 2.0 * math.pi * pl.c * np.hypot(X1, X2)
+    ang = (1j) ** k * np.exp(1j * k * np.arctan2(X2, X1))
+    return np.stack([ang * eigenimage_radial(pl, k, U[k][:, l], z) for l in ls])
