@@ -275,6 +275,16 @@ def main():
     spca = {"selected_components": int(n_sel.sum().item()), "coeffs_ms": round(c_ms, 3),
             "reconstruct_ms": round(r_ms, 3), "coeffs_images_per_s": round(args.n / (c_ms * 1e-3), 1),
             "coeffs_hbm_GBps": round(spca_bytes / (c_ms * 1e-3) / 1e9, 1)}
+    # real-space eigenimages of the selected components (Eq.(IFT_FB) combinations, FP64)
+    sel = n_sel.cpu().numpy()
+    ks = [k for k in range(plan.k_max + 1) if sel[k] > 0]
+    cap = max([int(sel[k]) for k in ks] + [1])
+    ebuf = torch.empty((cap, L, L), dtype=torch.complex128, device="cuda")
+    plan.eigenimages(evecs, 0, 0, 1, out=ebuf[:1])  # warm-up
+    _, e_ms = timed(lambda: [plan.eigenimages(evecs, k, 0, int(sel[k]), out=ebuf[:int(sel[k])]) for k in ks])
+    del ebuf
+    spca["eigenimages"] = int(sel.sum())
+    spca["eigenimages_ms"] = round(e_ms, 3)
     log(f"spca back end: {spca}")
 
     # adjoint synthesis T a (the differentiation and reconstruction path), outside images/s

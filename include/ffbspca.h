@@ -188,8 +188,18 @@ size_t fb_eig_workspace_bytes(fb_plan_t plan);
  * fb_spca_radial: f^{k,l}(xi_j) = sum_q N_{k,q} J_k(R_{k,q} xi_j / c) u_l^(k)(q)
  *   (Eq.(sPCArad)) at the Gauss-Legendre nodes; f float32, block k at n_xi * coef_off[k],
  *   [n_xi][p_k] row-major.
- * Errors: FB_ERR_INVALID_ARG (NULL pointers, in-place out, count <= 0, sigma2 < 0),
- * FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+ * fb_eigenimages: the real-space steerable principal components of Sec. VI-B on the
+ *   L x L pixel grid (axis 0 = x, axis 1 = y, pixel coordinates -floor(L/2) ..), as the
+ *   linear combinations E^{k,l}(x) = sum_q u_l^(k)(q) F^{-1}(psi_c^{k,q})(x) of the closed
+ *   forms of Eq.(IFT_FB) (with i^k in the numerator: the printed 1/i^k has the wrong
+ *   sign for odd k), for components l = l0 .. l0 + nl - 1 of angular frequency k.
+ *   evecs as written by fb_eig (device, FP64); out device FP64 [nl][L][L][2] (re, im),
+ *   caller-owned.  FP64 throughout (Bessel functions by Miller's backward recurrence);
+ *   within 1e-8 of a Bessel root the quotient J_k(z)/(z^2 - R^2) takes its limit.
+ *   For k > 0, 2 Re E^{k,l} is the image that fb_adjoint gives for the coefficient
+ *   vector u_l^(k) placed at k.  nl = 0 is a no-op.
+ * Errors: FB_ERR_INVALID_ARG (NULL pointers, in-place out, count <= 0, sigma2 < 0;
+ * k outside 0..k_max, l0 < 0, nl < 0 or l0 + nl > p_k), FB_ERR_NO_DEVICE, FB_ERR_HIP. */
 int fb_spca_select(fb_plan_t plan, const double* evals, int64_t count, double sigma2, int32_t* n_sel,
                    double* weights, void* stream);
 int fb_spca_coeffs(fb_plan_t plan, const float* coeffs, int64_t n, const double* evecs, const double* mean,
@@ -197,6 +207,7 @@ int fb_spca_coeffs(fb_plan_t plan, const float* coeffs, int64_t n, const double*
 int fb_spca_reconstruct(fb_plan_t plan, const float* c, int64_t n, const double* evecs, const double* mean,
                         const double* weights, float* out, void* stream);
 int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream);
+int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, double* out, void* stream);
 
 /* Seeded synthetic inputs on the device (not part of the method): Philox-4x32-10
  * (Salmon et al., SC'11) words with counter (word_block, index_lo, index_hi,

@@ -246,6 +246,16 @@ int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream) 
   return hip_rc(pl, fb::launch_spca_radial(pl, evecs, f, (hipStream_t)stream));
 }
 
+int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, double* out, void* stream) {
+  if (!plan || nl < 0 || l0 < 0) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (k < 0 || k > pl.k_max || l0 + nl > pl.p[k]) return FB_ERR_INVALID_ARG;
+  if (nl == 0) return FB_OK;
+  if (!evecs || !out) return FB_ERR_INVALID_ARG;
+  return hip_rc(pl, fb::launch_eigenimages(pl, evecs, k, l0, nl, out, (hipStream_t)stream));
+}
+
 int fb_synth_normals(uint64_t seed, uint32_t rng_stream, int64_t first_index, int64_t n, int64_t n_per, float scale,
                      float* out, void* stream) {
   if (n < 0 || n_per < 0 || first_index < 0) return FB_ERR_INVALID_ARG;

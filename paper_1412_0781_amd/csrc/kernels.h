@@ -55,6 +55,8 @@ hipError_t launch_spca_select(const Plan& pl, const double* evals, long long cou
 hipError_t launch_spca_apply(const Plan& pl, int mode, const float* in, long long n, const double* evecs,
                              const double* mean, const double* weights, float* out, hipStream_t st);
 hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hipStream_t st);
+hipError_t launch_eigenimages(const Plan& pl, const double* evecs, int k, int l0, int nl, double* out,
+                              hipStream_t st);
 
 // seeded inputs
 hipError_t launch_synth_normals(unsigned long long seed, unsigned rng_stream, long long first, long long n,

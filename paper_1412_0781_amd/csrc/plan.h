@@ -220,6 +220,7 @@ struct Plan {
   hipError_t last_hip = hipSuccess;
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
   float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
+  double* d_roots = nullptr;          // R_{k,q} at coef_off[k] + q - 1 (FP64, p_half)
   int* d_coef_off = nullptr;          // k_max + 2 (fits int32)
   int* d_p = nullptr;                 // k_max + 1
   long long* d_cov_off = nullptr;     // k_max + 2

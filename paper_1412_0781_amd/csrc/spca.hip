@@ -6,6 +6,8 @@
 //   project    c_{k,.} = (a_{k,.} - m delta_{k0}) U^(k)               (Eq.(sPCAcoeff))
 //   rebuild    a_{k,.} = U^(k) (w_k * c_{k,.}) + m delta_{k0}
 //   radial     f^{k,l}(xi_j) = sum_q N_{k,q} J_k(R_{k,q} xi_j / c) u_l^(k)(q)  (Eq.(sPCArad))
+//   real space E^{k,l}(x) = sum_q u_l^(k)(q) F^{-1}(psi_c^{k,q})(x)  (Eq.(IFT_FB), i^k in the
+//              numerator), the eigenimages of Sec. VI-B on the pixel grid, in FP64
 // The two coefficient maps are per-k products of the complex coefficients (real and
 // imaginary parts as separate rows) with the real p_k x p_k matrix U^(k), on
 // v_mfma_f32_32x32x2f32 in 64 x 64 tiles (FP32 products and sums; U rounded to FP32).
@@ -121,6 +123,93 @@ __global__ void k_spca_radial(const float* __restrict__ radial, const float* __r
   }
 }
 
+// J_k(z) and J_{k+1}(z), z >= 0, by Miller's backward recurrence J_{m-1} = (2m/z) J_m - J_{m+1}
+// started well above max(k + 1, z) (the start-order rule of Abramowitz & Stegun 9.12),
+// normalised with J_0 + 2 sum_{m>=1} J_{2m} = 1, rescaled whenever the values pass 1e250.
+__device__ void bessel_jk_pair(int k, double z, double& jk, double& jk1) {
+  if (z == 0.0) {
+    jk = k == 0 ? 1.0 : 0.0;
+    jk1 = 0.0;
+    return;
+  }
+  const double top = fmax((double)(k + 1), z);
+  const int m0 = 2 * ((int)(top + 20.0 + sqrt(60.0 * top)) / 2) + 2;
+  const double tz = 2.0 / z;
+  double jp = 0.0, j = 1e-300, sum = 0.0, a = 0.0, b = 0.0;
+  for (int m = m0; m >= 1; --m) {
+    const double jm = (double)m * tz * j - jp;  // J_{m-1}
+    jp = j;
+    j = jm;
+    const int o = m - 1;
+    if (o == k + 1) b = j;
+    if (o == k) a = j;
+    if (o > 0 && (o & 1) == 0) sum += 2.0 * j;
+    if (fabs(j) > 1e250) {
+      j *= 1e-250;
+      jp *= 1e-250;
+      sum *= 1e-250;
+      a *= 1e-250;
+      b *= 1e-250;
+    }
+  }
+  sum += j;
+  jk = a / sum;
+  jk1 = b / sum;
+}
+
+// Eigenimages of components l0 .. l0 + nl - 1 at angular frequency k on the L x L grid,
+// one pixel per lane:
+//   E(x) = 2 c sqrt(pi) i^k e^{ik phi} J_k(z) sum_q (-1)^q R_q u_l(q) / (z^2 - R_q^2),
+// z = 2 pi c r.  Within kEigRootGuard of a root R_q the quotient J_k(z) / (z^2 - R_q^2) takes
+// its limit -J_{k+1}(z) / (z + R_q).  Components go in chunks of kEigChunk accumulators.
+constexpr double kEigRootGuard = 1e-8;
+constexpr int kEigChunk = 16;
+__global__ __launch_bounds__(64) void k_spca_eigenimages(const double* __restrict__ evecs,
+                                                         const double* __restrict__ roots, int k, int pk,
+                                                         int l0, int nl, int L, double c,
+                                                         double2* __restrict__ out) {
+  const int pix = blockIdx.x * 64 + threadIdx.x;
+  if (pix >= L * L) return;
+  const int a = pix / L, b = pix - a * L;
+  const double x1 = (double)(a - L / 2), x2 = (double)(b - L / 2);
+  const double pi = 3.14159265358979323846;
+  const double z = 2.0 * pi * c * sqrt(x1 * x1 + x2 * x2);
+  double jk, jk1;
+  bessel_jk_pair(k, z, jk, jk1);
+  double sn, cs;
+  sincos((double)k * atan2(x2, x1), &sn, &cs);
+  double ar, ai;  // i^k e^{ik phi}
+  switch (k & 3) {
+    case 0: ar = cs; ai = sn; break;
+    case 1: ar = -sn; ai = cs; break;
+    case 2: ar = -cs; ai = -sn; break;
+    default: ar = sn; ai = -cs; break;
+  }
+  const double pref = 2.0 * c * sqrt(pi);
+  const size_t plane = (size_t)L * L;
+  for (int c0 = 0; c0 < nl; c0 += kEigChunk) {
+    const int nc = min(kEigChunk, nl - c0);
+    double acc[kEigChunk];
+#pragma unroll
+    for (int t = 0; t < kEigChunk; ++t) acc[t] = 0.0;
+    for (int q = 1; q <= pk; ++q) {
+      const double R = roots[q - 1];
+      const double d = z - R;
+      const double tq = (fabs(d) < kEigRootGuard ? -jk1 / (z + R) : jk / (d * (z + R))) * ((q & 1) ? -R : R);
+      const double* Uq = evecs + (size_t)(q - 1) * pk + l0 + c0;
+#pragma unroll
+      for (int t = 0; t < kEigChunk; ++t)
+        if (t < nc) acc[t] = fma(Uq[t], tq, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kEigChunk; ++t)
+      if (t < nc) {
+        const double v = pref * acc[t];
+        out[(size_t)(c0 + t) * plane + pix] = make_double2(v * ar, v * ai);
+      }
+  }
+}
+
 hipError_t launch_spca_select(const Plan& pl, const double* evals, long long count, double sigma2, int* n_sel,
                               double* weights, hipStream_t st) {
   pl.prof.begin(ST_SPCA, st);
@@ -148,6 +237,17 @@ hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hip
   pl.prof.begin(ST_SPCA, st);
   hipLaunchKernelGGL(k_spca_radial, dim3((unsigned)(pl.k_max + 1)), dim3(256), 0, st, pl.d_radial, pl.d_xw, evecs,
                      pl.d_coef_off, pl.d_p, pl.d_cov_off, pl.n_xi, f);
+  pl.prof.end(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_eigenimages(const Plan& pl, const double* evecs, int k, int l0, int nl, double* out,
+                              hipStream_t st) {
+  const long long npix = (long long)pl.L * pl.L;
+  pl.prof.begin(ST_SPCA, st);
+  hipLaunchKernelGGL(k_spca_eigenimages, dim3((unsigned)((npix + 63) / 64)), dim3(64), 0, st,
+                     evecs + pl.cov_off[k], pl.d_roots + pl.coef_off[k], k, pl.p[k], l0, nl, pl.L, pl.c,
+                     (double2*)out);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -228,6 +228,22 @@ class Plan:
         check(lib().fb_spca_radial(self._h, evecs.data_ptr(), f.data_ptr(), _stream_ptr(evecs.device)), self._h)
         return f
 
+    def eigenimages(self, evecs: torch.Tensor, k: int, l0: int = 0, nl: int | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+        """Real-space steerable principal components l0 .. l0 + nl - 1 of angular frequency k
+        on the pixel grid (Eq.(IFT_FB) combinations, Sec. VI-B): complex128 [nl][L][L]."""
+        _need(evecs, torch.float64, (self.cov_size,), "evecs")
+        if nl is None:
+            nl = self.p[k] - l0
+        if out is None:
+            out = torch.empty((nl, self.L, self.L), dtype=torch.complex128, device=evecs.device)
+        if out.dtype != torch.complex128 or tuple(out.shape) != (nl, self.L, self.L) or not out.is_contiguous() \
+                or out.device != evecs.device:
+            raise ValueError("out must be contiguous complex128 [nl][L][L] on the device of evecs")
+        check(lib().fb_eigenimages(self._h, evecs.data_ptr(), int(k), int(l0), int(nl), out.data_ptr(),
+                                   _stream_ptr(evecs.device)), self._h)
+        return out
+
     def radial_blocks(self, f: torch.Tensor | np.ndarray):
         return [f[self.n_xi * self.coef_off[k]:self.n_xi * self.coef_off[k + 1]].reshape(self.n_xi, self.p[k])
                 for k in range(self.k_max + 1)]
