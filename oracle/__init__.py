@@ -43,6 +43,8 @@ from .fb import (  # noqa: F401
     mean_and_covariance,
     covariance_blocks,
     eig_blocks,
+    coefficient_rows,
+    svd_blocks,
     adjoint,
     coeff_inner,
 )

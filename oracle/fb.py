@@ -300,6 +300,41 @@ def eig_blocks(C: list):
     return lam, U
 
 
+def coefficient_rows(a: np.ndarray, pl: Plan, k: int, mean0: np.ndarray | None = None) -> np.ndarray:
+    """The real data matrix of angular frequency k whose Gram matrix is n C^(k): for k > 0
+    the rows are Re a^i_{k,.} (i = 1..n) followed by Im a^i_{k,.}, so that
+    X^T X = Re(A^(k) A^(k)*) (Eq.(ck)); for k = 0 the rows are a^i_{0,.} - mean (Eq.(ck_0)
+    with the mean of Algorithm 2, step 1)."""
+    o = pl.coef_off[k]
+    A = a[:, o:o + pl.p[k]]
+    if k == 0:
+        m = A.real.mean(axis=0) if mean0 is None else mean0
+        return A.real - m[None, :]
+    return np.concatenate([A.real, A.imag], axis=0)
+
+
+def svd_blocks(a: np.ndarray, pl: Plan):
+    """Principal components from the SVD of the coefficient matrices (Sec. III-C: the left
+    singular vectors of A^(k), taken here as the right singular vectors of the real row
+    matrix X^(k) = [Re A^(k)^T; Im A^(k)^T], whose Gram matrix is n C^(k)), by LAPACK's SVD.
+    Eigenvalues of C^(k) are sigma^2 / n, descending; vectors sign-normalised as in
+    eig_blocks.  Returns (mean0, lam, U) like mean_and_covariance + eig_blocks."""
+    n = a.shape[0]
+    mean0 = a[:, :pl.p[0]].real.mean(axis=0)
+    lam, U = [], []
+    for k in range(pl.k_max + 1):
+        X = coefficient_rows(a, pl, k, mean0)
+        _, s, Vt = np.linalg.svd(X, full_matrices=False)
+        V = Vt.T.copy()
+        for col in range(V.shape[1]):
+            i = int(np.argmax(np.abs(V[:, col])))
+            if V[i, col] < 0:
+                V[:, col] = -V[:, col]
+        lam.append(s ** 2 / n)
+        U.append(V)
+    return mean0, lam, U
+
+
 # ----------------------------------------------------------------------------
 # The adjoint T of T* (Eq.(transf)), used for synthesis and differentiation
 # ----------------------------------------------------------------------------
