@@ -256,6 +256,23 @@ def main():
     torch.cuda.synchronize()
     eig_ms = 1e3 * (time.perf_counter() - te)
 
+    # principal components by the SVD of the coefficient matrices (Sec. III-C), outside
+    # images/s: the same eigenvalues without forming C^(k)
+    svd_ws = torch.empty(plan.svd_workspace_bytes(args.n), dtype=torch.uint8, device="cuda")
+    plan.svd(coeffs[:64], ws=svd_ws)  # warm-up
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    sv_evals, _, _ = plan.svd(coeffs, ws=svd_ws)
+    torch.cuda.synchronize()
+    svd_ms = 1e3 * (time.perf_counter() - ts)
+    del svd_ws
+    lam = evals.cpu().tolist()
+    d = (sv_evals - evals).abs().cpu().tolist()
+    rel = max(d[i] / max(lam[int(plan.coef_off[k])], 1e-300)
+              for k in range(plan.k_max + 1) for i in range(int(plan.coef_off[k]), int(plan.coef_off[k + 1])))
+    svd = {"images": args.n, "ms": round(svd_ms, 3), "max_eval_diff_vs_eig": rel}
+    log(f"svd route: {svd}")
+
     # steerable-PCA back end (outside images/s): selection with the workload's noise variance,
     # sPCA coefficients of every image, filtered reconstruction of their FB coefficients
     def timed(fn):
@@ -359,6 +376,7 @@ def main():
         "stages": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                    for k, v in stages.items()},
         "eig_ms": round(eig_ms, 2),
+        "svd": svd,
         "spca": spca,
         "adjoint": adjoint,
         "plan_s": round(plan_s, 2),

@@ -209,6 +209,32 @@ int fb_spca_reconstruct(fb_plan_t plan, const float* c, int64_t n, const double*
 int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream);
 int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, double* out, void* stream);
 
+/* Principal components by the SVD of the coefficient matrices (Sec. III-C: the left
+ * singular vectors of A^(k) in place of the eigenvectors of C^(k), same complexity,
+ * better conditioning).  For each k the real matrix X^(k) = [Re A^(k)^T; Im A^(k)^T]
+ * (2n x p_k; for k = 0, the n x p_0 matrix A^(0)^T minus the mean of Algorithm 2 step 1)
+ * has Gram matrix n C^(k).  The library reduces it to a triangular factor by Householder
+ * reflections (tall-skinny QR over row ranges, then a merge per k) and takes the SVD of
+ * that factor by one-sided Jacobi sweeps, in FP64 without forming any Gram matrix.
+ *   coeffs   device float32 [n][p_half][2] as written by fb_expand (k = 0 imaginary parts
+ *            are ignored).
+ *   evals    device FP64 [p_half]: lambda_l = sigma_l^2 / n at coef_off[k] + l, descending
+ *            within each k (the eigenvalues of C^(k)).
+ *   evecs    device FP64 [sum p_k^2], packed like fb_eig's: block k at cov_off[k],
+ *            p_k x p_k row-major, column l = the right singular vector for sigma_l, the
+ *            entry of largest magnitude positive (lowest index on ties).  A column with
+ *            sigma_l = 0 (fewer data rows than p_k) is written as zeros.
+ *   mean_out nullable device FP64 [p_0]: the k = 0 mean.
+ *   ws       device workspace of at least fb_svd_workspace_bytes(plan, n) bytes,
+ *            8-byte aligned, caller-owned (mean, per-range factors, p_k x p_k blocks).
+ * Asynchronous on `stream`; allocates nothing.  Errors: FB_ERR_INVALID_ARG (NULL
+ * pointers, n <= 0, misaligned ws), FB_ERR_WORKSPACE, FB_ERR_UNSUPPORTED (max p_k above
+ * 142: the p_k x p_k Jacobi block must fit a workgroup's LDS), FB_ERR_NO_DEVICE,
+ * FB_ERR_HIP. */
+size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n);
+int fb_svd(fb_plan_t plan, const float* coeffs, int64_t n, double* evals, double* evecs, double* mean_out, void* ws,
+           size_t ws_bytes, void* stream);
+
 /* Seeded synthetic inputs on the device (not part of the method): Philox-4x32-10
  * (Salmon et al., SC'11) words with counter (word_block, index_lo, index_hi,
  * stream) and key (seed_lo, seed_hi), Box-Muller normals on word pairs.
@@ -229,7 +255,7 @@ int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int6
  * the number of stages (FB_NUM_STAGES) or a negative FB_ERR_* code.  Stage
  * names come from fb_stage_name.  Not for concurrent use of one plan from
  * several streams while enabled. */
-#define FB_NUM_STAGES 13
+#define FB_NUM_STAGES 14
 int fb_profile_enable(fb_plan_t plan, int enable);
 int fb_profile_read(fb_plan_t plan, double* total_ms, int64_t* launches, int max_stages, int reset);
 const char* fb_stage_name(int stage);

@@ -56,6 +56,8 @@ SIGNATURES = [
     ("fb_spca_reconstruct", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_spca_radial", c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_eigenimages", c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+    ("fb_svd_workspace_bytes", c_size_t, [c_void_p, c_int64]),
+    ("fb_svd", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("fb_synth_normals", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_float, c_void_p, c_void_p]),
     ("fb_synth_words", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_void_p, c_void_p]),
     ("fb_profile_enable", c_int, [c_void_p, c_int]),

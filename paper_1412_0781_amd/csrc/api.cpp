@@ -246,6 +246,24 @@ int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream) 
   return hip_rc(pl, fb::launch_spca_radial(pl, evecs, f, (hipStream_t)stream));
 }
 
+size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n) {
+  if (!plan || n <= 0) return 0;
+  return (size_t)fb::svd_split(plan->pl, n).total_doubles * sizeof(double);
+}
+
+int fb_svd(fb_plan_t plan, const float* coeffs, int64_t n, double* evals, double* evecs, double* mean_out, void* ws,
+           size_t ws_bytes, void* stream) {
+  if (!plan || n <= 0 || !coeffs || !evals || !evecs || !ws) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (fb::svd_finish_lds_bytes(pl) > (size_t)fb::kSvdLdsLimit) return FB_ERR_UNSUPPORTED;
+  if ((uintptr_t)ws % 8 != 0) return FB_ERR_INVALID_ARG;
+  if (ws_bytes < fb_svd_workspace_bytes(plan, n)) return FB_ERR_WORKSPACE;
+  const fb::SvdSplit s = fb::svd_split(pl, n);
+  if ((long long)s.W0 + (long long)s.W1 * pl.k_max > 0x7fffffffLL) return FB_ERR_INVALID_ARG;
+  return hip_rc(pl, fb::launch_svd(pl, coeffs, n, evals, evecs, mean_out, (double*)ws, (hipStream_t)stream));
+}
+
 int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, double* out, void* stream) {
   if (!plan || nl < 0 || l0 < 0) return FB_ERR_INVALID_ARG;
   fb::Plan& pl = plan->pl;

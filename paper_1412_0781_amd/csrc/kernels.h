@@ -55,6 +55,22 @@ hipError_t launch_spca_select(const Plan& pl, const double* evals, long long cou
 hipError_t launch_spca_apply(const Plan& pl, int mode, const float* in, long long n, const double* evecs,
                              const double* mean, const double* weights, float* out, hipStream_t st);
 hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hipStream_t st);
+// SVD route (Sec. III-C): rows per level-1 workgroup, LDS ceiling of the two SVD kernels.
+constexpr int kSvdRowsPerGroup = 8192;
+constexpr int kSvdLdsLimit = 160 * 1024 - 1024;
+struct SvdSplit {
+  int W0, W1;                 // level-1 workgroups for k = 0 and for each k > 0
+  long long base1;            // doubles of the k = 0 level-1 factors
+  long long r_doubles;        // doubles of all level-1 factors
+  long long mean_doubles;     // doubles reserved for the k = 0 mean
+  long long total_doubles;    // workspace: mean, level-1 factors, p_k x p_k blocks
+};
+SvdSplit svd_split(const Plan& pl, long long n);
+size_t svd_finish_lds_bytes(const Plan& pl);
+size_t svd_qr_lds_bytes(const Plan& pl);
+hipError_t configure_svd_kernels();
+hipError_t launch_svd(const Plan& pl, const float* coeffs, long long n, double* evals, double* evecs,
+                      double* mean_out, double* ws, hipStream_t st);
 hipError_t launch_eigenimages(const Plan& pl, const double* evecs, int k, int l0, int nl, double* out,
                               hipStream_t st);
 

@@ -68,6 +68,8 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
   }
   pl.p_half = pl.coef_off[pl.k_max + 1];
   pl.cov_size = pl.cov_off[pl.k_max + 1];
+  pl.tri_off.assign(pl.k_max + 2, 0);  // packed upper triangles p_k (p_k + 1) / 2, by k
+  for (int k = 0; k <= pl.k_max; ++k) pl.tri_off[k + 1] = pl.tri_off[k] + (long long)pl.p[k] * (pl.p[k] + 1) / 2;
   pl.p_total = pl.p0 + 2 * (pl.p_half - pl.p0);
   pl.kq_k.resize(pl.p_half);
   pl.kq_q.resize(pl.p_half);
@@ -384,6 +386,7 @@ static hipError_t upload(T** dptr, const T* src, size_t count) {
 int upload_plan(Plan& pl) {
   FB_HIP_TRY(hipGetDevice(&pl.device));
   FB_HIP_TRY(configure_kernels());
+  FB_HIP_TRY(configure_svd_kernels());
   size_t nb = (size_t)pl.p_half * pl.n_xi;
   std::vector<float> r32(nb);
   for (size_t i = 0; i < nb; ++i) r32[i] = (float)pl.radial[i];
@@ -397,6 +400,7 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_p, pl.p.data(), pl.p.size()));
   std::vector<long long> coff(pl.cov_off.begin(), pl.cov_off.end());
   FB_HIP_TRY(upload(&pl.d_cov_off, coff.data(), coff.size()));
+  FB_HIP_TRY(upload(&pl.d_tri_off, pl.tri_off.data(), pl.tri_off.size()));
   std::vector<float> dc(pl.deconv.begin(), pl.deconv.end());
   FB_HIP_TRY(upload(&pl.d_deconv, dc.data(), dc.size()));
   FB_HIP_TRY(upload(&pl.d_gnodes, pl.gnodes.data(), pl.gnodes.size()));
@@ -419,7 +423,7 @@ int upload_plan(Plan& pl) {
 
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
-  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,
+  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
@@ -430,6 +434,7 @@ void free_device(Plan& pl) {
   pl.d_roots = nullptr;
   pl.d_coef_off = pl.d_p = nullptr;
   pl.d_cov_off = nullptr;
+  pl.d_tri_off = nullptr;
   pl.d_deconv = nullptr;
   pl.d_gnodes = nullptr;
   pl.d_gitems = nullptr;
@@ -448,7 +453,7 @@ const char* stage_name(int s) {
   static const char* names[ST_COUNT] = {"fwd_rows",    "fwd_cols",   "fwd_gather", "fwd_angular",
                                         "radial_fwd",  "covariance", "radial_adj", "adj_angular",
                                         "adj_spread",  "adj_cols",   "adj_rows",   "eig",
-                                        "spca"};
+                                        "spca",        "svd"};
   return (s >= 0 && s < ST_COUNT) ? names[s] : "unknown";
 }
 

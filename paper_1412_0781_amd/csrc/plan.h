@@ -140,6 +140,7 @@ enum Stage {
   ST_ADJ_ROWS,
   ST_EIG,
   ST_SPCA,
+  ST_SVD,
   ST_COUNT
 };
 const char* stage_name(int s);
@@ -182,6 +183,7 @@ struct Plan {
   std::vector<int> p;               // p_k
   std::vector<int64_t> coef_off;    // k_max + 2
   std::vector<int64_t> cov_off;     // k_max + 2
+  std::vector<long long> tri_off;   // k_max + 2: offsets of packed p_k x p_k upper triangles
   std::vector<int> kq_k, kq_q;      // p_half
   std::vector<double> roots, norms; // p_half
   std::vector<double> xi, wq;       // n_xi
@@ -224,6 +226,7 @@ struct Plan {
   int* d_coef_off = nullptr;          // k_max + 2 (fits int32)
   int* d_p = nullptr;                 // k_max + 1
   long long* d_cov_off = nullptr;     // k_max + 2
+  long long* d_tri_off = nullptr;     // k_max + 2
   float* d_deconv = nullptr;
   GatherNode* d_gnodes = nullptr;
   GatherItem* d_gitems = nullptr;

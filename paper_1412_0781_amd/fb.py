@@ -182,6 +182,26 @@ class Plan:
                            _stream_ptr(dev)), self._h)
         return evals, evecs, C, mean
 
+    def svd_workspace_bytes(self, n: int) -> int:
+        return int(lib().fb_svd_workspace_bytes(self._h, int(n)))
+
+    def svd(self, coeffs: torch.Tensor, ws: torch.Tensor | None = None):
+        """Principal components by the SVD of the coefficient matrices (Sec. III-C), without
+        forming C^(k).  Returns (evals [p_half], evecs [cov_size], mean [p0]), FP64 device
+        tensors laid out like eig's."""
+        n = coeffs.shape[0]
+        _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
+        dev = coeffs.device
+        evals = torch.empty(self.p_half, dtype=torch.float64, device=dev)
+        evecs = torch.empty(self.cov_size, dtype=torch.float64, device=dev)
+        mean = torch.empty(self.p0, dtype=torch.float64, device=dev)
+        wsb = self.svd_workspace_bytes(n)
+        if ws is None or ws.numel() * ws.element_size() < wsb:
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        check(lib().fb_svd(self._h, coeffs.data_ptr(), n, evals.data_ptr(), evecs.data_ptr(), mean.data_ptr(),
+                           ws.data_ptr(), ws.numel() * ws.element_size(), _stream_ptr(dev)), self._h)
+        return evals, evecs, mean
+
     # -- steerable PCA back end (Algorithm 2 steps 5-6, Sec. V) ------------------
     def spca_select(self, evals: torch.Tensor, count: int, sigma2: float):
         """Components above the Marcenko-Pastur edge per k (Eq.(compselect)) and the coefficient
