@@ -229,8 +229,8 @@ int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, d
  *            8-byte aligned, caller-owned (mean, per-range factors, p_k x p_k blocks).
  * Asynchronous on `stream`; allocates nothing.  Errors: FB_ERR_INVALID_ARG (NULL
  * pointers, n <= 0, misaligned ws), FB_ERR_WORKSPACE, FB_ERR_UNSUPPORTED (max p_k above
- * 142: the p_k x p_k Jacobi block must fit a workgroup's LDS), FB_ERR_NO_DEVICE,
- * FB_ERR_HIP. */
+ * 128: two threads per column of a 256-thread workgroup, and the p_k x p_k Jacobi block
+ * in its LDS), FB_ERR_NO_DEVICE, FB_ERR_HIP. */
 size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n);
 int fb_svd(fb_plan_t plan, const float* coeffs, int64_t n, double* evals, double* evecs, double* mean_out, void* ws,
            size_t ws_bytes, void* stream);

@@ -256,7 +256,8 @@ int fb_svd(fb_plan_t plan, const float* coeffs, int64_t n, double* evals, double
   if (!plan || n <= 0 || !coeffs || !evals || !evecs || !ws) return FB_ERR_INVALID_ARG;
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
-  if (fb::svd_finish_lds_bytes(pl) > (size_t)fb::kSvdLdsLimit) return FB_ERR_UNSUPPORTED;
+  if (fb::svd_finish_lds_bytes(pl) > (size_t)fb::kSvdLdsLimit || fb::svd_max_p(pl) > fb::kSvdMaxP)
+    return FB_ERR_UNSUPPORTED;
   if ((uintptr_t)ws % 8 != 0) return FB_ERR_INVALID_ARG;
   if (ws_bytes < fb_svd_workspace_bytes(plan, n)) return FB_ERR_WORKSPACE;
   const fb::SvdSplit s = fb::svd_split(pl, n);

@@ -58,6 +58,8 @@ hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hip
 // SVD route (Sec. III-C): rows per level-1 workgroup, LDS ceiling of the two SVD kernels.
 constexpr int kSvdRowsPerGroup = 8192;
 constexpr int kSvdLdsLimit = 160 * 1024 - 1024;
+constexpr int kSvdMaxP = 128;  // two threads per column in a 256-thread workgroup
+int svd_max_p(const Plan& pl);
 struct SvdSplit {
   int W0, W1;                 // level-1 workgroups for k = 0 and for each k > 0
   long long base1;            // doubles of the k = 0 level-1 factors

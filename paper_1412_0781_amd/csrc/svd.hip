@@ -14,9 +14,9 @@
 
 namespace fb {
 
-constexpr int kSvdChunk = 16;          // rows per Householder update
-constexpr int kSvdYs = kSvdChunk + 1;  // LDS stride of a chunk column (bank spread)
-constexpr int kSvdThreads = 256;       // one matrix column per thread
+constexpr int kSvdChunk = 32;          // rows per Householder update
+constexpr int kSvdHalf = kSvdChunk / 2;  // rows per thread: two threads per column
+constexpr int kSvdThreads = 256;       // two threads per matrix column (p_k <= 128)
 constexpr int kSvdMaxSweeps = 60;
 constexpr double kSvdTol = 1e-15;      // rotate while |x.y| > tol ||x|| ||y||
 
@@ -41,46 +41,72 @@ __global__ __launch_bounds__(256) void k_svd_mean(const float* __restrict__ coef
 
 // [R; Y] <- the triangular factor of the stack: R upper triangular p x p (rows packed,
 // row j from tri_row(j, p); its diagonal kept apart, read from dA and written to dB), Y
-// a chunk of kSvdChunk rows (column c at Y + c * kSvdYs).  For column j every thread
-// derives the same reflector (LAPACK's convention: beta = -sign(x0) ||(x0, y)||,
-// tau = (beta - x0) / beta, v = (1, y / (x0 - beta))) from the same LDS values, and thread
-// c > j applies it to column c.  One barrier per column.
-__device__ void householder_chunk(double* R, const double* dA, double* dB, double* Y, int p) {
-  const int c = threadIdx.x;
-  for (int j = 0; j < p; ++j) {
-    const double* yj = Y + j * kSvdYs;
-    double s2 = 0.0;
+// a chunk of kSvdChunk rows held in registers: thread (c = tid / 2, h = tid % 2) holds rows
+// h * kSvdHalf .. of column c in y[], and only it changes them.  The reflector of column j
+// follows LAPACK's convention (beta = -sign(x0) ||(x0, y)||, tau = (beta - x0) / beta,
+// v = (1, y / (x0 - beta))).  The owners of column j + 1 publish it at the end of step j,
+// once it is up to date: its values to yb and its scalars (tau, 1 / (x0 - beta)) to ref,
+// both double-buffered by the parity of the column.  One barrier per column.
+__device__ __forceinline__ void publish_column(const double (&y)[kSvdHalf], int h, double x0, int j, double* yb,
+                                               double* ref, double* dB) {
+  double* dst = yb + (j & 1) * kSvdChunk + h * kSvdHalf;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < kSvdChunk; ++r) s2 = fma(yj[r], yj[r], s2);
-    const double x0 = dA[j];
+  for (int r = 0; r < kSvdHalf; ++r) {
+    dst[r] = y[r];
+    s[r & 3] = fma(y[r], y[r], s[r & 3]);
+  }
+  double s2 = (s[0] + s[1]) + (s[2] + s[3]);
+  s2 += __shfl_xor(s2, 1);
+  if (h == 0) {
+    double tau = 0.0, inv_d = 0.0, beta = x0;
     if (s2 != 0.0) {
       const double nrm = sqrt(fma(x0, x0, s2));
-      const double beta = x0 >= 0.0 ? -nrm : nrm;
-      const double inv_d = 1.0 / (x0 - beta);
-      const double tau = (beta - x0) / beta;
-      if (c > j && c < p) {
-        double* yc = Y + c * kSvdYs;
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      inv_d = 1.0 / (x0 - beta);
+      tau = (beta - x0) / beta;
+    }
+    ref[2 * (j & 1)] = tau;
+    ref[2 * (j & 1) + 1] = inv_d;
+    dB[j] = beta;
+  }
+}
+
+__device__ void householder_chunk(double* R, const double* dA, double* dB, double (&y)[kSvdHalf], double* yb,
+                                  double* ref, int p) {
+  const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+  if (c == 0) publish_column(y, h, dA[0], 0, yb, ref, dB);
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    const double tau = ref[2 * (j & 1)], inv_d = ref[2 * (j & 1) + 1];
+    if (c > j && c < p) {
+      if (tau != 0.0) {
+        const double* yj = yb + (j & 1) * kSvdChunk + h * kSvdHalf;
         double* rjc = R + tri_row(j, p) + (c - j);
-        double w = *rjc;
+        double w4[4] = {h == 0 ? *rjc : 0.0, 0.0, 0.0, 0.0};
+        double v[kSvdHalf];
 #pragma unroll
-        for (int r = 0; r < kSvdChunk; ++r) w = fma(yj[r] * inv_d, yc[r], w);
+        for (int r = 0; r < kSvdHalf; ++r) {
+          v[r] = yj[r] * inv_d;
+          w4[r & 3] = fma(v[r], y[r], w4[r & 3]);
+        }
+        double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+        w += __shfl_xor(w, 1);
         const double tw = tau * w;
-        *rjc -= tw;
-        const double g = -tw * inv_d;
+        if (h == 0) *rjc -= tw;
 #pragma unroll
-        for (int r = 0; r < kSvdChunk; ++r) yc[r] = fma(g, yj[r], yc[r]);
+        for (int r = 0; r < kSvdHalf; ++r) y[r] = fma(-tw, v[r], y[r]);
       }
-      if (c == j) dB[j] = beta;
-    } else if (c == j) {
-      dB[j] = x0;
+      if (c == j + 1) publish_column(y, h, dA[c], c, yb, ref, dB);
     }
     __syncthreads();
   }
 }
 
-// LDS of the streaming QR: packed R, two diagonals, one chunk.
+// LDS of the streaming QR: packed R, two diagonals, the published column (two buffers)
+// and its reflector scalars (two pairs).
 __host__ __device__ inline long long svd_qr_lds_doubles(int p) {
-  return (long long)p * (p + 1) / 2 + 2LL * p + (long long)p * kSvdYs;
+  return (long long)p * (p + 1) / 2 + 2LL * p + 2LL * kSvdChunk + 4;
 }
 
 // Level 1: workgroup (k, w) reduces rows [w rows_per, (w + 1) rows_per) of X^(k) to a
@@ -109,24 +135,26 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_tsqr(const float* __restric
   double* R = sm;
   double* dA = R + tp;
   double* dB = dA + pk;
-  double* Y = dB + pk;
+  double* yb = dB + pk;
+  double* ref = yb + 2 * kSvdChunk;
   for (long long i = tid; i < tp; i += kSvdThreads) R[i] = 0.0;
   for (int i = tid; i < pk; i += kSvdThreads) dA[i] = dB[i] = 0.0;
+  const int c = tid >> 1, h = tid & 1;
+  double y[kSvdHalf];
   for (long long q0 = r0; q0 < r1; q0 += kSvdChunk) {
-    __syncthreads();
-    for (int e = tid; e < kSvdChunk * pk; e += kSvdThreads) {
-      const int r = e / pk, c = e - r * pk;
-      const long long row = q0 + r;
+#pragma unroll
+    for (int r = 0; r < kSvdHalf; ++r) {
+      const long long row = q0 + h * kSvdHalf + r;
       double v = 0.0;
-      if (row < r1) {
+      if (c < pk && row < r1) {
         const long long img = row < n ? row : row - n;
         v = (double)coeffs[((size_t)img * p_half + off + c) * 2 + (row < n ? 0 : 1)];
         if (k == 0) v -= mean[c];
       }
-      Y[c * kSvdYs + r] = v;
+      y[r] = v;
     }
     __syncthreads();
-    householder_chunk(R, dA, dB, Y, pk);
+    householder_chunk(R, dA, dB, y, yb, ref, pk);
     double* t = dA;
     dA = dB;
     dB = t;
@@ -161,25 +189,27 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
   double* R = sm;
   double* dA = R + tp;
   double* dB = dA + pk;
-  double* Y = dB + pk;
+  double* yb = dB + pk;
+  double* ref = yb + 2 * kSvdChunk;
   for (long long i = tid; i < tp; i += kSvdThreads) R[i] = 0.0;
   for (int i = tid; i < pk; i += kSvdThreads) dA[i] = dB[i] = 0.0;
   const long long nrows = (long long)W * pk;
+  const int c = tid >> 1, h = tid & 1;
+  double y[kSvdHalf];
   for (long long g0 = 0; g0 < nrows; g0 += kSvdChunk) {
-    __syncthreads();
-    for (int e = tid; e < kSvdChunk * pk; e += kSvdThreads) {
-      const int r = e / pk, c = e - r * pk;
-      const long long g = g0 + r;
+#pragma unroll
+    for (int r = 0; r < kSvdHalf; ++r) {
+      const long long g = g0 + h * kSvdHalf + r;
       double v = 0.0;
-      if (g < nrows) {
+      if (c < pk && g < nrows) {
         const long long w = g / pk;
         const int j = (int)(g - w * pk);
         if (c >= j) v = Rin[w * tp + tri_row(j, pk) + (c - j)];
       }
-      Y[c * kSvdYs + r] = v;
+      y[r] = v;
     }
     __syncthreads();
-    householder_chunk(R, dA, dB, Y, pk);
+    householder_chunk(R, dA, dB, y, yb, ref, pk);
     double* t = dA;
     dA = dB;
     dB = t;
@@ -267,6 +297,8 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
     for (int e = 0; e < pk; ++e) evecs[eo + (long long)e * pk + rank] = inv * col[e];
   }
 }
+
+int svd_max_p(const Plan& pl) { return *std::max_element(pl.p.begin(), pl.p.end()); }
 
 size_t svd_finish_lds_bytes(const Plan& pl) {
   const int pm = *std::max_element(pl.p.begin(), pl.p.end());
