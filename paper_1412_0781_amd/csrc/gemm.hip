@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
                                                         const float* __restrict__ coeffs, float* __restrict__ D,
                                                         const GemmItem* __restrict__ items,
                                                         const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                        int n_xi, int ncol, long long p_half, int weight_mode) {
+                                                        int n_xi, int nk, int ncol, long long p_half,
+                                                        int weight_mode) {
   __shared__ float As[BK][BM + 4];
   __shared__ float Bs[BK][BN + 4];
   const GemmItem it = items[blockIdx.y];
@@ -263,12 +264,17 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
     mma_f32(As, Bs, acc, wm, wn, lane);
     __syncthreads();
   }
+  // D grouped like the forward spectrum: [image group][ring j][k][16 images] complex, so
+  // that a (ring, group) unit of the angular step reads one contiguous run
   const float wk = (k == 0 || weight_mode == 1) ? 1.f : 2.f;
-  float* dk = D + (size_t)k * n_xi * ncol;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     int j = j0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-    if (j < n_xi && c < ncol) dk[(size_t)j * ncol + c] = wk * acc[i];
+    if (j < n_xi && c < ncol) {
+      const int img = c >> 1;
+      D[((((size_t)(img / kImgGroup) * n_xi + j) * nk + k) * kImgGroup + (img & (kImgGroup - 1))) * 2 + (c & 1)] =
+          wk * acc[i];
+    }
   }
 }
 
@@ -468,7 +474,7 @@ hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D,
   dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_adj.size());
   pl.prof.begin(ST_RADIAL_ADJ, st);
   hipLaunchKernelGGL(k_radial_adj_f32, g, dim3(256), 0, st, pl.d_radial, coeffs, (float*)D, pl.d_items_adj,
-                     pl.d_coef_off, pl.d_p, pl.n_xi, ncol, (long long)pl.p_half, weight_mode);
+                     pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half, weight_mode);
   pl.prof.end(st);
   return hipGetLastError();
 }

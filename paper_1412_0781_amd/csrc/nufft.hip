@@ -568,10 +568,10 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
 }
 
 // ---------------------------------------------------------------------------
-// adjoint angular: D [K+1][n_xi][ncol] -> Q [n_xi][group][H][16] (grouped like P)
+// adjoint angular: D [group][n_xi][K+1][16] -> Q [n_xi][group][H][16] (grouped like P)
 // Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H}),  s'_t = Re sum_{k<=K} E_k e^{2 pi i k t / n_theta},
-// E_k = c D_k (k even), -i c D_k (k odd).  Images vary fastest in both loops (coalesced
-// reads of D and writes of Q); transforms padded to H+1.
+// E_k = c D_k (k even), -i c D_k (k odd).  Images vary fastest in both loops (whole
+// 128-byte lines of D and Q); transforms padded to H+1.
 // ---------------------------------------------------------------------------
 template <int FORM>
 __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__ Q, FftDesc fd,
@@ -586,7 +586,8 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
   const int ng = min(AG, ngrp * kImgGroup - g0);  // slots past nimg read zeros
   auto Ek = [&](int k, int gg) -> float2 {
     if (g0 + gg >= nimg) return make_float2(0.f, 0.f);
-    float2 d = D[((size_t)k * n_xi + j) * nimg + g0 + gg];
+    const int img = g0 + gg;
+    float2 d = D[(((size_t)(img / kImgGroup) * n_xi + j) * (K + 1) + k) * kImgGroup + (img & (kImgGroup - 1))];
     return (k & 1) ? make_float2(d.y * scale, -d.x * scale) : make_float2(d.x * scale, d.y * scale);
   };
   // Zin(k') = (Y_k' + Y_{k'+H}) + i e^{+i pi k'/H} (Y_k' - Y_{k'+H}); stored conjugated for the forward FFT

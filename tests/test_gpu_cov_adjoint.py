@@ -106,7 +106,26 @@ def test_adjoint_matches_oracle(L, c, R):
     assert rel_l2(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (128, 0.5, 64), (31, 0.5, 15.5)])
+def test_adjoint_many_images():
+    """300 images: 19 image groups, so two slices of the spread's 16-group slices (the
+    second ragged) and a partly filled last group.  Sampled images against the oracle; a
+    ragged sub-batch gives the same images as the full batch."""
+    L, c, R = 64, 0.5, 32
+    print(f"[adjoint] L={L} n=300", flush=True)
+    po = oracle.plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(9, np.arange(300), k, q)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    full = plan.adjoint(bt).cpu().numpy()
+    pick = [0, 17, 150, 299]
+    ref = oracle.adjoint(b[pick], po)
+    assert rel_l2(full[pick], ref) <= TOL
+    part = plan.adjoint(bt[280:]).cpu().numpy()
+    assert np.max(np.abs(part - full[280:])) <= 1e-6 * np.max(np.abs(full[280:]))
+
+
+@pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (128, 0.5, 64), (31, 0.5, 15.5), (256, 0.5, 128)])
 def test_dot_product_identity_gpu(L, c, R):
     """<T* I, b> = <I, T b> with the folded inner product, to 1e-6 in FP32, relative to
     ||T* I|| ||b|| (the Cauchy-Schwarz scale of both sides; |<T* I, b>| itself can cancel
