@@ -626,6 +626,107 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// adjoint angular, streaming form (conditions as for the forward streaming form).  Same
+// result as k_adj_angular.  Each workgroup runs U consecutive (ring, group) units; the
+// next unit's spectrum (K+1 values of 16 images, one contiguous run of D) is loaded into
+// registers before the current unit is transformed and written.  Per unit the values are
+// placed in LDS at their k (zeros above K), the Hermitian completion is formed in place
+// for the pairs (k', H - k'), and the in-place FFT meets at LDS-only barriers so that the
+// loads stay in flight.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __restrict__ D, float2* __restrict__ Q,
+                                                             FftDesc fd, const float2* __restrict__ tw,
+                                                             const float2* __restrict__ angtw, int n_xi, int K,
+                                                             int nimg, int ngrp, int U, float scale) {
+  constexpr int G = kImgGroup;
+  constexpr int PF = kAngStreamH * G / 2 / 1024;  // pairs of spectrum values per thread (K + 1 <= H <= 512)
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];
+  __shared__ float2 s_tw[kAngStreamH];
+  __shared__ float2 s_angtw[kAngStreamH];
+  const int H = fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int total = n_xi * ngrp;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int nval = (K + 1) * G;
+  for (int i = tid; i < H; i += nthr) {
+    s_tw[i] = tw[fd.tw_off + i];
+    s_angtw[i] = angtw[i];
+  }
+  __syncthreads();
+  // unit u = (ring j, group): groups vary fastest, so consecutive units write consecutive Q
+  // item e holds the values 2e and 2e + 1 of the unit's run: k = 2e / 16, images gg, gg + 1
+  float4 pre[PF];
+  auto load = [&](int u) {
+    const int j = u / ngrp, grp = u - j * ngrp;
+    const float4* src = (const float4*)(D + ((size_t)grp * n_xi + j) * (K + 1) * G);
+    const int live = nimg - grp * G;  // image slots of this group that hold data
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int e = tid + p * nthr;
+      if (2 * e < nval) {
+        float4 v = src[e];
+        const int gg = (2 * e) & (G - 1);
+        if (gg >= live) v.x = v.y = 0.f;
+        if (gg + 1 >= live) v.z = v.w = 0.f;
+        pre[p] = v;
+      }
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    // E_k = c D_k (k even), -i c D_k (k odd), at its k; zeros for K < k < H
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int e = tid + p * nthr;
+      if (2 * e < nval) {
+        const int k = (2 * e) / G, gg = (2 * e) & (G - 1);
+        const float4 d = pre[p];
+        const float sr = (k & 1) ? -scale : scale;  // odd k: -i c D_k
+        s_buf[gg * S + fpad(k)] = (k & 1) ? make_float2(d.y * scale, d.x * sr) : make_float2(d.x * scale, d.y * scale);
+        s_buf[(gg + 1) * S + fpad(k)] =
+            (k & 1) ? make_float2(d.w * scale, d.z * sr) : make_float2(d.z * scale, d.w * scale);
+      }
+    }
+    for (int e = nval + tid; e < H * G; e += nthr) s_buf[(e & (G - 1)) * S + fpad(e / G)] = make_float2(0.f, 0.f);
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
+    // Zin(k') = (Y_k' + Y_{k'+H}) + i e^{+i pi k'/H} (Y_k' - Y_{k'+H}), Y_k' = E_k'/2 (Re E_0 at 0),
+    // Y_{k'+H} = conj(E_{H-k'})/2; pairs (k', H - k') share their two inputs; stored conjugated
+    for (int e = tid; e < (Hh + 1) * G; e += nthr) {
+      const int kp = e / G, gg = e & (G - 1), km = H - kp;
+      float2* row = s_buf + gg * S;
+      const float2 a = row[fpad(kp)];
+      const float2 b = kp == 0 ? make_float2(0.f, 0.f) : row[fpad(km)];
+      auto zin = [&](int k, float2 ek, float2 eo) {  // ek = E_k, eo = E_{H-k}
+        const float2 y0 = k == 0 ? make_float2(ek.x, 0.f) : make_float2(0.5f * ek.x, 0.5f * ek.y);
+        const float2 y1 = k == 0 ? make_float2(0.f, 0.f) : make_float2(0.5f * eo.x, -0.5f * eo.y);
+        const float2 ze = cadd(y0, y1);
+        const float2 zo = cmul(cconj(s_angtw[k]), csub(y0, y1));
+        return cconj(make_float2(ze.x - zo.y, ze.y + zo.x));
+      };
+      row[fpad(kp)] = zin(kp, a, b);
+      if (kp != 0 && kp != Hh) row[fpad(km)] = zin(km, b, a);
+    }
+    stage_barrier<true>();
+    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1};  Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H})
+    float2* dst = Q + (size_t)u * H * G;
+    for (int e = tid; e < H * G; e += nthr) {
+      const int l = e / G, gg = e & (G - 1);
+      const float2* row = s_buf + gg * S;
+      auto sp = [&](int t) -> float {
+        const float2 z = row[fpad(t >> 1)];
+        return (t & 1) ? -z.y : z.x;
+      };
+      const float a = sp(l), b = sp(l + H);
+      dst[e] = make_float2(a + b, a - b);
+    }
+    stage_barrier<true>();  // s_buf is rewritten by the next unit
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint spread (gather form, tiled): Q [n_xi][group][H][16] -> Y [N/2+1][group][N][16]
 // workgroup = (cell of kSpreadCell^2 output points, one of its nsub workgroups, slice of
 // kSpreadSlice image groups); it walks its (chunk, image group) steps, chunks outer, with
@@ -976,6 +1077,18 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
 
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st) {
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
+  const bool stream_ok = pl.H % 8 == 0 && pl.H <= kAngStreamH && pl.k_max < pl.H &&
+                         fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
+  if (stream_ok) {
+    const long long units = (long long)pl.n_xi * ngrp;
+    const int U = kAngularUnits;
+    const float sc = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
+    pl.prof.begin(ST_ADJ_ANGULAR, st);
+    hipLaunchKernelGGL(k_adj_angular_stream, dim3((unsigned)((units + U - 1) / U)), dim3(1024), 0, st, D, Q,
+                       pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, ngrp, U, sc);
+    pl.prof.end(st);
+    return hipGetLastError();
+  }
   FftLaunch fa = fft_launch(pl.fft_ang, pl.H + 1);
   dim3 g((unsigned)pl.n_xi, (unsigned)((ngrp * kImgGroup + fa.count - 1) / fa.count));
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
