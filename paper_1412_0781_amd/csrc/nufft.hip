@@ -867,6 +867,139 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// adjoint cols, streaming form (conditions as for the forward streaming forms).  Same
+// result as k_adj_cols.  Unit = (row m2, group of 16 image slots), groups fastest; its
+// input is one contiguous run Y[m2][group][0..N)[16], loaded into registers while the
+// previous unit is transformed; 16 in-place inverse FFTs (conjugate, forward FFT,
+// conjugate) with LDS twiddles and LDS-only barriers; the columns x1 of the pixel range go
+// to Zc [n][N/2+1][L].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __restrict__ Y, float2* __restrict__ Zc,
+                                                            FftDesc fd, const float2* __restrict__ tw, int L,
+                                                            int nimg, int ngrp, int U, FastDiv dL) {
+  constexpr int G = kImgGroup;
+  constexpr int PF = kGridStreamN * G / 2 / 1024;  // pairs of values per thread
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
+  __shared__ float2 s_tw[kGridStreamN];
+  const int N = fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int total = Nh * ngrp;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int x0 = -((L - 1 + 1) / 2);
+  const int nval = N * G / 2;
+  for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
+  __syncthreads();
+  // item e: the values of slots 2e % 16 and 2e % 16 + 1 at m1 = 2e / 16
+  float4 pre[PF];
+  auto load = [&](int u) {
+    const float4* src = (const float4*)(Y + (size_t)u * N * G);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nval) pre[q] = src[e];
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    const int m2 = u / ngrp, grp = u - m2 * ngrp;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nval) {
+        const int m1 = (2 * e) / G, c = (2 * e) & (G - 1);
+        const float4 v = pre[q];
+        s_buf[c * S + fpad(m1)] = make_float2(v.x, -v.y);
+        s_buf[(c + 1) * S + fpad(m1)] = make_float2(v.z, -v.w);
+      }
+    }
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);
+    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    for (int e = tid; e < G * L; e += nthr) {
+      const int c = dL.div(e), a = e - c * L, i = grp * G + c;
+      if (i < nimg) {
+        int pos = x0 + a;
+        pos += (pos < 0) ? N : 0;
+        Zc[((size_t)i * Nh + m2) * L + a] = cconj(s_buf[c * S + fpad(pos)]);
+      }
+    }
+    stage_barrier<true>();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint rows, streaming form (L even).  Same result as k_adj_rows.  Unit = (image, 16
+// row pairs): rows a0 .. a0 + 31 of Zc for every m2 (runs of 32 values), loaded into
+// registers while the previous unit is transformed.  Row pair (a, a + 1) forms one complex
+// sequence z(m) = conj(h_a(m) + i h_b(m)) with the Hermitian completions
+// h(m) = r(m) (m <= N/2), conj r(N - m) (above), placed at m and N - m directly.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __restrict__ Zc, float* __restrict__ img,
+                                                            const float* __restrict__ deconv, FftDesc fd,
+                                                            const float2* __restrict__ tw, int L, int nimg, int U,
+                                                            FastDiv dL) {
+  constexpr int RP = 16;
+  constexpr int PF = ((kGridStreamN / 2 + 1) * RP + 1023) / 1024;  // row-pair values per thread
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
+  __shared__ float2 s_tw[kGridStreamN];
+  __shared__ float s_dec[kGridStreamN / 2];
+  const int N = fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nrb = ((L + 1) / 2 + RP - 1) / RP;
+  const int total = nimg * nrb;
+  const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
+  const int u1 = min(total, u0 + U);
+  const int x0 = -((L - 1 + 1) / 2);
+  const int nval = Nh * RP;
+  for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
+  for (int i = tid; i < L; i += nthr) s_dec[i] = deconv[i];
+  __syncthreads();
+  // item e: rows a0 + 2 (e % 16) and the next one at m2 = e / 16 (one 16-byte pair; L even)
+  float4 pre[PF];
+  auto load = [&](int u) {
+    const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
+    const float2* src = Zc + (size_t)im * Nh * L;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      const int ms = e / RP, a = a0 + 2 * (e & (RP - 1));
+      if (e < nval) pre[q] = a < L ? *(const float4*)(src + (size_t)ms * L + a) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  if (u0 < u1) load(u0);
+  for (int u = u0; u < u1; ++u) {
+    const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nval) {
+        const int ms = e / RP, p = e & (RP - 1);
+        float4 v = pre[q];  // (r_a(ms), r_{a+1}(ms))
+        if (ms == 0 || 2 * ms == N) v.y = v.w = 0.f;
+        float2* row = s_buf + p * S;
+        row[fpad(ms)] = make_float2(v.x - v.w, -(v.y + v.z));
+        if (ms > 0 && 2 * ms < N) row[fpad(N - ms)] = make_float2(v.x + v.w, v.y - v.z);
+      }
+    }
+    stage_barrier<true>();
+    if (u + 1 < u1) load(u + 1);
+    fft_lds_inplace_tw<true, true>(s_buf, RP, S, fd, s_tw);
+    float* dst = img + (size_t)im * L * L;
+    for (int e = tid; e < 2 * RP * L; e += nthr) {
+      const int r = dL.div(e), b = e - r * L, a = a0 + r;
+      if (a < L) {
+        int pos = x0 + b;
+        pos += (pos < 0) ? N : 0;
+        const float2 z = s_buf[(r >> 1) * S + fpad(pos)];  // conj of the inverse transform
+        dst[(size_t)a * L + b] = ((r & 1) ? -z.y : z.x) * s_dec[a] * s_dec[b];
+      }
+    }
+    stage_barrier<true>();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint cols: Y [N/2+1][group][N][16] -> Zc [n][N/2+1][L]: inverse FFT along m1, keep x1 in
 // the pixel range.  workgroup = (row m2, CP consecutive image slots); transforms padded to N+1
 // ---------------------------------------------------------------------------
@@ -1111,6 +1244,20 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   hipLaunchKernelGGL((k_adj_spread<C, NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
                      pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sent, N, Nh, pl.H, ngrp, nsl);
   pl.prof.end(st);
+  const bool stream_ok = N <= kGridStreamN && fft_inplace_capacity(pl.fft_grid, 1024) >= 16 * N && L % 2 == 0;
+  if (stream_ok) {
+    const long long uc = (long long)Nh * ngrp;
+    pl.prof.begin(ST_ADJ_COLS, st);
+    hipLaunchKernelGGL(k_adj_cols_stream, dim3((unsigned)((uc + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
+                       bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, kGridUnits, make_fastdiv(L));
+    pl.prof.end(st);
+    const long long ur = (long long)nimg * (((L + 1) / 2 + 15) / 16);
+    pl.prof.begin(ST_ADJ_ROWS, st);
+    hipLaunchKernelGGL(k_adj_rows_stream, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
+                       bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, kGridUnits, make_fastdiv(L));
+    pl.prof.end(st);
+    return hipGetLastError();
+  }
   FftLaunch fc = fft_launch(pl.fft_grid, N + 1);
   dim3 g2((unsigned)((nimg + fc.count - 1) / fc.count), (unsigned)Nh);
   pl.prof.begin(ST_ADJ_COLS, st);
