@@ -728,16 +728,18 @@ __global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __
 
 // ---------------------------------------------------------------------------
 // adjoint spread (gather form, tiled): Q [n_xi][group][H][16] -> Y [N/2+1][group][N][16]
-// workgroup = (cell of kSpreadCell^2 output points, one of its nsub workgroups, slice of
-// kSpreadSlice image groups); it walks its (chunk, image group) steps, chunks outer, with
-// the next step's node values (one 128-byte line per node: 16 images) and, when the chunk
-// changes, entries on their way into registers.  A cell of several chunks keeps the partial
-// sums of its (at most kSpreadHeavyGroups) image groups in registers, added in chunk order.  Per step the values and entries sit in LDS and
-// lane (point, image pair) sums the point's entries in their fixed order, so the result is
-// the same on every run.  A point's entries come in aligned batches of kSpreadBatch.
-// Spreading weights are non-negative, so an entry carries the conjugate flag as its sign.
+// workgroup = (cell of kSpreadRows x kSpreadCols output points, one of its nsub
+// workgroups, slice of kSpreadSlice image groups); it walks its (chunk, image group) steps,
+// chunks outer, with the next step's node values (one 128-byte line per node: 16 images)
+// and, when the chunk changes, entries on their way into registers.  A cell of several
+// chunks keeps the partial sums of its (at most kSpreadHeavyGroups) image groups in
+// registers, added in chunk order.  Per step the values and entries sit in LDS and lane
+// (point pair, image pair) sums the pair's entries in their fixed order, one 16-byte LDS
+// read of node values for eight FMAs, so the result is the same on every run.  Entries
+// come in aligned batches of kSpreadBatch; spreading weights are non-negative, so each
+// weight carries its point's conjugate flag as its sign.
 // ---------------------------------------------------------------------------
-template <int C, int NT>
+template <int NT>
 __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y,
                                                       const SpreadTile* __restrict__ tiles,
                                                       const SpreadBlock* __restrict__ blocks,
@@ -745,27 +747,31 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
                                                       const int* __restrict__ snodes, const int* __restrict__ sseg,
                                                       const SpreadLocal* __restrict__ sent, int N, int Nh, int H,
                                                       int ngrp, int nsl) {
-  constexpr int G = kImgGroup, IP = G / 2, PC = C * C;
-  constexpr int KQ = kSpreadNodes * IP / NT, KE = kSpreadEntries / 2 / NT;
-  static_assert(NT == PC * IP, "one lane per (point, image pair)");
-  static_assert(KQ * NT == kSpreadNodes * IP && KE * NT * 2 == kSpreadEntries, "staging slots per lane");
-  static_assert(sizeof(SpreadLocal) == 8 && kSpreadBatch == 8, "a batch is four 16-byte vectors");
-  static_assert(kSpreadHeavyGroups == 4, "four partial-sum registers");
+  constexpr int G = kImgGroup, IP = G / 2, NP = kSpreadPairs, CC = kSpreadCols;
+  constexpr int EV = kSpreadEntries * 3 / 4;  // 16-byte vectors of a chunk's entries
+  constexpr int KQ = kSpreadNodes * IP / NT, KE = EV / NT;
+  static_assert(NT == NP * IP, "one lane per (point pair, image pair)");
+  static_assert(KQ * NT == kSpreadNodes * IP && KE * NT == EV, "staging slots per lane");
+  static_assert(sizeof(SpreadLocal) == 12 && kSpreadBatch == 4, "a batch is three 16-byte vectors");
+  static_assert(kSpreadHeavyGroups == 4, "four partial-sum sets");
   __shared__ __attribute__((aligned(16))) float4 s_q[kSpreadNodes * IP];
-  __shared__ __attribute__((aligned(16))) uint4 s_e[kSpreadEntries / 2];
-  const int tid = threadIdx.x, ip = tid & (IP - 1), p = tid / IP;
+  __shared__ __attribute__((aligned(16))) uint4 s_e[EV];
+  const int tid = threadIdx.x, ip = tid & (IP - 1), pp = tid / IP;
   const int slice = (int)(blockIdx.x % (unsigned)nsl);
   const SpreadBlock bk = blocks[blockIdx.x / (unsigned)nsl];
   const SpreadTile t = tiles[bk.tile];
   const int nch = t.c1 - t.c0;
   const int gb = slice * kSpreadSlice + bk.sub, ge = min(ngrp, (slice + 1) * kSpreadSlice);
-  const int m2 = t.m2 + p / C, m1 = t.m1 + p % C;
-  const bool out = m2 < Nh && m1 < N;
+  const int m2 = t.m2 + 2 * (pp / CC), m1 = t.m1 + pp % CC;
+  const bool outA = m2 < Nh && m1 < N, outB = m2 + 1 < Nh && m1 < N;
   float4* Y4 = (float4*)Y;
-  auto yidx = [&](int g) { return (((size_t)m2 * ngrp + g) * N + m1) * IP + ip; };
+  auto yidx = [&](int r, int g) { return (((size_t)r * ngrp + g) * N + m1) * IP + ip; };
+  auto put = [&](int g, float4 a, float4 b) {
+    if (outA) Y4[yidx(m2, g)] = a;
+    if (outB) Y4[yidx(m2 + 1, g)] = b;
+  };
   if (nch == 0) {  // no node reaches this cell
-    for (int g = gb; g < ge; g += t.nsub)
-      if (out) Y4[yidx(g)] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int g = gb; g < ge; g += t.nsub) put(g, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f));
     return;
   }
   // image groups of this workgroup; a cell of several chunks has nsub >= 4, so ng <= 4
@@ -783,13 +789,13 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     const SpreadChunk ch = chunks[c];
     nl_n = ch.n1 - ch.n0;
     const int base = sseg[ch.seg];
-    ne_n = sseg[ch.seg + PC] - base;
-    e0_n = sseg[ch.seg + p] - base;
-    e1_n = sseg[ch.seg + p + 1] - base;
+    ne_n = (sseg[ch.seg + NP] - base) / 4 * 3;  // 16-byte vectors
+    e0_n = (sseg[ch.seg + pp] - base) / 4 * 3;
+    e1_n = (sseg[ch.seg + pp + 1] - base) / 4 * 3;
 #pragma unroll
     for (int k = 0; k < KE; ++k) {
       const int i = tid + k * NT;
-      if (i < ne_n / 2) er[k] = E4[base / 2 + i];
+      if (i < ne_n) er[k] = E4[base / 4 * 3 + i];
     }
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
@@ -801,27 +807,74 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
       }
     }
   };
-  auto load_q = [&](int g) {
+  auto load_q_into = [&](float4 (&dst)[KQ], int g) {
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
-      if (tid + k * NT < nl_n * IP) qr[k] = Q4[qoff[k] + (size_t)g * gstride];
+      if (tid + k * NT < nl_n * IP) dst[k] = Q4[qoff[k] + (size_t)g * gstride];
   };
-  float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
-  // entry: byte offset of the node row in s_q, weight signed by the conjugate flag
+  auto load_q = [&](int g) { load_q_into(qr, g); };
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
+  // entry: byte offset of the node row in s_q, the two points' weights signed by their conjugate flags
   const char* s_lane = (const char*)s_q + ip * sizeof(float4);
-  auto acc = [&](unsigned off, unsigned wbits) {
+  auto acc = [&](unsigned off, unsigned wa_bits, unsigned wb_bits) {
     const float4 q = *(const float4*)(s_lane + off);
-    const float ws = __uint_as_float(wbits), w = fabsf(ws);
-    ax0 = fmaf(w, q.x, ax0);
-    ay0 = fmaf(ws, q.y, ay0);
-    ax1 = fmaf(w, q.z, ax1);
-    ay1 = fmaf(ws, q.w, ay1);
+    const float wsa = __uint_as_float(wa_bits), wa = fabsf(wsa);
+    const float wsb = __uint_as_float(wb_bits), wb = fabsf(wsb);
+    a0 = fmaf(wa, q.x, a0);
+    a1 = fmaf(wsa, q.y, a1);
+    a2 = fmaf(wa, q.z, a2);
+    a3 = fmaf(wsa, q.w, a3);
+    b0 = fmaf(wb, q.x, b0);
+    b1 = fmaf(wsb, q.y, b1);
+    b2 = fmaf(wb, q.z, b2);
+    b3 = fmaf(wsb, q.w, b3);
   };
+  auto sum_entries = [&](int e0, int e1) {
+    a0 = a1 = a2 = a3 = b0 = b1 = b2 = b3 = 0.f;
+    for (int e = e0; e < e1; e += 3) {
+      const uint4 v0 = s_e[e], v1 = s_e[e + 1], v2 = s_e[e + 2];
+      acc(v0.x, v0.y, v0.z);
+      acc(v0.w, v1.x, v1.y);
+      acc(v1.z, v1.w, v2.x);
+      acc(v2.y, v2.z, v2.w);
+    }
+  };
+  if (nch == 1) {
+    // one chunk: its entries go to LDS once; the image groups' values are prefetched two
+    // groups ahead in two register sets
+    if (ng == 0) return;
+    load_meta(t.c0);
+    float4 qb[KQ];
+    load_q_into(qr, gb);
+    if (ng > 1) load_q_into(qb, gb + t.nsub);
+    const int e0 = e0_n, e1 = e1_n;
+    auto step = [&](float4 (&cur)[KQ], int gi) {
+      __syncthreads();  // the previous step's readers are done with LDS
+#pragma unroll
+      for (int k = 0; k < KQ; ++k)
+        if (tid + k * NT < nl_n * IP) s_q[tid + k * NT] = cur[k];
+      if (gi == 0) {
+#pragma unroll
+        for (int k = 0; k < KE; ++k)
+          if (tid + k * NT < ne_n) s_e[tid + k * NT] = er[k];
+      }
+      __syncthreads();
+      if (gi + 2 < ng) load_q_into(cur, gb + (gi + 2) * t.nsub);
+      sum_entries(e0, e1);
+      put(gb + gi * t.nsub, make_float4(a0, a1, a2, a3), make_float4(b0, b1, b2, b3));
+    };
+    for (int gi = 0; gi < ng; gi += 2) {
+      step(qr, gi);
+      if (gi + 1 < ng) step(qb, gi + 1);
+    }
+    return;
+  }
   if (nsteps > 0) {
     load_meta(t.c0);
     load_q(gb);
   }
-  float4 P0 = make_float4(0.f, 0.f, 0.f, 0.f), P1 = P0, P2 = P0, P3 = P0;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 PA0 = z4, PB0 = z4, PA1 = z4, PB1 = z4, PA2 = z4, PB2 = z4, PA3 = z4, PB3 = z4;
   for (int s = 0; s < nsteps; ++s) {
     const int ci = s / ng, gi = s - ci * ng;
     const int g = gb + gi * t.nsub;
@@ -832,37 +885,31 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     if (gi == 0) {
 #pragma unroll
       for (int k = 0; k < KE; ++k)
-        if (tid + k * NT < ne_n / 2) s_e[tid + k * NT] = er[k];
+        if (tid + k * NT < ne_n) s_e[tid + k * NT] = er[k];
     }
     const int e0 = e0_n, e1 = e1_n;
     __syncthreads();
     const bool same_chunk = gi + 1 < ng;
     if (same_chunk) load_q(g + t.nsub);
     else if (ci + 1 < nch) load_meta(t.c0 + ci + 1);
-    ax0 = ay0 = ax1 = ay1 = 0.f;
-    for (int e = e0 / 2; e < e1 / 2; e += kSpreadBatch / 2) {
-      uint4 v[kSpreadBatch / 2];
-#pragma unroll
-      for (int u = 0; u < kSpreadBatch / 2; ++u) v[u] = s_e[e + u];
-#pragma unroll
-      for (int u = 0; u < kSpreadBatch / 2; ++u) {
-        acc(v[u].x, v[u].y);
-        acc(v[u].z, v[u].w);
-      }
-    }
+    sum_entries(e0, e1);
     if (!same_chunk && ci + 1 < nch) load_q(gb);
-    float4 r = make_float4(ax0, ay0, ax1, ay1);
+    float4 ra = make_float4(a0, a1, a2, a3), rb = make_float4(b0, b1, b2, b3);
     if (nch > 1) {
-      auto upd = [&](float4& P) {
-        if (ci > 0) r = make_float4(P.x + r.x, P.y + r.y, P.z + r.z, P.w + r.w);
-        P = r;
+      auto upd = [&](float4& PA, float4& PB) {
+        if (ci > 0) {
+          ra = make_float4(PA.x + ra.x, PA.y + ra.y, PA.z + ra.z, PA.w + ra.w);
+          rb = make_float4(PB.x + rb.x, PB.y + rb.y, PB.z + rb.z, PB.w + rb.w);
+        }
+        PA = ra;
+        PB = rb;
       };
-      if (gi == 0) upd(P0);
-      else if (gi == 1) upd(P1);
-      else if (gi == 2) upd(P2);
-      else upd(P3);
+      if (gi == 0) upd(PA0, PB0);
+      else if (gi == 1) upd(PA1, PB1);
+      else if (gi == 2) upd(PA2, PB2);
+      else upd(PA3, PB3);
     }
-    if (ci == nch - 1 && out) Y4[yidx(g)] = r;
+    if (ci == nch - 1) put(g, ra, rb);
   }
 }
 
@@ -1236,12 +1283,12 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
                                 float* images, hipStream_t st) {
   const int N = pl.N, L = pl.L, Nh = N / 2 + 1;
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
-  constexpr int C = kSpreadCell, NT = kSpreadCell * kSpreadCell * kImgGroup / 2;
+  constexpr int NT = kSpreadPairs * kImgGroup / 2;
   const int nsl = (ngrp + kSpreadSlice - 1) / kSpreadSlice;
   const size_t nblk = pl.sblocks.size() * (size_t)nsl;
   if (nblk > 0x7fffffffu) return hipErrorInvalidValue;
   pl.prof.begin(ST_ADJ_SPREAD, st);
-  hipLaunchKernelGGL((k_adj_spread<C, NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
+  hipLaunchKernelGGL((k_adj_spread<NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
                      pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sent, N, Nh, pl.H, ngrp, nsl);
   pl.prof.end(st);
   const bool stream_ok = N <= kGridStreamN && fft_inplace_capacity(pl.fft_grid, 1024) >= 16 * N && L % 2 == 0;

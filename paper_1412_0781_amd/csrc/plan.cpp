@@ -254,40 +254,73 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     std::vector<int> fill(pl.csr_ptr.begin(), pl.csr_ptr.end() - 1);
     for_each_tap([&](size_t row, uint32_t node, float om) { pl.csr[fill[row]++] = SpreadEntry{node, om}; });
 
-    // tiled form: per output cell, the distinct nodes of its points' entries in chunks
-    const int C = kSpreadCell, PC = C * C;
-    const int ncy = (Nh + C - 1) / C, ncx = (N + C - 1) / C;
+    // tiled form: per output cell, the pair entries of its point pairs and the distinct
+    // nodes they use, in chunks
+    const int CR = kSpreadRows, CC = kSpreadCols, NP = kSpreadPairs;
+    const int ncy = (Nh + CR - 1) / CR, ncx = (N + CC - 1) / CC;
     pl.stiles.clear();
     pl.sblocks.clear();
     pl.schunks.clear();
     pl.snodes.clear();
     pl.sseg.clear();
     pl.sent.clear();
-    pl.sent.reserve(pl.csr.size() + pl.csr.size() / 4);
+    pl.sent.reserve(pl.csr.size());
+    struct PairTmp {
+      uint32_t key;  // node * 2 + conjugate flag
+      float wa, wb;
+    };
     std::vector<int> where(pl.nodes.size(), -1);  // node -> index in the cell's node list
     std::vector<int> cell_nodes;
-    std::vector<std::vector<uint8_t>> node_pts;   // points reached by each listed node
-    std::vector<int> pcnt(PC);
+    std::vector<std::vector<PairTmp>> plist(NP);
+    std::vector<std::vector<uint8_t>> node_pairs;  // pairs reached by each listed node (per key)
+    std::vector<int> pcnt(NP);
+    std::vector<std::pair<uint32_t, float>> la, lb;
+    auto point_list = [&](int m2, int m1, std::vector<std::pair<uint32_t, float>>& out) {
+      out.clear();
+      if (m2 >= Nh || m1 >= N) return;
+      const size_t row = (size_t)m2 * N + m1;
+      for (int e = pl.csr_ptr[row]; e < pl.csr_ptr[row + 1]; ++e) {
+        const uint32_t nd = pl.csr[e].node & 0x7fffffffu, cj = pl.csr[e].node >> 31;
+        out.push_back({nd * 2u + cj, pl.csr[e].weight});
+      }
+      std::stable_sort(out.begin(), out.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    };
     auto padded = [](int n) { return (n + kSpreadBatch - 1) / kSpreadBatch * kSpreadBatch; };
     for (int cy = 0; cy < ncy; ++cy)
       for (int cx = 0; cx < ncx; ++cx) {
         cell_nodes.clear();
-        for (int p = 0; p < PC; ++p) {
-          int m2 = cy * C + p / C, m1 = cx * C + p % C;
-          if (m2 >= Nh || m1 >= N) continue;
-          size_t row = (size_t)m2 * N + m1;
-          for (int e = pl.csr_ptr[row]; e < pl.csr_ptr[row + 1]; ++e) {
-            int nd = (int)(pl.csr[e].node & 0x7fffffffu);
+        for (int pp = 0; pp < NP; ++pp) {
+          const int m2 = cy * CR + 2 * (pp / CC), m1 = cx * CC + pp % CC;
+          point_list(m2, m1, la);
+          point_list(m2 + 1, m1, lb);
+          auto& L2 = plist[pp];
+          L2.clear();
+          size_t i = 0, k = 0;
+          while (i < la.size() || k < lb.size()) {
+            if (k >= lb.size() || (i < la.size() && la[i].first < lb[k].first)) {
+              L2.push_back({la[i].first, la[i].second, 0.f});
+              ++i;
+            } else if (i >= la.size() || lb[k].first < la[i].first) {
+              L2.push_back({lb[k].first, 0.f, lb[k].second});
+              ++k;
+            } else {
+              L2.push_back({la[i].first, la[i].second, lb[k].second});
+              ++i;
+              ++k;
+            }
+          }
+          for (const PairTmp& t : L2) {
+            const int nd = (int)(t.key >> 1);
             if (where[nd] < 0) {
               where[nd] = (int)cell_nodes.size();
               cell_nodes.push_back(nd);
-              if (node_pts.size() < cell_nodes.size()) node_pts.resize(cell_nodes.size());
-              node_pts[where[nd]].clear();
+              if (node_pairs.size() < cell_nodes.size()) node_pairs.resize(cell_nodes.size());
+              node_pairs[where[nd]].clear();
             }
-            node_pts[where[nd]].push_back((uint8_t)p);
+            node_pairs[where[nd]].push_back((uint8_t)pp);
           }
         }
-        SpreadTile t{cy * C, cx * C, (int)pl.schunks.size(), 0, 1, {0, 0, 0}};
+        SpreadTile t{cy * CR, cx * CC, (int)pl.schunks.size(), 0, 1, {0, 0, 0}};
         const int nn = (int)cell_nodes.size();
         for (int a0 = 0; a0 < nn;) {
           // greedy chunk: as many nodes as fit kSpreadNodes and, padded, kSpreadEntries
@@ -295,12 +328,12 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
           int a1 = a0, total = 0;
           while (a1 < nn && a1 - a0 < kSpreadNodes) {
             int grow = 0;
-            for (uint8_t p : node_pts[a1]) {
-              grow += padded(pcnt[p] + 1) - padded(pcnt[p]);
-              pcnt[p]++;
+            for (uint8_t q : node_pairs[a1]) {
+              grow += padded(pcnt[q] + 1) - padded(pcnt[q]);
+              pcnt[q]++;
             }
             if (total + grow > kSpreadEntries) {
-              for (uint8_t p : node_pts[a1]) pcnt[p]--;
+              for (uint8_t q : node_pairs[a1]) pcnt[q]--;
               break;
             }
             total += grow;
@@ -308,24 +341,20 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
           }
           SpreadChunk ch{(int)pl.snodes.size(), 0, (int)pl.sseg.size(), 0};
           for (int a = a0; a < a1; ++a) {
-            int nd = cell_nodes[a];
+            const int nd = cell_nodes[a];
             pl.snodes.push_back(((nd / pl.H) << 16) | (nd % pl.H));
           }
           ch.n1 = (int)pl.snodes.size();
-          for (int p = 0; p < PC; ++p) {
+          for (int pp = 0; pp < NP; ++pp) {
             pl.sseg.push_back((int)pl.sent.size());
-            int m2 = cy * C + p / C, m1 = cx * C + p % C;
-            if (m2 >= Nh || m1 >= N) continue;
-            size_t row = (size_t)m2 * N + m1;
-            for (int e = pl.csr_ptr[row]; e < pl.csr_ptr[row + 1]; ++e) {
-              int nd = (int)(pl.csr[e].node & 0x7fffffffu);
-              int li = where[nd];
+            for (const PairTmp& e : plist[pp]) {
+              const int li = where[(int)(e.key >> 1)];
               if (li < a0 || li >= a1) continue;
-              const float wt = pl.csr[e].weight;
-              pl.sent.push_back(SpreadLocal{(uint32_t)(li - a0) * kImgGroup * 8u,
-                                            (pl.csr[e].node >> 31) ? -wt : wt});
+              const bool cj = e.key & 1u;
+              pl.sent.push_back(SpreadLocal{(uint32_t)(li - a0) * kImgGroup * 8u, cj ? -e.wa : e.wa,
+                                            cj ? -e.wb : e.wb});
             }
-            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0u, 0.f});
+            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0u, 0.f, 0.f});
           }
           pl.sseg.push_back((int)pl.sent.size());
           pl.schunks.push_back(ch);

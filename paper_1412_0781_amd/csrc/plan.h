@@ -88,21 +88,26 @@ struct SpreadEntry {
   uint32_t node;
   float weight;
 };
-// Tiled adjoint spread: the folded half-plane grid is cut into kSpreadCell x kSpreadCell
-// output cells.  The nodes that reach a cell are listed once (packed j << 16 | l) and
-// split into chunks of at most kSpreadNodes nodes and kSpreadEntries entries; a workgroup
-// stages one chunk's node values (one image group) and entries in LDS, and every output
-// point sums its entries of that chunk (LDS offset, signed weight), in the order
-// of the point's spreading entries.  Each point's entries of a chunk are padded with
-// zero-weight entries to a multiple of kSpreadBatch, so that they are read in aligned
-// batches.  A cell with several chunks is split over nsub >= kSpreadSlice / kSpreadHeavyGroups
-// workgroups per slice of kSpreadSlice image groups (workgroup r of the cell takes groups
-// r, r + nsub, ...), each walking the chunks in order with the next image group's values
-// prefetched and per-group partial sums in registers.
-constexpr int kSpreadCell = 8;
+// Tiled adjoint spread: the folded half-plane grid is cut into cells of kSpreadRows x
+// kSpreadCols output points, taken as pairs of vertically neighbouring points (m2, m2 + 1),
+// which share most of the nodes that reach them.  The nodes that reach a cell are listed
+// once (packed j << 16 | l) and split into chunks of at most kSpreadNodes nodes and
+// kSpreadEntries pair entries; a workgroup stages one chunk's node values (one image
+// group) and entries in LDS, and every pair sums its entries of that chunk: one entry per
+// (node, conjugate flag) reaching either point, with the LDS offset of the node's values
+// and one weight per point (0 where the node misses that point), in node order.  Each
+// pair's entries of a chunk are padded with zero-weight entries to a multiple of
+// kSpreadBatch, so that they are read in aligned batches.  A cell with several chunks is
+// split over nsub >= kSpreadSlice / kSpreadHeavyGroups workgroups per slice of
+// kSpreadSlice image groups (workgroup r of the cell takes groups r, r + nsub, ...), each
+// walking the chunks in order with the next image group's values prefetched and
+// per-group partial sums in registers.
+constexpr int kSpreadRows = 16;
+constexpr int kSpreadCols = 8;
+constexpr int kSpreadPairs = kSpreadRows / 2 * kSpreadCols;
 constexpr int kSpreadNodes = 256;
-constexpr int kSpreadEntries = 6144;
-constexpr int kSpreadBatch = 8;
+constexpr int kSpreadEntries = 4096;
+constexpr int kSpreadBatch = 4;
 constexpr int kSpreadSlice = 16;
 constexpr int kSpreadHeavyGroups = 4;
 struct SpreadTile {
@@ -117,12 +122,13 @@ struct SpreadBlock {
 };
 struct SpreadChunk {
   int n0, n1;    // node range in the chunk node list
-  int seg;       // kSpreadCell^2 + 1 entry offsets of this chunk's points start here
+  int seg;       // kSpreadPairs + 1 entry offsets of this chunk's pairs start here
   int pad;
 };
 struct SpreadLocal {
   uint32_t off;   // byte offset of the node's values (one image group) in the chunk's LDS copy
-  float weight;   // spreading weight (>= 0), negated when the conjugate of the node value is taken
+  float wa, wb;   // spreading weights (>= 0) of the upper and lower point, each negated when
+                  // that point takes the conjugate of the node value
 };
 
 // Kernel stages, in launch order (names in stage_name()).
