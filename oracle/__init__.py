@@ -49,3 +49,4 @@ from .fb import (  # noqa: F401
     coeff_inner,
 )
 from . import spca  # noqa: F401,E402
+from . import estimate  # noqa: F401,E402

@@ -347,13 +347,17 @@ def coeff_inner(a: np.ndarray, b: np.ndarray, pl: Plan) -> np.ndarray:
     return s0 + 2.0 * s1
 
 
-def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096) -> np.ndarray:
+def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096, ring_filter=None) -> np.ndarray:
     """(T b)(x) = Re sum_{k=-kmax..kmax} sum_q b_{kq} conj(M_{kq}(x)), with b_{-k} = conj(b_k).
 
     M_{kq}(x) is the row of T* for coefficient (k, q): Eq.(nufft), Eq.(1DFFT)
     and Eq.(a) composed.  Folding +-k gives weight 1 for k = 0 and 2 for k > 0.
     Computed as the transpose of each step in turn: the radial sum, the angular
     sum, then the direct type-1 sum over the polar nodes.
+
+    ring_filter (optional, [n_xi]) multiplies the spectrum on ring j by H(xi_j) after the
+    radial sum: the image of a radially symmetric Fourier filter H applied to the
+    band-limited synthesis (the convolution of Sec. VI-C's CTF workload).
     """
     b = np.asarray(b, dtype=np.complex128)
     n = b.shape[0]
@@ -363,6 +367,8 @@ def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096) -> np.ndarray:
         o = pl.coef_off[k]
         wk = 1.0 if k == 0 else 2.0
         D[:, :, k] = wk * (b[:, o:o + pl.p[k]] @ pl.B[k])              # sum_q B_qj b_kq
+    if ring_filter is not None:
+        D *= np.asarray(ring_filter, dtype=np.float64)[None, :, None]
     l = np.arange(pl.n_theta)
     kk = np.arange(K + 1)
     phase = (np.outer(l, kk) % pl.n_theta) / pl.n_theta
