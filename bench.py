@@ -311,6 +311,28 @@ def main():
     adjoint = {"images": na, "ms": round(adj_ms, 3), "images_per_s": round(na / (adj_ms * 1e-3), 1)}
     log(f"adjoint: {adjoint}")
 
+    # estimation of R and c (Sec. VI-C) on a CTF-filtered workload (Eq.(CTFenv), 1 A per pixel,
+    # noise at SNR 1/2 over the filtered clean power), outside images/s
+    from paper_1412_0781_amd import workload as wl
+    ne = min(args.n, 20000)
+    Hf = wl.ctf_ring_filter(plan)
+    clean = wl.synthetic_images(plan, 0, 256, seed=1, snr=1.0, ring_filter=Hf, sigma=0.0)
+    sig = float((clean.double().pow(2).mean() / 0.5).sqrt())
+    del clean
+    imgs_e = wl.synthetic_images(plan, 0, ne, seed=1, snr=1.0, ring_filter=Hf, sigma=sig)
+    plan.pixel_moments(imgs_e[:64])  # warm-up
+
+    def estimate_rc():
+        s1, s2 = plan.pixel_moments(imgs_e)
+        pw = plan.polar_power(imgs_e, pixel_sum=s1, count=ne, batch=args.pass_images)
+        return plan.estimate_support(s1, s2, ne, pw, sig * sig, 0.999)
+
+    (R_est, c_est), est_ms = timed(estimate_rc)
+    del imgs_e
+    support = {"images": ne, "ms": round(est_ms, 3), "images_per_s": round(ne / (est_ms * 1e-3), 1), "R": R_est,
+               "c": round(c_est, 4), "workload": "CTF-filtered synthesis, support R=L/2, SNR 1/2"}
+    log(f"support estimate: {support}")
+
     # per-kernel figures of the headline form; dominant kernel against the HBM roofline
     prof = profs[head]
     bpi = algorithmic_bytes_per_image(plan)
@@ -379,6 +401,7 @@ def main():
         "svd": svd,
         "spca": spca,
         "adjoint": adjoint,
+        "support_estimate": support,
         "plan_s": round(plan_s, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,

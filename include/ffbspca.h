@@ -134,6 +134,13 @@ int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int
  * fb_expand, used for gradients).  Asynchronous; same errors as fb_expand. */
 int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode,
                void* ws, size_t ws_bytes, void* stream);
+/* fb_adjoint with a radially symmetric Fourier filter: ring_filter (device FP32 [n_xi],
+ * nullable = no filter) multiplies the spectrum on ring xi_j by H(xi_j) before the
+ * angular and polar steps, i.e. the synthesised image is convolved with the inverse
+ * transform of H restricted to the band (the CTF-filtered workload of Sec. VI-C,
+ * Eq.(CTFenv), with H evaluated at the plan's xi_j by the caller).  Same errors. */
+int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode,
+                        const float* ring_filter, void* ws, size_t ws_bytes, void* stream);
 
 /* Accumulate the steerable covariance of n coefficient vectors (Eqs.(ck),(ck_0)):
  *   G[cov_off[k] + q p_k + q'] += sum_i Re(a^i_{kq} conj(a^i_{kq'}))   (FP64, full p_k x p_k blocks)
@@ -209,6 +216,34 @@ int fb_spca_reconstruct(fb_plan_t plan, const float* c, int64_t n, const double*
 int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream);
 int fb_eigenimages(fb_plan_t plan, const double* evecs, int k, int l0, int nl, double* out, void* stream);
 
+/* Estimation of the support radius R and the band limit c from noisy images (Sec. VI-C).
+ * fb_pixel_moments: sum[p] += sum_i I_i(p), sumsq[p] += sum_i I_i(p)^2 (device FP64 [L*L],
+ *   caller-owned, zero them first); images device float32 [n][L][L]; ws of at least
+ *   fb_moments_workspace_bytes(plan) bytes, 8-byte aligned.  Fixed summation order.
+ * fb_polar_power: power[j] += sum_i sum_{l < n_theta/2} |F(I_i - mean)(xi_j, theta_l)|^2
+ *   (device FP64 [n_xi], caller-owned; Eq.(nufft) with unit normalisation at the plan's
+ *   polar nodes; a plan with c = 1/2 covers the band up to Nyquist).  The mean image is
+ *   pixel_sum / count (pixel_sum device FP64 [L*L], e.g. from fb_pixel_moments; NULL: no
+ *   subtraction).  ws of at least fb_polar_power_workspace_bytes(plan, batch) bytes.
+ * fb_estimate_support: out[0] = R, out[1] = c (device FP64 [2]).  The mean radial variance
+ *   v_r averages sumsq/n - (sum/n)^2 over the pixels with round(|x|) = r, r = 0 .. L/2;
+ *   R is the smallest r at which sum_{r' <= r} (v_r' - noise_var) r' reaches frac of its
+ *   total.  The mean radial power spectrum is p_j = power[j] / (n (n_theta/2) L^2); c is the
+ *   smallest xi_j at which sum_{j' <= j} (p_j' - noise_var) xi_j' w_j' reaches frac of its
+ *   total (w_j the Gauss-Legendre weights).  One workgroup; FP64, sums in pixel and ring
+ *   order.  frac in (0, 1] (the paper's 0.999).
+ * Asynchronous on `stream`; allocate nothing.  Errors: FB_ERR_INVALID_ARG (NULL pointers,
+ * n < 0 (n <= 0 for the estimate), pixel_sum with count <= 0, frac outside (0, 1],
+ * misaligned ws), FB_ERR_WORKSPACE, FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+size_t fb_moments_workspace_bytes(fb_plan_t plan);
+int fb_pixel_moments(fb_plan_t plan, const float* images, int64_t n, double* sum, double* sumsq, void* ws,
+                     size_t ws_bytes, void* stream);
+size_t fb_polar_power_workspace_bytes(fb_plan_t plan, int64_t batch);
+int fb_polar_power(fb_plan_t plan, const float* images, int64_t n, const double* pixel_sum, int64_t count,
+                   double* power, void* ws, size_t ws_bytes, void* stream);
+int fb_estimate_support(fb_plan_t plan, const double* sum, const double* sumsq, int64_t n, const double* power,
+                        double noise_var, double frac, double* out, void* stream);
+
 /* Principal components by the SVD of the coefficient matrices (Sec. III-C: the left
  * singular vectors of A^(k) in place of the eigenvectors of C^(k), same complexity,
  * better conditioning).  For each k the real matrix X^(k) = [Re A^(k)^T; Im A^(k)^T]
@@ -255,7 +290,7 @@ int fb_synth_words(uint64_t seed, uint32_t rng_stream, int64_t first_index, int6
  * the number of stages (FB_NUM_STAGES) or a negative FB_ERR_* code.  Stage
  * names come from fb_stage_name.  Not for concurrent use of one plan from
  * several streams while enabled. */
-#define FB_NUM_STAGES 14
+#define FB_NUM_STAGES 15
 int fb_profile_enable(fb_plan_t plan, int enable);
 int fb_profile_read(fb_plan_t plan, double* total_ms, int64_t* launches, int max_stages, int reset);
 const char* fb_stage_name(int stage);

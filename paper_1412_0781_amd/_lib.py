@@ -56,6 +56,15 @@ SIGNATURES = [
     ("fb_spca_reconstruct", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_spca_radial", c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_eigenimages", c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+    ("fb_adjoint_filtered", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_size_t,
+                                    c_void_p]),
+    ("fb_moments_workspace_bytes", c_size_t, [c_void_p]),
+    ("fb_pixel_moments", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    ("fb_polar_power_workspace_bytes", c_size_t, [c_void_p, c_int64]),
+    ("fb_polar_power", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
+                               c_void_p]),
+    ("fb_estimate_support", c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_double, c_double, c_void_p,
+                                    c_void_p]),
     ("fb_svd_workspace_bytes", c_size_t, [c_void_p, c_int64]),
     ("fb_svd", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("fb_synth_normals", c_int, [c_uint64, c_uint32, c_int64, c_int64, c_int64, c_float, c_void_p, c_void_p]),

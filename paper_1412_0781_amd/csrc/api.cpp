@@ -158,6 +158,11 @@ int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int
 
 int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode, void* ws,
                size_t ws_bytes, void* stream) {
+  return fb_adjoint_filtered(plan, coeffs, n, images, weight_mode, nullptr, ws, ws_bytes, stream);
+}
+
+int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode,
+                        const float* ring_filter, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || n < 0 || (weight_mode != 0 && weight_mode != 1)) return FB_ERR_INVALID_ARG;
   if (n == 0) return FB_OK;
   if (!images || !coeffs || !ws) return FB_ERR_INVALID_ARG;
@@ -172,7 +177,8 @@ int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, in
   const size_t coef_stride = 2 * (size_t)pl.p_half;
   for (int64_t s = 0; s < n; s += nb) {
     int m = (int)std::min<int64_t>(nb, n - s);
-    int rc = hip_rc(pl, fb::launch_radial_adjoint(pl, coeffs + s * coef_stride, bufB, m, weight_mode, st));
+    int rc = hip_rc(pl, fb::launch_radial_adjoint(pl, coeffs + s * coef_stride, bufB, m, weight_mode,
+                                                  ring_filter, st));
     if (rc == FB_OK) rc = hip_rc(pl, fb::launch_adjoint_angular(pl, bufB, bufA, m, st));
     if (rc == FB_OK) rc = hip_rc(pl, fb::launch_adjoint_nufft(pl, bufA, m, bufA, bufB, images + s * img_stride, st));
     if (rc != FB_OK) return rc;
@@ -244,6 +250,78 @@ int fb_spca_radial(fb_plan_t plan, const double* evecs, float* f, void* stream) 
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   return hip_rc(pl, fb::launch_spca_radial(pl, evecs, f, (hipStream_t)stream));
+}
+
+size_t fb_moments_workspace_bytes(fb_plan_t plan) {
+  if (!plan) return 0;
+  return fb::moments_workspace_bytes(plan->pl);
+}
+
+int fb_pixel_moments(fb_plan_t plan, const float* images, int64_t n, double* sum, double* sumsq, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (n == 0) return FB_OK;
+  if (!images || !sum || !sumsq || !ws || (uintptr_t)ws % 8 != 0) return FB_ERR_INVALID_ARG;
+  if (ws_bytes < fb::moments_workspace_bytes(pl)) return FB_ERR_WORKSPACE;
+  return hip_rc(pl, fb::launch_pixel_moments(pl, images, n, sum, sumsq, (double*)ws, (hipStream_t)stream));
+}
+
+// polar power workspace: mean image (L^2 floats), its polar samples (n_xi H complex), then
+// the pass buffers of fb_expand
+static size_t power_head_bytes(const fb::Plan& pl) {
+  const size_t a = ((size_t)pl.L * pl.L * sizeof(float) + kAlign - 1) & ~(size_t)(kAlign - 1);
+  const size_t b = ((size_t)pl.n_xi * pl.H * sizeof(float2) + kAlign - 1) & ~(size_t)(kAlign - 1);
+  return a + b + kAlign;
+}
+
+size_t fb_polar_power_workspace_bytes(fb_plan_t plan, int64_t batch) {
+  if (!plan || batch < 1) return 0;
+  return power_head_bytes(plan->pl) + fb_workspace_bytes(plan, batch, FB_FP32);
+}
+
+int fb_polar_power(fb_plan_t plan, const float* images, int64_t n, const double* pixel_sum, int64_t count,
+                   double* power, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  if (n == 0) return FB_OK;
+  if (!images || !power || !ws || (pixel_sum && count <= 0)) return FB_ERR_INVALID_ARG;
+  const size_t head = power_head_bytes(pl);
+  if (ws_bytes < head) return FB_ERR_WORKSPACE;
+  const uintptr_t base = ((uintptr_t)ws + kAlign - 1) & ~(uintptr_t)(kAlign - 1);
+  float* mean = (float*)base;
+  float2* pmean = (float2*)(base + (((size_t)pl.L * pl.L * sizeof(float) + kAlign - 1) & ~(size_t)(kAlign - 1)));
+  void* rest = (char*)ws + head;
+  fb::PassLayout lay = fb::pass_layout(pl);
+  float2 *bufA = nullptr, *bufB = nullptr;
+  int64_t nb = split_workspace(lay, rest, ws_bytes - head, n, &bufA, &bufB);
+  if (nb < 1) return FB_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = FB_OK;
+  if (pixel_sum) {
+    rc = hip_rc(pl, fb::launch_mean_image(pl, pixel_sum, count, mean, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_forward_nufft(pl, mean, 1, bufA, bufB, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_copy_polar(pl, bufA, pmean, st));
+    if (rc != FB_OK) return rc;
+  }
+  const size_t img_stride = (size_t)pl.L * pl.L;
+  for (int64_t s = 0; s < n; s += nb) {
+    int m = (int)std::min<int64_t>(nb, n - s);
+    rc = hip_rc(pl, fb::launch_forward_nufft(pl, images + s * img_stride, m, bufA, bufB, st));
+    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_polar_power(pl, bufA, pixel_sum ? pmean : nullptr, m, power, st));
+    if (rc != FB_OK) return rc;
+  }
+  return FB_OK;
+}
+
+int fb_estimate_support(fb_plan_t plan, const double* sum, const double* sumsq, int64_t n, const double* power,
+                        double noise_var, double frac, double* out, void* stream) {
+  if (!plan || n <= 0 || !sum || !sumsq || !power || !out || !(frac > 0.0 && frac <= 1.0)) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  return hip_rc(pl, fb::launch_estimate_support(pl, sum, sumsq, n, power, noise_var, frac, out, (hipStream_t)stream));
 }
 
 size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n) {

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
                                                         const GemmItem* __restrict__ items,
                                                         const int* __restrict__ coef_off, const int* __restrict__ p,
                                                         int n_xi, int nk, int ncol, long long p_half,
-                                                        int weight_mode) {
+                                                        int weight_mode, const float* __restrict__ ring_filter) {
   __shared__ float As[BK][BM + 4];
   __shared__ float Bs[BK][BN + 4];
   const GemmItem it = items[blockIdx.y];
@@ -272,8 +272,9 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
     int j = j0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
     if (j < n_xi && c < ncol) {
       const int img = c >> 1;
+      const float h = ring_filter ? ring_filter[j] : 1.f;  // radial filter H(xi_j), if any
       D[((((size_t)(img / kImgGroup) * n_xi + j) * nk + k) * kImgGroup + (img & (kImgGroup - 1))) * 2 + (c & 1)] =
-          wk * acc[i];
+          h * (wk * acc[i]);
     }
   }
 }
@@ -469,12 +470,13 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
 }
 
 hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
-                                 hipStream_t st) {
+                                 const float* ring_filter, hipStream_t st) {
   const int ncol = 2 * nimg;
   dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_adj.size());
   pl.prof.begin(ST_RADIAL_ADJ, st);
   hipLaunchKernelGGL(k_radial_adj_f32, g, dim3(256), 0, st, pl.d_radial, coeffs, (float*)D, pl.d_items_adj,
-                     pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half, weight_mode);
+                     pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half, weight_mode,
+                     ring_filter);
   pl.prof.end(st);
   return hipGetLastError();
 }

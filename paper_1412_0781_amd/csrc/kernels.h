@@ -23,7 +23,7 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
 
 // transposes
 hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
-                                 hipStream_t st);
+                                 const float* ring_filter, hipStream_t st);
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st);
 hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
                                 float* images, hipStream_t st);
@@ -73,6 +73,17 @@ size_t svd_qr_lds_bytes(const Plan& pl);
 hipError_t configure_svd_kernels();
 hipError_t launch_svd(const Plan& pl, const float* coeffs, long long n, double* evals, double* evecs,
                       double* mean_out, double* ws, hipStream_t st);
+// Estimation of R and c (Sec. VI-C)
+constexpr int kMomentSlices = 64;  // image slices of the per-pixel moments
+size_t moments_workspace_bytes(const Plan& pl);
+hipError_t launch_pixel_moments(const Plan& pl, const float* images, long long n, double* sum, double* sumsq,
+                                double* ws, hipStream_t st);
+hipError_t launch_mean_image(const Plan& pl, const double* sum, long long count, float* mean, hipStream_t st);
+hipError_t launch_polar_power(const Plan& pl, const float2* P, const float2* Pmean, int nimg, double* power,
+                              hipStream_t st);
+hipError_t launch_copy_polar(const Plan& pl, const float2* P, float2* dst, hipStream_t st);
+hipError_t launch_estimate_support(const Plan& pl, const double* sum, const double* sumsq, long long n,
+                                   const double* power, double noise_var, double frac, double* out, hipStream_t st);
 hipError_t launch_eigenimages(const Plan& pl, const double* evecs, int k, int l0, int nl, double* out,
                               hipStream_t st);
 

@@ -423,6 +423,8 @@ int upload_plan(Plan& pl) {
   std::vector<float> xw(pl.n_xi);
   for (int j = 0; j < pl.n_xi; ++j) xw[j] = (float)(pl.xi[j] * pl.wq[j]);
   FB_HIP_TRY(upload(&pl.d_xw, xw.data(), xw.size()));
+  FB_HIP_TRY(upload(&pl.d_xi, pl.xi.data(), pl.xi.size()));
+  FB_HIP_TRY(upload(&pl.d_wq, pl.wq.data(), pl.wq.size()));
   FB_HIP_TRY(upload(&pl.d_roots, pl.roots.data(), pl.roots.size()));
   std::vector<int> off32(pl.coef_off.begin(), pl.coef_off.end());
   FB_HIP_TRY(upload(&pl.d_coef_off, off32.data(), off32.size()));
@@ -452,7 +454,7 @@ int upload_plan(Plan& pl) {
 
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
-  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
+  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
@@ -460,6 +462,8 @@ void free_device(Plan& pl) {
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
   pl.d_xw = nullptr;
+  pl.d_xi = nullptr;
+  pl.d_wq = nullptr;
   pl.d_roots = nullptr;
   pl.d_coef_off = pl.d_p = nullptr;
   pl.d_cov_off = nullptr;
@@ -482,7 +486,7 @@ const char* stage_name(int s) {
   static const char* names[ST_COUNT] = {"fwd_rows",    "fwd_cols",   "fwd_gather", "fwd_angular",
                                         "radial_fwd",  "covariance", "radial_adj", "adj_angular",
                                         "adj_spread",  "adj_cols",   "adj_rows",   "eig",
-                                        "spca",        "svd"};
+                                        "spca",        "svd",        "estimate"};
   return (s >= 0 && s < ST_COUNT) ? names[s] : "unknown";
 }
 

@@ -147,6 +147,7 @@ enum Stage {
   ST_EIG,
   ST_SPCA,
   ST_SVD,
+  ST_ESTIMATE,
   ST_COUNT
 };
 const char* stage_name(int s);
@@ -229,6 +230,8 @@ struct Plan {
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
   float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
   double* d_roots = nullptr;          // R_{k,q} at coef_off[k] + q - 1 (FP64, p_half)
+  double* d_xi = nullptr;             // Gauss-Legendre nodes xi_j (FP64, n_xi)
+  double* d_wq = nullptr;             // Gauss-Legendre weights w_j (FP64, n_xi)
   int* d_coef_off = nullptr;          // k_max + 2 (fits int32)
   int* d_p = nullptr;                 // k_max + 1
   long long* d_cov_off = nullptr;     // k_max + 2

@@ -135,17 +135,76 @@ class Plan:
         return out
 
     def adjoint(self, coeffs: torch.Tensor, weight_mode: int = 0, out: torch.Tensor | None = None,
-                batch: int | None = None) -> torch.Tensor:
-        """I = T b: synthesis, the transpose of expand (weight_mode 0: +-k folded; 1: plain transpose)."""
+                batch: int | None = None, ring_filter: torch.Tensor | None = None) -> torch.Tensor:
+        """I = T b: synthesis, the transpose of expand (weight_mode 0: +-k folded; 1: plain transpose).
+        ring_filter (float32 [n_xi]) applies a radial Fourier filter H(xi_j) on the way."""
         n = coeffs.shape[0]
         _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
         if out is None:
             out = torch.empty((n, self.L, self.L), dtype=torch.float32, device=coeffs.device)
         _need(out, torch.float32, (n, self.L, self.L), "out")
         ws, wsb = self._ws_for(n, batch)
-        check(lib().fb_adjoint(self._h, coeffs.data_ptr(), n, out.data_ptr(), int(weight_mode), ws.data_ptr(), wsb,
-                               _stream_ptr(coeffs.device)), self._h)
+        if ring_filter is None:
+            check(lib().fb_adjoint(self._h, coeffs.data_ptr(), n, out.data_ptr(), int(weight_mode), ws.data_ptr(),
+                                   wsb, _stream_ptr(coeffs.device)), self._h)
+        else:
+            _need(ring_filter, torch.float32, (self.n_xi,), "ring_filter")
+            check(lib().fb_adjoint_filtered(self._h, coeffs.data_ptr(), n, out.data_ptr(), int(weight_mode),
+                                            ring_filter.data_ptr(), ws.data_ptr(), wsb,
+                                            _stream_ptr(coeffs.device)), self._h)
         return out
+
+    # -- estimation of R and c (Sec. VI-C) ---------------------------------------
+    def pixel_moments(self, images: torch.Tensor, sum: torch.Tensor | None = None,
+                      sumsq: torch.Tensor | None = None):
+        """Accumulate per-pixel sums and sums of squares (FP64 [L*L] each); returns (sum, sumsq)."""
+        n = images.shape[0]
+        _need(images, torch.float32, (n, self.L, self.L), "images")
+        dev = images.device
+        if sum is None:
+            sum = torch.zeros(self.L * self.L, dtype=torch.float64, device=dev)
+        if sumsq is None:
+            sumsq = torch.zeros(self.L * self.L, dtype=torch.float64, device=dev)
+        _need(sum, torch.float64, (self.L * self.L,), "sum")
+        _need(sumsq, torch.float64, (self.L * self.L,), "sumsq")
+        wsb = int(lib().fb_moments_workspace_bytes(self._h))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        check(lib().fb_pixel_moments(self._h, images.data_ptr(), n, sum.data_ptr(), sumsq.data_ptr(), ws.data_ptr(),
+                                     wsb, _stream_ptr(dev)), self._h)
+        return sum, sumsq
+
+    def polar_power(self, images: torch.Tensor, pixel_sum: torch.Tensor | None = None, count: int = 0,
+                    power: torch.Tensor | None = None, batch: int | None = None) -> torch.Tensor:
+        """Accumulate sum_i sum_l |F(I_i - mean)(xi_j, theta_l)|^2 per ring (FP64 [n_xi]); the mean
+        image is pixel_sum / count when pixel_sum is given."""
+        n = images.shape[0]
+        _need(images, torch.float32, (n, self.L, self.L), "images")
+        dev = images.device
+        if power is None:
+            power = torch.zeros(self.n_xi, dtype=torch.float64, device=dev)
+        _need(power, torch.float64, (self.n_xi,), "power")
+        if pixel_sum is not None:
+            _need(pixel_sum, torch.float64, (self.L * self.L,), "pixel_sum")
+        b = max(1, min(int(n), int(batch) if batch else 2048))
+        wsb = int(lib().fb_polar_power_workspace_bytes(self._h, b))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        check(lib().fb_polar_power(self._h, images.data_ptr(), n,
+                                   pixel_sum.data_ptr() if pixel_sum is not None else None, int(count),
+                                   power.data_ptr(), ws.data_ptr(), wsb, _stream_ptr(dev)), self._h)
+        return power
+
+    def estimate_support(self, sum: torch.Tensor, sumsq: torch.Tensor, n: int, power: torch.Tensor,
+                         noise_var: float, frac: float = 0.999):
+        """(R, c) from the accumulated moments and ring power (the cumulative-fraction rule)."""
+        _need(sum, torch.float64, (self.L * self.L,), "sum")
+        _need(sumsq, torch.float64, (self.L * self.L,), "sumsq")
+        _need(power, torch.float64, (self.n_xi,), "power")
+        out = torch.empty(2, dtype=torch.float64, device=sum.device)
+        check(lib().fb_estimate_support(self._h, sum.data_ptr(), sumsq.data_ptr(), int(n), power.data_ptr(),
+                                        float(noise_var), float(frac), out.data_ptr(), _stream_ptr(sum.device)),
+              self._h)
+        R, c = out.cpu().tolist()
+        return int(R), c
 
     def new_covariance(self) -> CovState:
         return CovState(G=torch.zeros(self.cov_size, dtype=torch.float64, device=self.device),

@@ -34,9 +34,27 @@ def noise_sigma(plan, snr: float) -> float:
     return math.sqrt(synth.noise_sigma2(plan.k.astype(np.float64), plan.q.astype(np.float64), plan.L, snr))
 
 
+# Sec. VI-C, CTF-filtered workload: wavelength and defocus (Angstrom), amplitude phase (rad),
+# B-factor (Angstrom^2).  The pixel size is not printed; 1 Angstrom by default.
+CTF_LAMBDA, CTF_DEFOCUS, CTF_PHASE, CTF_B = 0.0197, 2.5e4, 0.1, 100.0
+
+
+def ctf_ring_filter(plan, pixel_size: float = 1.0, lam: float = CTF_LAMBDA, z: float = CTF_DEFOCUS,
+                    a: float = CTF_PHASE, B: float = CTF_B) -> torch.Tensor:
+    """Eq.(CTFenv), min(pi lambda z f^2 + a, 1) exp(-B f^2) at f = xi_j / pixel_size, on the plan's
+    rings: float32 [n_xi] on the device, for fb_adjoint_filtered."""
+    xi = plan.host_tables()[2]
+    f2 = (xi / pixel_size) ** 2
+    h = np.minimum(math.pi * lam * z * f2 + a, 1.0) * np.exp(-B * f2)
+    return torch.tensor(h.astype(np.float32), device=plan.device)
+
+
 def synthetic_images(plan, first: int, m: int, seed: int, snr: float, out: torch.Tensor | None = None,
-                     batch: int = 2048) -> torch.Tensor:
-    """Images first .. first+m-1 of the seeded workload, float32 [m, L, L] on the device."""
+                     batch: int = 2048, ring_filter: torch.Tensor | None = None,
+                     sigma: float | None = None) -> torch.Tensor:
+    """Images first .. first+m-1 of the seeded workload, float32 [m, L, L] on the device.
+    ring_filter: a radial Fourier filter of the clean images (the CTF workload); sigma: the
+    noise standard deviation (default from snr and the unfiltered clean power)."""
     L = plan.L
     if out is None:
         out = torch.empty((m, L, L), dtype=torch.float32, device=plan.device)
@@ -44,7 +62,7 @@ def synthetic_images(plan, first: int, m: int, seed: int, snr: float, out: torch
         return out
     a = synth_normals(seed, synth.STREAM_COEF, first, m, 2 * plan.p_half, 1.0, plan.device).view(m, plan.p_half, 2)
     a.mul_(coefficient_scale(plan))
-    plan.adjoint(a, out=out, batch=min(m, batch))
-    out.add_(synth_normals(seed, synth.STREAM_NOISE, first, m, L * L, noise_sigma(plan, snr), plan.device)
-             .view(m, L, L))
+    plan.adjoint(a, out=out, batch=min(m, batch), ring_filter=ring_filter)
+    s = noise_sigma(plan, snr) if sigma is None else float(sigma)
+    out.add_(synth_normals(seed, synth.STREAM_NOISE, first, m, L * L, s, plan.device).view(m, L, L))
     return out
