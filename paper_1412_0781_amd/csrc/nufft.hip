@@ -1139,6 +1139,15 @@ constexpr int kMaxTransforms = 16;
 constexpr int kAngularUnits = 16;                  // (ring, group) units per streaming angular workgroup
 constexpr int kGridUnits = 16;                     // units per streaming row / column workgroup
 static_assert(kMaxTransforms <= kImgGroup, "an FFT workgroup's image slots map to lanes of one group");
+// Units per workgroup of a streaming column launch: enough that the workgroups fill the
+// device's resident slots (per_cu per compute unit) once, so no partly filled last round is
+// left, and at least `floor` (the prefetch pipeline needs a few units to pay off).  (The
+// row and angular launches keep a fixed count: measured, their several rounds balance
+// better.)
+static int stream_units(const Plan& pl, long long units, int per_cu, int floor) {
+  const long long slots = (long long)pl.num_cus * per_cu;
+  return (int)std::max<long long>(floor, (units + slots - 1) / slots);
+}
 struct FftLaunch {
   int count;
   int form;
@@ -1204,8 +1213,9 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
     pl.prof.begin(ST_FWD_COLS, st);
-    hipLaunchKernelGGL(k_fwd_cols_stream, dim3((unsigned)((uc + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
-                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, kGridUnits, make_fastdiv(L));
+    const int Uc = stream_units(pl, uc, 2, kGridUnits);
+    hipLaunchKernelGGL(k_fwd_cols_stream, dim3((unsigned)((uc + Uc - 1) / Uc)), dim3(1024), 0, st,
+                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L));
     pl.prof.end(st);
   } else {
     FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
@@ -1295,13 +1305,15 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   if (stream_ok) {
     const long long uc = (long long)Nh * ngrp;
     pl.prof.begin(ST_ADJ_COLS, st);
-    hipLaunchKernelGGL(k_adj_cols_stream, dim3((unsigned)((uc + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
-                       bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, kGridUnits, make_fastdiv(L));
+    const int Uc = stream_units(pl, uc, 1, kGridUnits);
+    hipLaunchKernelGGL(k_adj_cols_stream, dim3((unsigned)((uc + Uc - 1) / Uc)), dim3(1024), 0, st,
+                       bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, Uc, make_fastdiv(L));
     pl.prof.end(st);
     const long long ur = (long long)nimg * (((L + 1) / 2 + 15) / 16);
     pl.prof.begin(ST_ADJ_ROWS, st);
-    hipLaunchKernelGGL(k_adj_rows_stream, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
-                       bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, kGridUnits, make_fastdiv(L));
+    const int Ur = stream_units(pl, ur, 1, kGridUnits);
+    hipLaunchKernelGGL(k_adj_rows_stream, dim3((unsigned)((ur + Ur - 1) / Ur)), dim3(1024), 0, st,
+                       bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, Ur, make_fastdiv(L));
     pl.prof.end(st);
     return hipGetLastError();
   }

@@ -414,6 +414,7 @@ static hipError_t upload(T** dptr, const T* src, size_t count) {
 
 int upload_plan(Plan& pl) {
   FB_HIP_TRY(hipGetDevice(&pl.device));
+  FB_HIP_TRY(hipDeviceGetAttribute(&pl.num_cus, hipDeviceAttributeMultiprocessorCount, pl.device));
   FB_HIP_TRY(configure_kernels());
   FB_HIP_TRY(configure_svd_kernels());
   size_t nb = (size_t)pl.p_half * pl.n_xi;

@@ -226,6 +226,7 @@ struct Plan {
   // device
   bool has_device = false;
   int device = -1;
+  int num_cus = 256;                  // compute units of the device (sizes persistent launches)
   hipError_t last_hip = hipSuccess;
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
   float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
