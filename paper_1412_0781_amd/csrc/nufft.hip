@@ -785,8 +785,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   size_t qoff[KQ];
   uint4 er[KE];
   float4 qr[KQ];
-  auto load_meta = [&](int c) {
-    const SpreadChunk ch = chunks[c];
+  auto load_meta_rec = [&](const SpreadChunk ch) {
     nl_n = ch.n1 - ch.n0;
     const int base = sseg[ch.seg];
     ne_n = (sseg[ch.seg + NP] - base) / 4 * 3;  // 16-byte vectors
@@ -843,7 +842,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     // one chunk: its entries go to LDS once; the image groups' values are prefetched two
     // groups ahead in two register sets
     if (ng == 0) return;
-    load_meta(t.c0);
+    load_meta_rec(chunks[t.c0]);
     float4 qb[KQ];
     load_q_into(qr, gb);
     if (ng > 1) load_q_into(qb, gb + t.nsub);
@@ -869,8 +868,12 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     }
     return;
   }
+  // the chunk record the next load_meta_rec takes, read one chunk ahead so that the
+  // entry and node loads of a chunk change do not wait for it
+  SpreadChunk rec_next = chunks[t.c0];
   if (nsteps > 0) {
-    load_meta(t.c0);
+    load_meta_rec(rec_next);
+    if (nch > 1) rec_next = chunks[t.c0 + 1];
     load_q(gb);
   }
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -890,8 +893,12 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     const int e0 = e0_n, e1 = e1_n;
     __syncthreads();
     const bool same_chunk = gi + 1 < ng;
-    if (same_chunk) load_q(g + t.nsub);
-    else if (ci + 1 < nch) load_meta(t.c0 + ci + 1);
+    if (same_chunk) {
+      load_q(g + t.nsub);
+    } else if (ci + 1 < nch) {
+      load_meta_rec(rec_next);
+      if (ci + 2 < nch) rec_next = chunks[t.c0 + ci + 2];
+    }
     sum_entries(e0, e1);
     if (!same_chunk && ci + 1 < nch) load_q(gb);
     float4 ra = make_float4(a0, a1, a2, a3), rb = make_float4(b0, b1, b2, b3);
