@@ -36,6 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # published 157.3 TFLOP/s counts the packed FMA.)
 ALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 ALU_FP32_PUBLISHED_TFLOPS = 157.3
+# LDS read rate of ds_read_b128 measured on the device (a plain read loop): the practical
+# limit of the gather, whose every tap is one 16-byte LDS read per lane
+LDS_MEASURED_TBS = 116.0
 PROFILES = os.path.join(ROOT, "profiles")
 # sources whose change invalidates stored HBM counter readings of the forward kernels
 KERNEL_SOURCES = ["paper_1412_0781_amd/csrc/" + f for f in
@@ -355,6 +358,11 @@ def main():
                     "unit": "TFLOP/s", "frac": round(ach / ALU_FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                     "flops_per_launch": int(flops), "frac_of_published_fp32_peak": round(ach / ALU_FP32_PUBLISHED_TFLOPS, 4),
                     "hbm_algorithmic_GBps": round(hbm_achieved, 1), "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
+        if dom == "fwd_gather":
+            # W x W taps per node and image pair, one 16-byte LDS read each (8 bytes per image)
+            lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
+            roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
+            roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
     else:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
