@@ -1,10 +1,14 @@
 // Algorithm 2, steps 1 and 4 in FP64 on the device: finalise each covariance
 // block C^(k) = G^(k)/n (k = 0: minus m m^T, m the mean of a_{0,q}) and
-// diagonalise it by cyclic two-sided Jacobi rotations.  One workgroup per k;
-// every round applies p_k/2 disjoint rotations in parallel (round-robin
-// pairing), so a sweep of p_k - 1 rounds visits every pair once.
+// diagonalise it, one workgroup per k.  Where the block fits in LDS, by one-sided
+// Jacobi rotations on its columns in LDS; otherwise by cyclic two-sided Jacobi
+// rotations in global memory, every round applying p_k/2 disjoint rotations in
+// parallel (round-robin pairing), so a sweep of p_k - 1 rounds visits every pair once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "jacobi_dev.h"
 #include "kernels.h"
 
 namespace fb {
@@ -23,33 +27,23 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ G, const double* __restrict__ S0,
-                                                     long long count, double* __restrict__ evals,
-                                                     double* __restrict__ evecs, double* __restrict__ C_out,
-                                                     double* __restrict__ mean_out, double* __restrict__ work,
-                                                     const int* __restrict__ p, const int* __restrict__ coef_off,
-                                                     const long long* __restrict__ cov_off) {
+// C^(k) entry i = q p_k + r: G/n, minus m_q m_r for k = 0
+__device__ __forceinline__ double cov_entry(const double* G, const double* S0, long long base, int k, int pk, int i,
+                                            double inv) {
+  const int q = i / pk, r = i - q * pk;
+  double v = G[base + i] * inv;
+  if (k == 0) v -= (S0[q] * inv) * (S0[r] * inv);
+  return v;
+}
+
+// Two-sided cyclic Jacobi on A (global, p_k x p_k, destroyed) with the rotations
+// accumulated into V (global, starts as the identity; ends as the sign-normalised
+// eigenvectors in descending eigenvalue order), eigenvalues to evals + off_k.
+__device__ void eig_two_sided(double* A, double* V, int pk, int off_k, double* evals) {
   __shared__ double red[EIG_THREADS / 64];
   __shared__ double cs[EIG_MAX_P / 2], sn[EIG_MAX_P / 2];
   __shared__ int pa[EIG_MAX_P / 2], pb[EIG_MAX_P / 2];
   __shared__ int stop;
-  const int k = blockIdx.x;
-  const int pk = p[k];
-  const long long base = cov_off[k];
-  double* A = work + base;
-  double* V = evecs + base;
-  const double inv = 1.0 / (double)count;
-  for (int i = threadIdx.x; i < pk * pk; i += blockDim.x) {
-    int q = i / pk, r = i - q * pk;
-    double v = G[base + i] * inv;
-    if (k == 0) v -= (S0[q] * inv) * (S0[r] * inv);
-    A[i] = v;
-    if (C_out) C_out[base + i] = v;
-    V[i] = (q == r) ? 1.0 : 0.0;
-  }
-  if (k == 0 && mean_out)
-    for (int q = threadIdx.x; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
-  __syncthreads();
 
   const int m = pk + (pk & 1);  // even number of positions; position pk is a dummy when pk is odd
   const int npair = m / 2;
@@ -119,7 +113,6 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ 
   // eigenvalues = diagonal, ordered descending (ties by index); columns sign-normalised
   // so that the entry of largest magnitude (lowest index on ties) is positive
   __shared__ int rk[EIG_MAX_P];
-  const int off_k = coef_off[k];
   for (int col = threadIdx.x; col < pk; col += blockDim.x) {
     double di = A[(size_t)col * pk + col];
     int rank = 0;
@@ -149,13 +142,116 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ 
   }
 }
 
+// Two-sided form, A and V in global memory (any p_k up to EIG_MAX_P).
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ G, const double* __restrict__ S0,
+                                                     long long count, double* __restrict__ evals,
+                                                     double* __restrict__ evecs, double* __restrict__ C_out,
+                                                     double* __restrict__ mean_out, double* __restrict__ work,
+                                                     const int* __restrict__ p, const int* __restrict__ coef_off,
+                                                     const long long* __restrict__ cov_off) {
+  const int k = blockIdx.x, pk = p[k];
+  const long long base = cov_off[k];
+  double* A = work + base;
+  double* V = evecs + base;
+  const double inv = 1.0 / (double)count;
+  for (int i = threadIdx.x; i < pk * pk; i += blockDim.x) {
+    const double v = cov_entry(G, S0, base, k, pk, i, inv);
+    A[i] = v;
+    if (C_out) C_out[base + i] = v;
+    V[i] = (i / pk == i % pk) ? 1.0 : 0.0;
+  }
+  if (k == 0 && mean_out)
+    for (int q = threadIdx.x; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
+  __syncthreads();
+  eig_two_sided(A, V, pk, coef_off[k], evals);
+}
+
+// One-sided form with C^(k) in LDS (p_k^2 + p_k doubles must fit): the columns of C are
+// orthogonalised by Jacobi rotations, C V = B, with the rotations accumulated into V (in
+// the workspace, column-major).  (C V)^T (C V) = V^T C^2 V diagonal makes V^T C V diagonal
+// for a positive semidefinite C (the PSD square root of a diagonal matrix is diagonal), so
+// the columns of V are the eigenvectors, each accurate to the orthogonality tolerance times
+// ||C|| however small its eigenvalue; lambda_l = v_l . b_l (the Rayleigh quotient).
+__global__ __launch_bounds__(EIG_THREADS) void k_eig_lds(const double* __restrict__ G, const double* __restrict__ S0,
+                                                         long long count, double* __restrict__ evals,
+                                                         double* __restrict__ evecs, double* __restrict__ C_out,
+                                                         double* __restrict__ mean_out, double* __restrict__ work,
+                                                         const int* __restrict__ p, const int* __restrict__ coef_off,
+                                                         const long long* __restrict__ cov_off) {
+  extern __shared__ double sm[];
+  __shared__ int s_rot;
+  __shared__ int rk[EIG_MAX_P];
+  const int k = blockIdx.x, pk = p[k], tid = threadIdx.x;
+  const long long base = cov_off[k];
+  double* M = sm;                       // C^(k), column-major (symmetric)
+  double* lam = sm + (long long)pk * pk;
+  double* V = work + base;              // accumulated rotations, column-major
+  const double inv = 1.0 / (double)count;
+  for (int i = tid; i < pk * pk; i += blockDim.x) {
+    const double v = cov_entry(G, S0, base, k, pk, i, inv);
+    M[i] = v;
+    V[i] = (i / pk == i % pk) ? 1.0 : 0.0;
+    if (C_out) C_out[base + i] = v;
+  }
+  if (k == 0 && mean_out)
+    for (int q = tid; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
+  __syncthreads();
+  one_sided_jacobi<true>(M, pk, &s_rot, V);
+  for (int l = tid; l < pk; l += blockDim.x) {
+    double a = 0.0;
+    for (int e = 0; e < pk; ++e) a = fma(V[(long long)l * pk + e], M[(long long)l * pk + e], a);
+    lam[l] = a;
+  }
+  __syncthreads();
+  // eigenvalues descending (ties by index); columns sign-normalised so that the entry of
+  // largest magnitude (lowest index on ties) is positive
+  const int off_k = coef_off[k];
+  for (int l = tid; l < pk; l += blockDim.x) {
+    const double d = lam[l];
+    int rank = 0;
+    for (int j = 0; j < pk; ++j) rank += (lam[j] > d) || (lam[j] == d && j < l);
+    rk[l] = rank;
+    evals[off_k + rank] = d;
+  }
+  __syncthreads();
+  for (int l = tid; l < pk; l += blockDim.x) {
+    const double* col = V + (long long)l * pk;
+    int imax = 0;
+    double vmax = -1.0;
+    for (int r = 0; r < pk; ++r)
+      if (fabs(col[r]) > vmax) {
+        vmax = fabs(col[r]);
+        imax = r;
+      }
+    const double sg = col[imax] < 0.0 ? -1.0 : 1.0;
+    double* out = evecs + base;
+    for (int r = 0; r < pk; ++r) out[(long long)r * pk + rk[l]] = sg * col[r];
+  }
+}
+
 size_t eig_workspace_bytes(const Plan& pl) { return (size_t)pl.cov_size * sizeof(double); }
+
+static_assert((size_t)kEigLdsLimit / sizeof(double) < (size_t)(64 * kJacobiMaxPerLane) * (64 * kJacobiMaxPerLane),
+              "the LDS form accumulates rotations for p_k <= 64 kJacobiMaxPerLane only");
+static size_t eig_lds_bytes(const Plan& pl) {
+  const int pm = *std::max_element(pl.p.begin(), pl.p.end());
+  return ((size_t)pm * pm + pm) * sizeof(double);
+}
+
+hipError_t configure_eig_kernels() {
+  return hipFuncSetAttribute((const void*)k_eig_lds, hipFuncAttributeMaxDynamicSharedMemorySize, kEigLdsLimit);
+}
 
 hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
                       double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st) {
   pl.prof.begin(ST_EIG, st);
-  hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, count, evals, evecs,
-                     C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+  const size_t lds = eig_lds_bytes(pl);
+  if (lds <= (size_t)kEigLdsLimit)
+    hipLaunchKernelGGL(k_eig_lds, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), lds, st, G, S0, count, evals,
+                       evecs, C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+  else
+    hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, count, evals, evecs,
+                       C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
   pl.prof.end(st);
   return hipGetLastError();
 }

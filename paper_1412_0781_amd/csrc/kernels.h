@@ -8,6 +8,8 @@ namespace fb {
 
 // Largest p_k the device eigensolver handles (one workgroup per block C^(k)).
 constexpr int EIG_MAX_P = 256;
+constexpr int kEigLdsLimit = 152 * 1024;  // dynamic LDS of the one-sided eigendecomposition (its static arrays need ~5 KB more)
+hipError_t configure_eig_kernels();
 
 // Raise the dynamic-LDS limit of the FFT kernels (called once per plan upload).
 hipError_t configure_kernels();

@@ -417,6 +417,7 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(hipDeviceGetAttribute(&pl.num_cus, hipDeviceAttributeMultiprocessorCount, pl.device));
   FB_HIP_TRY(configure_kernels());
   FB_HIP_TRY(configure_svd_kernels());
+  FB_HIP_TRY(configure_eig_kernels());
   size_t nb = (size_t)pl.p_half * pl.n_xi;
   std::vector<float> r32(nb);
   for (size_t i = 0; i < nb; ++i) r32[i] = (float)pl.radial[i];

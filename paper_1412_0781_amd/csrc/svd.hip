@@ -10,6 +10,7 @@
 // no Gram matrix is formed, so the small singular values keep their relative accuracy.
 #include <hip/hip_runtime.h>
 
+#include "jacobi_dev.h"
 #include "kernels.h"
 
 namespace fb {
@@ -17,8 +18,6 @@ namespace fb {
 constexpr int kSvdChunk = 32;          // rows per Householder update
 constexpr int kSvdHalf = kSvdChunk / 2;  // rows per thread: two threads per column
 constexpr int kSvdThreads = 256;       // two threads per matrix column (p_k <= 128)
-constexpr int kSvdMaxSweeps = 60;
-constexpr double kSvdTol = 1e-15;      // rotate while |x.y| > tol ||x|| ||y||
 
 __device__ __forceinline__ long long tri_row(int j, int p) { return (long long)j * p - (long long)j * (j - 1) / 2; }
 
@@ -227,49 +226,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
   for (int i = tid; i < pk * pk; i += kSvdThreads) M[i] = Mg[i];
   double* sig2 = M + (long long)pk * pk;
   // ---- one-sided Jacobi
-  const int wave = tid >> 6, lane = tid & 63, nw = kSvdThreads / 64;
-  const int P = pk + (pk & 1);
-  for (int sweep = 0; sweep < kSvdMaxSweeps && P > 1; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int rd = 0; rd < P - 1; ++rd) {
-      for (int s = wave; s < P / 2; s += nw) {
-        // circle method: position 0 holds column 0, position t >= 1 column (t - 1 + rd) % (P - 1) + 1
-        const int i = s == 0 ? 0 : (s - 1 + rd) % (P - 1) + 1;
-        const int j = (P - 2 - s + rd) % (P - 1) + 1;
-        if (i >= pk || j >= pk) continue;
-        double* ci = M + (long long)i * pk;
-        double* cj = M + (long long)j * pk;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int e = lane; e < pk; e += 64) {
-          const double x = ci[e], y = cj[e];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
-        }
-        for (int m = 32; m > 0; m >>= 1) {
-          al += __shfl_xor(al, m);
-          be += __shfl_xor(be, m);
-          ga += __shfl_xor(ga, m);
-        }
-        if (ga != 0.0 && fabs(ga) > kSvdTol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int e = lane; e < pk; e += 64) {
-            const double x = ci[e], y = cj[e];
-            ci[e] = cs * x - sn * y;
-            cj[e] = sn * x + cs * y;
-          }
-          if (lane == 0) s_rot = 1;
-        }
-      }
-      __syncthreads();
-    }
-    const int rot = s_rot;
-    __syncthreads();
-    if (!rot) break;
-  }
+  one_sided_jacobi(M, pk, &s_rot);
   // ---- singular values, order, sign, output
   for (int l = tid; l < pk; l += kSvdThreads) {
     double a = 0.0;

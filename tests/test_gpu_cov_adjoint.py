@@ -78,6 +78,32 @@ def test_eig_is_an_eigendecomposition_of_C():
         assert np.allclose(Cb[k] @ V, V * lk[None, :], atol=1e-12 * max(1.0, abs(lk).max()))
 
 
+def test_eig_rank_deficient_blocks():
+    """Fewer images than coefficients per block: the blocks have null directions, which the
+    one-sided form hands to the two-sided form.  Still an orthonormal eigendecomposition,
+    eigenvalues descending and equal to LAPACK's."""
+    plan = Plan(64, 0.5, 32)
+    po = oracle.plan(64, 0.5, 32)
+    x = torch.tensor(noise_images(64, 9, seed=4), device="cuda")
+    a = plan.expand(x)
+    st = plan.covariance(a)
+    evals, evecs, C, _ = plan.eig(st)
+    torch.cuda.synchronize()
+    Cb = plan.blocks(C.cpu().numpy())
+    Vb = plan.blocks(evecs.cpu().numpy())
+    lam = evals.cpu().numpy()
+    lam_ref, _ = oracle.eig_blocks(Cb)
+    for k in range(plan.k_max + 1):
+        o = plan.coef_off[k]
+        lk = lam[o:o + plan.p[k]]
+        assert np.all(np.diff(lk) <= 0)
+        V = Vb[k]
+        assert np.allclose(V.T @ V, np.eye(plan.p[k]), atol=1e-12)
+        scale = max(1.0, abs(lk).max())
+        assert np.allclose(Cb[k] @ V, V * lk[None, :], atol=1e-12 * scale)
+        assert np.max(np.abs(lk - lam_ref[k])) <= 1e-12 * scale
+
+
 def test_covariance_deterministic_and_additive():
     plan = Plan(32, 0.5, 16)
     x = torch.tensor(noise_images(32, 700, seed=9), device="cuda")
