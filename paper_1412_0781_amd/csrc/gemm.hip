@@ -78,30 +78,22 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 constexpr int RBM = 128, RBN = 64, RBK = 32;
 constexpr int RLDH = RBK + 8;
 
-template <int PREC>
-struct RadialSmem;
-template <>
-struct RadialSmem<0> {
+struct RadialSmem {
   float As[RBK][RBM + 4];
   float Bs[RBK][RBN + 4];
-};
-template <>
-struct RadialSmem<1> {
-  unsigned short Ah[RBM][RLDH], Al[RBM][RLDH];
-  unsigned short Bh[RBN][RLDH], Bl[RBN][RLDH];
 };
 union RadialOut {
   float Cs[RBN][RBM + 4];
 };
 
-template <int PREC>
-__global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ radial, const float* __restrict__ Fh,
+// FP32 form
+__global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ radial, const float* __restrict__ Fh,
                                                     float* __restrict__ coeffs, const GemmItem* __restrict__ items,
                                                     const int* __restrict__ coef_off, const int* __restrict__ p,
                                                     int n_xi, int nk, int ncol, long long p_half) {
-  constexpr size_t SZ = sizeof(RadialSmem<PREC>) > sizeof(RadialOut) ? sizeof(RadialSmem<PREC>) : sizeof(RadialOut);
+  constexpr size_t SZ = sizeof(RadialSmem) > sizeof(RadialOut) ? sizeof(RadialSmem) : sizeof(RadialOut);
   __shared__ __attribute__((aligned(16))) unsigned char smem[SZ];
-  RadialSmem<PREC>& S = *reinterpret_cast<RadialSmem<PREC>*>(smem);
+  RadialSmem& S = *reinterpret_cast<RadialSmem*>(smem);
   RadialOut& O = *reinterpret_cast<RadialOut*>(smem);
   const GemmItem it = items[blockIdx.x];  // k varies fastest: neighbouring workgroups read neighbouring lines of Fh
   const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
@@ -145,34 +137,13 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
     for (int u = 0; u < 4; ++u) {
       int idx = tid + u * 256, m = idx >> 3, kq = (idx & 7) * 4;
       float v[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
-      if constexpr (PREC == 0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) S.As[kq + e][m] = v[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          unsigned short h, l;
-          split_bf16(v[e], h, l);
-          S.Ah[m][kq + e] = h;
-          S.Al[m][kq + e] = l;
-        }
-      }
+      for (int e = 0; e < 4; ++e) S.As[kq + e][m] = v[e];
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
-      float v[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
-      if constexpr (PREC == 0) {
-        *(float4*)&S.Bs[kk][nq] = rb[u];
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          unsigned short h, l;
-          split_bf16(v[e], h, l);
-          S.Bh[nq + e][kk] = h;
-          S.Bl[nq + e][kk] = l;
-        }
-      }
+      *(float4*)&S.Bs[kk][nq] = rb[u];
     }
   };
   f32x16 acc0 = {}, acc1 = {};
@@ -182,30 +153,13 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     if (c + 1 < nch) gload((c + 1) * RBK);
-    if constexpr (PREC == 0) {
 #pragma unroll
-      for (int kk = 0; kk < RBK; kk += 2) {
-        float a = S.As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
-        float b0 = S.Bs[kk + (lane >> 5)][lane & 31];
-        float b1 = S.Bs[kk + (lane >> 5)][32 + (lane & 31)];
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
-      }
-    } else {
-      const int ra_ = wm * 32 + (lane & 31), rb0 = lane & 31, rb1 = 32 + (lane & 31);
-#pragma unroll
-      for (int kb = 0; kb < RBK; kb += 16) {
-        const int cc = kb + 8 * (lane >> 5);
-        bf16x8 ah = ld8(&S.Ah[ra_][cc]), al = ld8(&S.Al[ra_][cc]);
-        bf16x8 bh0 = ld8(&S.Bh[rb0][cc]), bl0 = ld8(&S.Bl[rb0][cc]);
-        bf16x8 bh1 = ld8(&S.Bh[rb1][cc]), bl1 = ld8(&S.Bl[rb1][cc]);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, acc0, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, acc0, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, acc1, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, acc1, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, acc1, 0, 0, 0);
-      }
+    for (int kk = 0; kk < RBK; kk += 2) {
+      float a = S.As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
+      float b0 = S.Bs[kk + (lane >> 5)][lane & 31];
+      float b1 = S.Bs[kk + (lane >> 5)][32 + (lane & 31)];
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
     }
     __syncthreads();
     if (c + 1 < nch) {
@@ -229,6 +183,136 @@ __global__ __launch_bounds__(256) void k_radial_fwd(const float* __restrict__ ra
     float im = (k == 0) ? 0.f : O.Cs[2 * il + 1][q];
     *(float2*)&coeffs[(size_t)(n0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
   }
+}
+
+// BF16x3 form of the radial quadrature.  The table operand is split once, at plan time
+// (tab: hi parts, then lo parts, rows padded to kRadialK with zeros), and each lane loads
+// its 8-value MFMA fragments straight from global memory: a wave's 32 rows are its own.
+// Only the F-hat operand, which the four waves share, is split here and staged in LDS,
+// two consecutive j of one column packed into each 32-bit store, its global loads issued
+// two chunks ahead.  Waves whose rows all lie
+// beyond p_k skip their loads and products.  Same grid and output as k_radial_fwd_f32.
+__global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __restrict__ tab,
+                                                       const float* __restrict__ Fh, float* __restrict__ coeffs,
+                                                       const GemmItem* __restrict__ items,
+                                                       const int* __restrict__ coef_off, const int* __restrict__ p,
+                                                       int n_xi, int nxp, int nk, int ncol, long long p_half) {
+  union Smem {
+    struct {
+      unsigned int Bh[RBN][RLDH / 2], Bl[RBN][RLDH / 2];  // [column][j / 2], two BF16 per word
+    } b;
+    float Cs[RBN / 2][RBM + 4];  // half of the output tile, [column][row]
+  };
+  __shared__ __attribute__((aligned(16))) Smem S;
+  const GemmItem it = items[blockIdx.x];
+  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
+  const int n0 = blockIdx.y * RBN;
+  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
+  const bool live = m0 + wm * 32 < pk;  // uniform over the wave
+  const int row = m0 + wm * 32 + (lane & 31);
+  const bool rlive = row < pk;
+  const size_t plane = (size_t)p_half * nxp;
+  const unsigned short* th = tab + (size_t)(off + (rlive ? row : 0)) * nxp + 8 * (lane >> 5);
+  // F-hat staging: thread -> rows j = 2 jp, 2 jp + 1 of the chunk, columns nq .. nq + 3
+  const int jp = tid & 15, nq = 4 * (tid >> 4), col = n0 + nq;
+  const float* fk = Fh + (size_t)k * (2 * kImgGroup) +
+                    (size_t)(col / (2 * kImgGroup)) * n_xi * nk * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
+  uint4 a_nx[4], a_cu[4];  // A fragments: hi (j0, j0 + 16), lo (j0, j0 + 16)
+  float4 b1[2], b2[2];      // F-hat of the next chunk and of the one after
+#pragma unroll
+  for (int u = 0; u < 4; ++u) a_nx[u] = a_cu[u] = make_uint4(0u, 0u, 0u, 0u);
+  auto load_a = [&](int k0) {
+    if (live && rlive) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const unsigned short* src = th + (size_t)h * plane + k0;
+        a_nx[2 * h] = *(const uint4*)src;
+        a_nx[2 * h + 1] = *(const uint4*)(src + 16);
+      }
+    }
+  };
+  auto load_b = [&](int k0, float4* dst) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int kc = k0 + 2 * jp + u;
+      const float* src = fk + (size_t)kc * nk * (2 * kImgGroup);
+      if (kc < n_xi && col + 3 < ncol) {
+        dst[u] = *(const float4*)src;
+      } else {
+        float t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (kc < n_xi && col + e < ncol) ? src[e] : 0.f;
+        dst[u] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+    }
+  };
+  auto lstore = [&]() {
+    const float v0[4] = {b1[0].x, b1[0].y, b1[0].z, b1[0].w};
+    const float v1[4] = {b1[1].x, b1[1].y, b1[1].z, b1[1].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      unsigned short h0, l0, h1, l1;
+      split_bf16(v0[e], h0, l0);
+      split_bf16(v1[e], h1, l1);
+      S.b.Bh[nq + e][jp] = (unsigned)h0 | ((unsigned)h1 << 16);
+      S.b.Bl[nq + e][jp] = (unsigned)l0 | ((unsigned)l1 << 16);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a_cu[u] = a_nx[u];
+  };
+  f32x16 acc0 = {}, acc1 = {};
+  const int nch = nxp / RBK;
+  load_b(0, b1);
+  load_a(0);
+  lstore();
+  if (1 < nch) load_b(RBK, b1);
+  __syncthreads();
+  const unsigned short* Bh = (const unsigned short*)&S.b.Bh[0][0];
+  const unsigned short* Bl = (const unsigned short*)&S.b.Bl[0][0];
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) load_a((c + 1) * RBK);
+    if (c + 2 < nch) load_b((c + 2) * RBK, b2);
+    if (live) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        const int cc = 16 * kb + 8 * (lane >> 5);
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, a_cu[kb]), al = __builtin_bit_cast(bf16x8, a_cu[2 + kb]);
+        const int r0 = (lane & 31) * RLDH + cc, r1 = (32 + (lane & 31)) * RLDH + cc;
+        const bf16x8 bh0 = ld8(Bh + r0), bl0 = ld8(Bl + r0), bh1 = ld8(Bh + r1), bl1 = ld8(Bl + r1);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh0, acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl0, acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh1, acc1, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl1, acc1, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, acc1, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nch) {
+      lstore();
+      b1[0] = b2[0];
+      b1[1] = b2[1];
+      __syncthreads();
+    }
+  }
+  // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
+  const int nrow = min(RBM, pk - m0);
+  auto emit = [&](const f32x16& acc, int half) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
+    __syncthreads();
+    const int c0 = n0 + 32 * half;
+    const int nimg_t = max(0, min(32, ncol - c0)) / 2;
+    for (int i = tid; i < nimg_t * nrow; i += 256) {
+      const int il = i / nrow, q = i - il * nrow;
+      const float re = S.Cs[2 * il][q];
+      const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
+      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
+    }
+  };
+  emit(acc0, 0);
+  __syncthreads();
+  emit(acc1, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,10 +544,10 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
   const int nk = pl.k_max + 1;
   pl.prof.begin(ST_RADIAL_FWD, st);
   if (precision == FB_BF16X3)
-    hipLaunchKernelGGL(k_radial_fwd<1>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
-                       pl.d_coef_off, pl.d_p, pl.n_xi, nk, ncol, (long long)pl.p_half);
+    hipLaunchKernelGGL(k_radial_fwd_b3, g, dim3(256), 0, st, pl.d_radial_bf, (const float*)Fh, coeffs,
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half);
   else
-    hipLaunchKernelGGL(k_radial_fwd<0>, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
+    hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
                        pl.d_coef_off, pl.d_p, pl.n_xi, nk, ncol, (long long)pl.p_half);
   pl.prof.end(st);
   return hipGetLastError();

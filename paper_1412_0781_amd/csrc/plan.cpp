@@ -422,6 +422,33 @@ int upload_plan(Plan& pl) {
   std::vector<float> r32(nb);
   for (size_t i = 0; i < nb; ++i) r32[i] = (float)pl.radial[i];
   FB_HIP_TRY(upload(&pl.d_radial, r32.data(), nb));
+  // the BF16x3 operand split of the FP32 table, x = hi + lo with hi = bf16(x) and lo =
+  // bf16(x - hi), both rounded to nearest even (x - hi is exact in FP32)
+  pl.n_xi_pad = (pl.n_xi + kRadialK - 1) / kRadialK * kRadialK;
+  {
+    const size_t nbp = (size_t)pl.p_half * pl.n_xi_pad;
+    auto bf16_rne = [](float f) {
+      uint32_t u;
+      std::memcpy(&u, &f, sizeof u);
+      u += 0x7fffu + ((u >> 16) & 1u);
+      return (unsigned short)(u >> 16);
+    };
+    auto bf16_val = [](unsigned short h) {
+      const uint32_t u = (uint32_t)h << 16;
+      float f;
+      std::memcpy(&f, &u, sizeof f);
+      return f;
+    };
+    std::vector<unsigned short> bf(2 * nbp, 0);
+    for (long long r = 0; r < pl.p_half; ++r)
+      for (int j = 0; j < pl.n_xi; ++j) {
+        const float x = r32[(size_t)r * pl.n_xi + j];
+        const unsigned short h = bf16_rne(x);
+        bf[(size_t)r * pl.n_xi_pad + j] = h;
+        bf[nbp + (size_t)r * pl.n_xi_pad + j] = bf16_rne(x - bf16_val(h));
+      }
+    FB_HIP_TRY(upload(&pl.d_radial_bf, bf.data(), bf.size()));
+  }
   std::vector<float> xw(pl.n_xi);
   for (int j = 0; j < pl.n_xi; ++j) xw[j] = (float)(pl.xi[j] * pl.wq[j]);
   FB_HIP_TRY(upload(&pl.d_xw, xw.data(), xw.size()));
@@ -456,13 +483,14 @@ int upload_plan(Plan& pl) {
 
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
-  void* ptrs[] = {pl.d_radial,    pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
+  void* ptrs[] = {pl.d_radial,    pl.d_radial_bf, pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
+  pl.d_radial_bf = nullptr;
   pl.d_xw = nullptr;
   pl.d_xi = nullptr;
   pl.d_wq = nullptr;

@@ -173,6 +173,7 @@ struct Profiler {
 };
 
 constexpr int kRadialRows = 128;  // row tile of the radial quadrature GEMM
+constexpr int kRadialK = 32;      // K chunk of the radial quadrature GEMM (rows of the BF16 table padded to it)
 
 struct GemmItem {  // one (k, tile) work item of a grouped GEMM
   int k;
@@ -229,6 +230,8 @@ struct Plan {
   int num_cus = 256;                  // compute units of the device (sizes persistent launches)
   hipError_t last_hip = hipSuccess;
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
+  unsigned short* d_radial_bf = nullptr;  // its BF16 hi parts, then its lo parts: 2 x p_half x n_xi_pad, zero-padded
+  int n_xi_pad = 0;                   // n_xi rounded up to kRadialK
   float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
   double* d_roots = nullptr;          // R_{k,q} at coef_off[k] + q - 1 (FP64, p_half)
   double* d_xi = nullptr;             // Gauss-Legendre nodes xi_j (FP64, n_xi)

@@ -91,3 +91,29 @@ def test_full_n_sampled(L, R, precision):
         lam_ref = np.sort(np.linalg.eigvalsh(Ck))[::-1]
         lam = ev[o:o + pk]
         assert np.abs(lam - lam_ref).max() <= 1e-9 * abs(lam_ref[0])
+
+
+def test_l360_eig_two_sided_form():
+    """At L = 360 the largest blocks (p_0 = 179) exceed LDS, so the eigendecomposition takes
+    the two-sided form in global memory: eigenvalues descending and equal to LAPACK's on the
+    finalised blocks, eigenvectors orthonormal with residuals at FP64 rounding of ||C||."""
+    L, c, R, n = 360, 0.5, 180.0, 1024
+    print(f"[fullsize] eig L={L} n={n}", flush=True)
+    plan = Plan(L, c, R)
+    x = synth_normals(3, 2, 0, n, L * L, 1.0).view(n, L, L)
+    st = plan.covariance(plan.expand(x, precision="fp32"))
+    del x
+    evals, evecs, C, _ = plan.eig(st)
+    torch.cuda.synchronize()
+    Cn, Vn, ev = C.cpu().numpy(), evecs.cpu().numpy(), evals.cpu().numpy()
+    for k in [0, 1, plan.k_max // 2, plan.k_max]:
+        o, pk = int(plan.coef_off[k]), int(plan.p[k])
+        Ck = Cn[plan.cov_off[k]:plan.cov_off[k + 1]].reshape(pk, pk)
+        V = Vn[plan.cov_off[k]:plan.cov_off[k + 1]].reshape(pk, pk)
+        lam = ev[o:o + pk]
+        scale = abs(lam).max()
+        print(f"  k={k} p_k={pk}", flush=True)
+        assert np.all(np.diff(lam) <= 0)
+        assert np.allclose(V.T @ V, np.eye(pk), atol=1e-12)
+        assert np.abs(Ck @ V - V * lam[None, :]).max() <= 1e-12 * scale
+        assert np.abs(lam - np.sort(np.linalg.eigvalsh(Ck))[::-1]).max() <= 1e-12 * scale
