@@ -175,7 +175,7 @@ constexpr int kGridStreamPF = 8;    // input values per thread held for the next
 __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
                                                              const float* __restrict__ deconv, FftDesc fd,
                                                              const float2* __restrict__ tw, int L, int M2, int hw,
-                                                             int nimg, int U, FastDiv dL4) {
+                                                             int nimg, int U, FastDiv dL4, FastDiv dZ) {
   constexpr int RP = 16;
   __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
       }
     }
     for (int e = tid; e < RP * (N - L); e += nthr) {
-      const int t = e / (N - L), z = e - t * (N - L);
+      const int t = dZ.div(e), z = e - t * (N - L);  // dZ: division by N - L
       int pos = x0 + L + z;  // columns past the image, wrapped
       pos -= (pos >= N) ? N : 0;
       pos += (pos < 0) ? N : 0;
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
 // columns: unit = (stored row m2, image group); output G [M2][group][N][16]
 __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
                                                              FftDesc fd, const float2* __restrict__ tw, int L,
-                                                             int M2, int nimg, int ngrp, int U, FastDiv dL) {
+                                                             int M2, int nimg, int ngrp, int U, FastDiv dL,
+                                                             FastDiv dZ) {
   constexpr int G = kImgGroup;
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __res
       }
     }
     for (int e = tid; e < G * (N - L); e += nthr) {
-      const int t = e / (N - L), z = e - t * (N - L);
+      const int t = dZ.div(e), z = e - t * (N - L);  // dZ: division by N - L
       int pos = x0 + L + z;
       pos -= (pos >= N) ? N : 0;
       pos += (pos < 0) ? N : 0;
@@ -1216,13 +1217,14 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     pl.prof.begin(ST_FWD_ROWS, st);
     hipLaunchKernelGGL(k_fwd_rows_stream, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
                        images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, kGridUnits,
-                       make_fastdiv(L / 4));
+                       make_fastdiv(L / 4), make_fastdiv(N - L));
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
     pl.prof.begin(ST_FWD_COLS, st);
     const int Uc = stream_units(pl, uc, 2, kGridUnits);
     hipLaunchKernelGGL(k_fwd_cols_stream, dim3((unsigned)((uc + Uc - 1) / Uc)), dim3(1024), 0, st,
-                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L));
+                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L),
+                       make_fastdiv(N - L));
     pl.prof.end(st);
   } else {
     FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
