@@ -309,6 +309,74 @@ __device__ inline void fft_lds_inplace_tw(float2* buf, int count, int stride, co
   }
 }
 
+// The same in-place padded FFT for a power-of-two length N known at compile time, with
+// COUNT transforms at stride STRIDE and NT threads: stage radices follow the plan's rule
+// (radix 8 while the remaining length is a multiple of 8 other than 16, then 4), and
+// every index and twiddle position is a shift or mask, most LDS offsets immediates.
+// Same operations in the same order as the run-time form (the first stage's unit
+// twiddles are skipped: multiplying by exactly 1 changes nothing).
+constexpr int pow2_stage_radix(int rem) { return (rem % 8 == 0 && rem != 16) ? 8 : 4; }
+
+template <int N, int R, int NS, int COUNT, int STRIDE, int NT>
+__device__ __forceinline__ void fft_stage_pow2(float2* buf, const float2* __restrict__ tw, unsigned tid) {
+  constexpr unsigned NB = N / R, TWS = N / (NS * R), BM = kFftVmax / R, TOTAL = COUNT * NB;
+  static_assert((N & (N - 1)) == 0 && TOTAL <= BM * NT, "one pass of the threads covers every butterfly");
+  float2 v[BM][R];
+#pragma unroll
+  for (unsigned b = 0; b < BM; ++b) {
+    const unsigned idx = tid + b * NT;
+    if (idx < TOTAL) {
+      const unsigned t = idx / NB, j = idx % NB;
+      const float2* src = buf + t * STRIDE;
+#pragma unroll
+      for (unsigned r = 0; r < R; ++r) v[b][r] = src[fpad(j + r * NB)];
+    }
+  }
+  stage_barrier<true>();
+#pragma unroll
+  for (unsigned b = 0; b < BM; ++b) {
+    const unsigned idx = tid + b * NT;
+    if (idx < TOTAL) {
+      const unsigned t = idx / NB, j = idx % NB, k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (unsigned r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[k * r * TWS]);
+      }
+      Dft<R>::run(v[b], tw, N, R);
+      float2* dst = buf + t * STRIDE;
+      const unsigned base = (j - k) * R + k;
+#pragma unroll
+      for (unsigned r = 0; r < R; ++r) dst[fpad(base + r * NS)] = v[b][r];
+    }
+  }
+  stage_barrier<true>();
+}
+
+template <int N, int COUNT, int STRIDE, int NT, int NS = 1>
+__device__ __forceinline__ void fft_pow2_inplace(float2* buf, const float2* __restrict__ tw, unsigned tid) {
+  if constexpr (NS < N) {
+    constexpr int R = pow2_stage_radix(N / NS);
+    fft_stage_pow2<N, R, NS, COUNT, STRIDE, NT>(buf, tw, tid);
+    fft_pow2_inplace<N, COUNT, STRIDE, NT, NS * R>(buf, tw, tid);
+  }
+}
+
+// The FFT of the streaming kernels (1024 threads, padded in-place layout, LDS twiddles):
+// the compile-time form for NC > 0 (NC = d.n), the run-time form for NC = 0.  In the
+// compile-time form the thread index passes through an empty asm statement, so that the
+// stages' addresses are formed here rather than held in registers across the caller's
+// loop (they depend on nothing else that changes).
+template <int NC, int COUNT>
+__device__ __forceinline__ void fft_stream(float2* buf, int stride, const FftDesc& d, const float2* __restrict__ tw) {
+  if constexpr (NC > 0) {
+    unsigned tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    fft_pow2_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+  } else {
+    fft_lds_inplace_tw<true, true>(buf, COUNT, stride, d, tw);
+  }
+}
+
 __device__ inline void fft_lds_inplace(float2* buf, int count, int stride, const FftDesc& d,
                                        const float2* __restrict__ tw_all) {
   fft_lds_inplace_tw<false>(buf, count, stride, d, tw_all + d.tw_off);

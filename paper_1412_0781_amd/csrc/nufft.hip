@@ -172,6 +172,7 @@ constexpr int kGridStreamN = 512;   // largest grid side of the streaming forms
 constexpr int kGridStreamPF = 8;    // input values per thread held for the next unit
 
 // rows: unit = (image, 16 row pairs); rows a = 2 p0 .. 2 p0 + 31 of the image
+template <int NC>
 __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
                                                              const float* __restrict__ deconv, FftDesc fd,
                                                              const float2* __restrict__ tw, int L, int M2, int hw,
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
   __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
   __shared__ float s_dec[kGridStreamN / 2];
-  const int N = fd.n, S = fpad(N - 1) + 2;
+  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;  // row blocks per image
   const int total = nimg * nrb;
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_lds_inplace_tw<true, true>(s_buf, RP, S, fd, s_tw);
+    fft_stream<NC, RP>(s_buf, S, fd, s_tw);
     // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i); lanes over the rows
     float2* out = g1 + (size_t)im * M2 * L;
     const int r = tid & 31, a = a0 + r;
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
 }
 
 // columns: unit = (stored row m2, image group); output G [M2][group][N][16]
+template <int NC>
 __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
                                                              FftDesc fd, const float2* __restrict__ tw, int L,
                                                              int M2, int nimg, int ngrp, int U, FastDiv dL,
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __res
   constexpr int G = kImgGroup;
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
-  const int N = fd.n, S = fpad(N - 1) + 2;
+  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = M2 * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __res
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    fft_stream<NC, G>(s_buf, S, fd, s_tw);
     const int c = tid & (G - 1);
     float2* dst = g + ((size_t)m2 * ngrp + grp) * N * G + c;
     for (int m1 = tid / G; m1 < N; m1 += nthr / G) dst[(size_t)m1 * G] = s_buf[c * S + fpad(m1)];
@@ -501,6 +503,7 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int kAngStreamH = 512;  // largest angular half length of the streaming form
 
+template <int NC>
 __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __restrict__ P, float2* __restrict__ Fh,
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const float2* __restrict__ angtw, int n_xi, int K,
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];  // packed transforms, padded
   __shared__ float2 s_tw[kAngStreamH];
   __shared__ float2 s_angtw[kAngStreamH];
-  const int H = fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
+  const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
-    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    fft_stream<NC, G>(s_buf, S, fd, s_tw);
     const int j = u / ngrp, grp = u - j * ngrp;
     const int gg = tid & (G - 1);
     float2* dst = Fh + (((size_t)grp * n_xi + j) * (K + 1)) * G + gg;
@@ -635,6 +638,7 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
 // for the pairs (k', H - k'), and the in-place FFT meets at LDS-only barriers so that the
 // loads stay in flight.
 // ---------------------------------------------------------------------------
+template <int NC>
 __global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __restrict__ D, float2* __restrict__ Q,
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const float2* __restrict__ angtw, int n_xi, int K,
@@ -644,7 +648,7 @@ __global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];
   __shared__ float2 s_tw[kAngStreamH];
   __shared__ float2 s_angtw[kAngStreamH];
-  const int H = fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
+  const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __
       if (kp != 0 && kp != Hh) row[fpad(km)] = zin(km, b, a);
     }
     stage_barrier<true>();
-    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    fft_stream<NC, G>(s_buf, S, fd, s_tw);
     // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1};  Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H})
     float2* dst = Q + (size_t)u * H * G;
     for (int e = tid; e < H * G; e += nthr) {
@@ -929,6 +933,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
 // conjugate) with LDS twiddles and LDS-only barriers; the columns x1 of the pixel range go
 // to Zc [n][N/2+1][L].
 // ---------------------------------------------------------------------------
+template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __restrict__ Y, float2* __restrict__ Zc,
                                                             FftDesc fd, const float2* __restrict__ tw, int L,
                                                             int nimg, int ngrp, int U, FastDiv dL) {
@@ -936,7 +941,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
   constexpr int PF = kGridStreamN * G / 2 / 1024;  // pairs of values per thread
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
-  const int N = fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = Nh * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -970,7 +975,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_lds_inplace_tw<true, true>(s_buf, G, S, fd, s_tw);
+    fft_stream<NC, G>(s_buf, S, fd, s_tw);
     for (int e = tid; e < G * L; e += nthr) {
       const int c = dL.div(e), a = e - c * L, i = grp * G + c;
       if (i < nimg) {
@@ -990,6 +995,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
 // sequence z(m) = conj(h_a(m) + i h_b(m)) with the Hermitian completions
 // h(m) = r(m) (m <= N/2), conj r(N - m) (above), placed at m and N - m directly.
 // ---------------------------------------------------------------------------
+template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __restrict__ Zc, float* __restrict__ img,
                                                             const float* __restrict__ deconv, FftDesc fd,
                                                             const float2* __restrict__ tw, int L, int nimg, int U,
@@ -999,7 +1005,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
   __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
   __shared__ float2 s_tw[kGridStreamN];
   __shared__ float s_dec[kGridStreamN / 2];
-  const int N = fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;
   const int total = nimg * nrb;
@@ -1039,7 +1045,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_lds_inplace_tw<true, true>(s_buf, RP, S, fd, s_tw);
+    fft_stream<NC, RP>(s_buf, S, fd, s_tw);
     float* dst = img + (size_t)im * L * L;
     for (int e = tid; e < 2 * RP * L; e += nthr) {
       const int r = dL.div(e), b = e - r * L, a = a0 + r;
@@ -1203,6 +1209,19 @@ hipError_t configure_kernels() {
   return hipSuccess;
 }
 
+// Launch a streaming kernel compiled for its transform length n (a power of two from 64
+// to 512), or its run-time-length form for any other n.
+#define FB_LAUNCH_POW2(K, n, grid, st, ...)                                                 \
+  do {                                                                                      \
+    switch (n) {                                                                            \
+      case 512: hipLaunchKernelGGL(K<512>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
+      case 256: hipLaunchKernelGGL(K<256>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
+      case 128: hipLaunchKernelGGL(K<128>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
+      case 64: hipLaunchKernelGGL(K<64>, grid, dim3(1024), 0, st, __VA_ARGS__); break;      \
+      default: hipLaunchKernelGGL(K<0>, grid, dim3(1024), 0, st, __VA_ARGS__); break;       \
+    }                                                                                       \
+  } while (0)
+
 hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, float2* bufA, float2* bufB,
                                 hipStream_t st) {
   const int N = pl.N, L = pl.L;
@@ -1215,14 +1234,14 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     const int nrb = ((L + 1) / 2 + 15) / 16;
     const long long ur = (long long)nimg * nrb;
     pl.prof.begin(ST_FWD_ROWS, st);
-    hipLaunchKernelGGL(k_fwd_rows_stream, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), dim3(1024), 0, st,
+    FB_LAUNCH_POW2(k_fwd_rows_stream, N, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), st,
                        images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, kGridUnits,
                        make_fastdiv(L / 4), make_fastdiv(N - L));
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
     pl.prof.begin(ST_FWD_COLS, st);
     const int Uc = stream_units(pl, uc, 2, kGridUnits);
-    hipLaunchKernelGGL(k_fwd_cols_stream, dim3((unsigned)((uc + Uc - 1) / Uc)), dim3(1024), 0, st,
+    FB_LAUNCH_POW2(k_fwd_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
                        bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L),
                        make_fastdiv(N - L));
     pl.prof.end(st);
@@ -1260,7 +1279,7 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
     const int units = pl.n_xi * ngrp;
     const int U = kAngularUnits;
     pl.prof.begin(ST_FWD_ANGULAR, st);
-    hipLaunchKernelGGL(k_fwd_angular_stream, dim3((unsigned)((units + U - 1) / U)), dim3(1024), 0, st, P,
+    FB_LAUNCH_POW2(k_fwd_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, P,
                        Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, ngrp, U, scale);
     pl.prof.end(st);
     return hipGetLastError();
@@ -1283,7 +1302,7 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
     const int U = kAngularUnits;
     const float sc = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
     pl.prof.begin(ST_ADJ_ANGULAR, st);
-    hipLaunchKernelGGL(k_adj_angular_stream, dim3((unsigned)((units + U - 1) / U)), dim3(1024), 0, st, D, Q,
+    FB_LAUNCH_POW2(k_adj_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, D, Q,
                        pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, ngrp, U, sc);
     pl.prof.end(st);
     return hipGetLastError();
@@ -1315,13 +1334,13 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
     const long long uc = (long long)Nh * ngrp;
     pl.prof.begin(ST_ADJ_COLS, st);
     const int Uc = stream_units(pl, uc, 1, kGridUnits);
-    hipLaunchKernelGGL(k_adj_cols_stream, dim3((unsigned)((uc + Uc - 1) / Uc)), dim3(1024), 0, st,
+    FB_LAUNCH_POW2(k_adj_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
                        bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, Uc, make_fastdiv(L));
     pl.prof.end(st);
     const long long ur = (long long)nimg * (((L + 1) / 2 + 15) / 16);
     pl.prof.begin(ST_ADJ_ROWS, st);
     const int Ur = stream_units(pl, ur, 1, kGridUnits);
-    hipLaunchKernelGGL(k_adj_rows_stream, dim3((unsigned)((ur + Ur - 1) / Ur)), dim3(1024), 0, st,
+    FB_LAUNCH_POW2(k_adj_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
                        bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, Ur, make_fastdiv(L));
     pl.prof.end(st);
     return hipGetLastError();
