@@ -217,17 +217,19 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   const int jp = tid & 15, nq = 4 * (tid >> 4), col = n0 + nq;
   const float* fk = Fh + (size_t)k * (2 * kImgGroup) +
                     (size_t)(col / (2 * kImgGroup)) * n_xi * nk * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
-  uint4 a_nx[4], a_cu[4];  // A fragments: hi (j0, j0 + 16), lo (j0, j0 + 16)
-  float4 b1[2], b2[2];      // F-hat of the next chunk and of the one after
+  uint4 a_cu[4];        // A fragments: hi (j0, j0 + 16), lo (j0, j0 + 16)
+  float4 b1[2], b2[2];  // F-hat of the next chunk and of the one after
 #pragma unroll
-  for (int u = 0; u < 4; ++u) a_nx[u] = a_cu[u] = make_uint4(0u, 0u, 0u, 0u);
+  for (int u = 0; u < 4; ++u) a_cu[u] = make_uint4(0u, 0u, 0u, 0u);
+  // the next chunk's fragments are loaded into the same registers once this chunk's
+  // products have been issued; their latency overlaps the barrier and the F-hat staging
   auto load_a = [&](int k0) {
     if (live && rlive) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const unsigned short* src = th + (size_t)h * plane + k0;
-        a_nx[2 * h] = *(const uint4*)src;
-        a_nx[2 * h + 1] = *(const uint4*)(src + 16);
+        a_cu[2 * h] = *(const uint4*)src;
+        a_cu[2 * h + 1] = *(const uint4*)(src + 16);
       }
     }
   };
@@ -257,8 +259,6 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
       S.b.Bh[nq + e][jp] = (unsigned)h0 | ((unsigned)h1 << 16);
       S.b.Bl[nq + e][jp] = (unsigned)l0 | ((unsigned)l1 << 16);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a_cu[u] = a_nx[u];
   };
   f32x16 acc0 = {}, acc1 = {};
   const int nch = nxp / RBK;
@@ -270,7 +270,6 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   const unsigned short* Bh = (const unsigned short*)&S.b.Bh[0][0];
   const unsigned short* Bl = (const unsigned short*)&S.b.Bl[0][0];
   for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) load_a((c + 1) * RBK);
     if (c + 2 < nch) load_b((c + 2) * RBK, b2);
     if (live) {
 #pragma unroll
@@ -287,6 +286,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh1, acc1, 0, 0, 0);
       }
     }
+    if (c + 1 < nch) load_a((c + 1) * RBK);
     __syncthreads();
     if (c + 1 < nch) {
       lstore();
