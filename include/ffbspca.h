@@ -168,8 +168,13 @@ size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n);
  *         sign-normalised so that its entry of largest magnitude is positive;
  *   C_out [cov_size] (nullable): the finalised C^(k) blocks;
  *   mean_out [p_0] (nullable): m.
- * ws must hold fb_eig_workspace_bytes(plan) bytes.  Cyclic Jacobi sweeps until
- * every off-diagonal entry is below 1e-15 of the block norm.  Asynchronous.
+ * ws must hold fb_eig_workspace_bytes(plan) bytes.  When the plan's largest block fits
+ * in LDS (max p_k <= 138, p_k^2 + p_k doubles): one-sided Jacobi on the columns of each
+ * C^(k) with the rotations accumulated into V, until every column pair is orthogonal to
+ * 1e-15 of the product of their norms; eigenvalues are the Rayleigh quotients u_l^T C u_l.
+ * Otherwise: cyclic two-sided Jacobi until the off-diagonal norm is below 1e-15 of the
+ * block norm.
+ * Asynchronous.
  * Errors: FB_ERR_INVALID_ARG if count <= 0 or a required pointer is NULL. */
 int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, double* evals, double* evecs,
            double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream);
