@@ -43,6 +43,7 @@ def _run(L, c, R, n, precision, seed=0, snr=0.1, batch=None):
     (48, 0.5, 24, 3),      # grid 96 = 2^5 3
     (64, 0.3, 32, 4),      # c < 1/2, angular length 77 = 7 * 11 (generic radices)
     (24, 0.375, 12, 9),
+    (16, 0.5, 8, 5),       # grid 32, angular length 32: the run-time-length streaming FFTs
 ])
 def test_expand_matches_oracle(L, c, R, n, precision):
     got, ref, plan, po = _run(L, c, R, n, precision)
