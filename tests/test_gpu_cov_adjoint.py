@@ -212,3 +212,18 @@ def test_device_philox_matches_host():
     z = synth_normals(5, 2, 11, 4, 1001).cpu().numpy()
     zr = synth.normals(5, 2, np.arange(11, 15), 1001)
     assert np.max(np.abs(z - zr)) <= 1e-6 * np.max(np.abs(zr))
+
+
+def test_empty_batches_are_no_ops():
+    """Zero images: the synthesis returns an empty batch, and the covariance state (G, the
+    k = 0 sums and the count) is left exactly as it was."""
+    plan = Plan(32, 0.5, 16)
+    empty = torch.zeros((0, plan.p_half, 2), dtype=torch.float32, device="cuda")
+    assert plan.adjoint(empty).shape == (0, 32, 32)
+    x = torch.tensor(noise_images(32, 20, seed=6), device="cuda")
+    st = plan.covariance(plan.expand(x))
+    G0, S00, n0 = st.G.clone(), st.S0.clone(), st.count
+    plan.covariance(empty, st)
+    torch.cuda.synchronize()
+    assert st.count == n0 == 20
+    assert torch.equal(st.G, G0) and torch.equal(st.S0, S00)
