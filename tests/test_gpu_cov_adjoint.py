@@ -227,3 +227,26 @@ def test_empty_batches_are_no_ops():
     torch.cuda.synchronize()
     assert st.count == n0 == 20
     assert torch.equal(st.G, G0) and torch.equal(st.S0, S00)
+
+
+def test_eig_blocks_above_128_in_lds():
+    """L = 276 (p_0 = 137): the largest blocks still fit in LDS but take three entries per
+    lane in the rotations; descending eigenvalues equal to LAPACK's, orthonormal
+    eigenvectors, residuals at FP64 rounding of ||C||."""
+    L = 276
+    plan = Plan(L, 0.5, L / 2)
+    assert max(plan.p) == 137
+    x = torch.tensor(noise_images(L, 200, seed=8), device="cuda")
+    evals, evecs, C, _ = plan.eig(plan.covariance(plan.expand(x)))
+    torch.cuda.synchronize()
+    Cb = plan.blocks(C.cpu().numpy())
+    Vb = plan.blocks(evecs.cpu().numpy())
+    lam = evals.cpu().numpy()
+    for k in [0, 1, 2, plan.k_max // 2]:
+        o, pk = plan.coef_off[k], plan.p[k]
+        lk, V = lam[o:o + pk], Vb[k]
+        scale = abs(lk).max()
+        assert np.all(np.diff(lk) <= 0)
+        assert np.allclose(V.T @ V, np.eye(pk), atol=1e-12)
+        assert np.abs(Cb[k] @ V - V * lk[None, :]).max() <= 1e-12 * scale
+        assert np.abs(lk - np.sort(np.linalg.eigvalsh(Cb[k]))[::-1]).max() <= 1e-12 * scale
