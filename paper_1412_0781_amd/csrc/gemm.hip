@@ -78,111 +78,107 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 constexpr int RBM = 128, RBN = 64, RBK = 32;
 constexpr int RLDH = RBK + 8;
 
-struct RadialSmem {
-  float As[RBK][RBM + 4];
-  float Bs[RBK][RBN + 4];
-};
-union RadialOut {
-  float Cs[RBN][RBM + 4];
-};
-
-// FP32 form
-__global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ radial, const float* __restrict__ Fh,
-                                                    float* __restrict__ coeffs, const GemmItem* __restrict__ items,
-                                                    const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                    int n_xi, int nk, int ncol, long long p_half) {
-  constexpr size_t SZ = sizeof(RadialSmem) > sizeof(RadialOut) ? sizeof(RadialSmem) : sizeof(RadialOut);
-  __shared__ __attribute__((aligned(16))) unsigned char smem[SZ];
-  RadialSmem& S = *reinterpret_cast<RadialSmem*>(smem);
-  RadialOut& O = *reinterpret_cast<RadialOut*>(smem);
-  const GemmItem it = items[blockIdx.x];  // k varies fastest: neighbouring workgroups read neighbouring lines of Fh
+// FP32 form, built like the BF16x3 form below.  Each v_mfma_f32_32x32x2f32 takes the pair
+// j = (i, 16 + i) of the chunk in its two lane halves, so that a lane's table fragments
+// for a chunk are 16 consecutive values of its row, loaded straight from global memory
+// (tab: rows zero-padded to kRadialK); F-hat is staged in LDS as [j][column], its loads
+// issued two chunks ahead.  Waves whose rows all lie beyond p_k skip loads and products.
+__global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ tab, const float* __restrict__ Fh,
+                                                        float* __restrict__ coeffs, const GemmItem* __restrict__ items,
+                                                        const int* __restrict__ coef_off, const int* __restrict__ p,
+                                                        int n_xi, int nxp, int nk, int ncol, long long p_half) {
+  union Smem {
+    float Bs[RBK][RBN + 4];      // F-hat chunk, [j][column]
+    float Cs[RBN / 2][RBM + 4];  // half of the output tile, [column][row]
+  };
+  __shared__ __attribute__((aligned(16))) Smem S;
+  const GemmItem it = items[blockIdx.x];
   const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
   const int n0 = blockIdx.y * RBN;
-  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
-  const float* fk = Fh + (size_t)k * (2 * kImgGroup);
-  const bool vec = (n_xi & 3) == 0;
-  float4 ra[4], rb[2];
-  auto gload = [&](int k0) {
+  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6, hf = lane >> 5;
+  const bool live = m0 + wm * 32 < pk;  // uniform over the wave
+  const int row = m0 + wm * 32 + (lane & 31);
+  const bool rlive = row < pk;
+  const float* ta = tab + (size_t)(off + (rlive ? row : 0)) * nxp + 16 * hf;
+  // F-hat staging: thread -> rows j = 2 jp, 2 jp + 1 of the chunk, columns nq .. nq + 3
+  const int jp = tid & 15, nq = 4 * (tid >> 4), col = n0 + nq;
+  const float* fk = Fh + (size_t)k * (2 * kImgGroup) +
+                    (size_t)(col / (2 * kImgGroup)) * n_xi * nk * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
+  float4 a_cu[4];       // this lane's 16 table values of the chunk
+  float4 b1[2], b2[2];  // F-hat of the next chunk and of the one after
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {  // A: 128 rows x 32 k, four consecutive k per thread
-      int idx = tid + u * 256, m = idx >> 3, kq = (idx & 7) * 4;
-      int row = m0 + m, kc = k0 + kq;
-      const float* src = radial + (size_t)(off + row) * n_xi + kc;
-      if (row < pk && vec && kc + 3 < n_xi) {
-        ra[u] = *(const float4*)src;
-      } else {
-        float t[4];
+  for (int u = 0; u < 4; ++u) a_cu[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto load_a = [&](int k0) {
+    if (live && rlive) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] = (row < pk && kc + e < n_xi) ? src[e] : 0.f;
-        ra[u] = make_float4(t[0], t[1], t[2], t[3]);
-      }
+      for (int u = 0; u < 4; ++u) a_cu[u] = *(const float4*)(ta + k0 + 4 * u);
     }
+  };
+  auto load_b = [&](int k0, float4* dst) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {  // B: 32 k x 64 columns, four consecutive columns per thread
-      int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
-      int kc = k0 + kk, col = n0 + nq;  // col % 4 == 0: the four columns share one group
-      const float* src = fk + ((size_t)(col / (2 * kImgGroup)) * n_xi + kc) * nk * (2 * kImgGroup) + (col & (2 * kImgGroup - 1));
+    for (int u = 0; u < 2; ++u) {
+      const int kc = k0 + 2 * jp + u;
+      const float* src = fk + (size_t)kc * nk * (2 * kImgGroup);
       if (kc < n_xi && col + 3 < ncol) {
-        rb[u] = *(const float4*)src;
+        dst[u] = *(const float4*)src;
       } else {
         float t[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) t[e] = (kc < n_xi && col + e < ncol) ? src[e] : 0.f;
-        rb[u] = make_float4(t[0], t[1], t[2], t[3]);
+        dst[u] = make_float4(t[0], t[1], t[2], t[3]);
       }
     }
   };
   auto lstore = [&]() {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int idx = tid + u * 256, m = idx >> 3, kq = (idx & 7) * 4;
-      float v[4] = {ra[u].x, ra[u].y, ra[u].z, ra[u].w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) S.As[kq + e][m] = v[e];
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int idx = tid + u * 256, kk = idx >> 4, nq = (idx & 15) * 4;
-      *(float4*)&S.Bs[kk][nq] = rb[u];
-    }
+    *(float4*)&S.Bs[2 * jp][nq] = b1[0];
+    *(float4*)&S.Bs[2 * jp + 1][nq] = b1[1];
   };
   f32x16 acc0 = {}, acc1 = {};
-  const int nch = (n_xi + RBK - 1) / RBK;
-  gload(0);
+  const int nch = nxp / RBK;
+  load_b(0, b1);
+  load_a(0);
   lstore();
+  if (1 < nch) load_b(RBK, b1);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) gload((c + 1) * RBK);
+    if (c + 2 < nch) load_b((c + 2) * RBK, b2);
+    if (live) {
+      const float av[16] = {a_cu[0].x, a_cu[0].y, a_cu[0].z, a_cu[0].w, a_cu[1].x, a_cu[1].y, a_cu[1].z, a_cu[1].w,
+                            a_cu[2].x, a_cu[2].y, a_cu[2].z, a_cu[2].w, a_cu[3].x, a_cu[3].y, a_cu[3].z, a_cu[3].w};
 #pragma unroll
-    for (int kk = 0; kk < RBK; kk += 2) {
-      float a = S.As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
-      float b0 = S.Bs[kk + (lane >> 5)][lane & 31];
-      float b1 = S.Bs[kk + (lane >> 5)][32 + (lane & 31)];
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+      for (int i = 0; i < 16; ++i) {
+        const float bv0 = S.Bs[16 * hf + i][lane & 31], bv1 = S.Bs[16 * hf + i][32 + (lane & 31)];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv1, acc1, 0, 0, 0);
+      }
     }
+    if (c + 1 < nch) load_a((c + 1) * RBK);
     __syncthreads();
     if (c + 1 < nch) {
       lstore();
+      b1[0] = b2[0];
+      b1[1] = b2[1];
       __syncthreads();
     }
   }
-  // transpose the 128 x 64 tile through LDS: Cs[column][row]
+  // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
+  const int nrow = min(RBM, pk - m0);
+  auto emit = [&](const f32x16& acc, int half) {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int r = wm * 32 + acc_row(i, lane);
-    O.Cs[lane & 31][r] = acc0[i];
-    O.Cs[32 + (lane & 31)][r] = acc1[i];
-  }
+    for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
+    __syncthreads();
+    const int c0 = n0 + 32 * half;
+    const int nimg_t = max(0, min(32, ncol - c0)) / 2;
+    for (int i = tid; i < nimg_t * nrow; i += 256) {
+      const int il = i / nrow, q = i - il * nrow;
+      const float re = S.Cs[2 * il][q];
+      const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
+      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
+    }
+  };
+  emit(acc0, 0);
   __syncthreads();
-  const int nq = min(RBM, pk - m0);
-  const int nimg_t = min(RBN, ncol - n0) / 2;
-  for (int i = tid; i < nimg_t * nq; i += 256) {
-    int il = i / nq, q = i - il * nq;
-    float re = O.Cs[2 * il][q];
-    float im = (k == 0) ? 0.f : O.Cs[2 * il + 1][q];
-    *(float2*)&coeffs[(size_t)(n0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
-  }
+  emit(acc1, 1);
 }
 
 // BF16x3 form of the radial quadrature.  The table operand is split once, at plan time
@@ -547,8 +543,8 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
     hipLaunchKernelGGL(k_radial_fwd_b3, g, dim3(256), 0, st, pl.d_radial_bf, (const float*)Fh, coeffs,
                        pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half);
   else
-    hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial, (const float*)Fh, coeffs, pl.d_items_fwd,
-                       pl.d_coef_off, pl.d_p, pl.n_xi, nk, ncol, (long long)pl.p_half);
+    hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial_pad, (const float*)Fh, coeffs,
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -448,6 +448,11 @@ int upload_plan(Plan& pl) {
         bf[nbp + (size_t)r * pl.n_xi_pad + j] = bf16_rne(x - bf16_val(h));
       }
     FB_HIP_TRY(upload(&pl.d_radial_bf, bf.data(), bf.size()));
+    std::vector<float> pad(nbp, 0.f);
+    for (long long r = 0; r < pl.p_half; ++r)
+      std::copy(r32.begin() + (size_t)r * pl.n_xi, r32.begin() + (size_t)(r + 1) * pl.n_xi,
+                pad.begin() + (size_t)r * pl.n_xi_pad);
+    FB_HIP_TRY(upload(&pl.d_radial_pad, pad.data(), pad.size()));
   }
   std::vector<float> xw(pl.n_xi);
   for (int j = 0; j < pl.n_xi; ++j) xw[j] = (float)(pl.xi[j] * pl.wq[j]);
@@ -483,7 +488,7 @@ int upload_plan(Plan& pl) {
 
 void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
-  void* ptrs[] = {pl.d_radial,    pl.d_radial_bf, pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
+  void* ptrs[] = {pl.d_radial,    pl.d_radial_bf, pl.d_radial_pad, pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
@@ -491,6 +496,7 @@ void free_device(Plan& pl) {
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
   pl.d_radial_bf = nullptr;
+  pl.d_radial_pad = nullptr;
   pl.d_xw = nullptr;
   pl.d_xi = nullptr;
   pl.d_wq = nullptr;

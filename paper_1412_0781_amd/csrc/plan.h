@@ -231,6 +231,7 @@ struct Plan {
   hipError_t last_hip = hipSuccess;
   float* d_radial = nullptr;          // FP32 copy of radial, p_half x n_xi
   unsigned short* d_radial_bf = nullptr;  // its BF16 hi parts, then its lo parts: 2 x p_half x n_xi_pad, zero-padded
+  float* d_radial_pad = nullptr;      // FP32 radial with rows zero-padded to n_xi_pad, p_half x n_xi_pad
   int n_xi_pad = 0;                   // n_xi rounded up to kRadialK
   float* d_xw = nullptr;              // xi_j w_j, n_xi (the radial table's quadrature factor)
   double* d_roots = nullptr;          // R_{k,q} at coef_off[k] + q - 1 (FP64, p_half)
