@@ -23,16 +23,17 @@ constexpr int BM = 64, BN = 64, BK = 16;   // FP32 tiles
 constexpr int BKH = 32;                    // BF16 K chunk
 constexpr int LDH = BKH + 8;               // padded LDS row (80 bytes)
 
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
-  hi = bf16_rne(x);
-  lo = bf16_rne(x - bf16_to_f(hi));
+// The BF16x3 operand split of two values at once, hi = bf16(x), lo = bf16(x - hi), both
+// rounded to nearest even by the hardware conversion (v_cvt_pk_bf16_f32; x - hi is exact
+// in FP32): hi and lo packed two per word, x0 in the low half.
+__device__ __forceinline__ void split_bf16_pair(float x0, float x1, unsigned& hi, unsigned& lo) {
+  const f32x2_t xv = {x0, x1};
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(xv, bf16x2_t));
+  const f32x2_t rv = {x0 - __uint_as_float(hi << 16), x1 - __uint_as_float(hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(rv, bf16x2_t));
 }
 
 __device__ __forceinline__ int acc_row(int i, int lane) { return (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3); }
@@ -249,11 +250,10 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
     const float v1[4] = {b1[1].x, b1[1].y, b1[1].z, b1[1].w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      unsigned short h0, l0, h1, l1;
-      split_bf16(v0[e], h0, l0);
-      split_bf16(v1[e], h1, l1);
-      S.b.Bh[nq + e][jp] = (unsigned)h0 | ((unsigned)h1 << 16);
-      S.b.Bl[nq + e][jp] = (unsigned)l0 | ((unsigned)l1 << 16);
+      unsigned h, l;
+      split_bf16_pair(v0[e], v1[e], h, l);
+      S.b.Bh[nq + e][jp] = h;
+      S.b.Bl[nq + e][jp] = l;
     }
   };
   f32x16 acc0 = {}, acc1 = {};
@@ -449,16 +449,14 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
           S.Bs[col + 1][q] = rb[u].y;
         }
       } else {
-        unsigned short h0, l0, h1, l1;
-        split_bf16(ra[u].x, h0, l0);
-        split_bf16(ra[u].y, h1, l1);
-        *(unsigned*)&S.Ah[q][col] = (unsigned)h0 | ((unsigned)h1 << 16);
-        *(unsigned*)&S.Al[q][col] = (unsigned)l0 | ((unsigned)l1 << 16);
+        unsigned h, l;
+        split_bf16_pair(ra[u].x, ra[u].y, h, l);
+        *(unsigned*)&S.Ah[q][col] = h;
+        *(unsigned*)&S.Al[q][col] = l;
         if (!diag) {
-          split_bf16(rb[u].x, h0, l0);
-          split_bf16(rb[u].y, h1, l1);
-          *(unsigned*)&S.Bh[q][col] = (unsigned)h0 | ((unsigned)h1 << 16);
-          *(unsigned*)&S.Bl[q][col] = (unsigned)l0 | ((unsigned)l1 << 16);
+          split_bf16_pair(rb[u].x, rb[u].y, h, l);
+          *(unsigned*)&S.Bh[q][col] = h;
+          *(unsigned*)&S.Bl[q][col] = l;
         }
       }
     }
