@@ -1160,7 +1160,16 @@ static_assert(kMaxTransforms <= kImgGroup, "an FFT workgroup's image slots map t
 // better.)
 static int stream_units(const Plan& pl, long long units, int per_cu, int floor) {
   const long long slots = (long long)pl.num_cus * per_cu;
-  return (int)std::max<long long>(floor, (units + slots - 1) / slots);
+  const long long u = (units + slots - 1) / slots;
+  // a pass too small to give every resident slot `floor` units takes one round of
+  // workgroups instead of a few long ones
+  return (int)(units >= slots * floor ? u : std::max<long long>(1, u));
+}
+// Units per workgroup of the row and angular launches: `cap` when the pass fills the
+// device several times over, fewer when it would leave resident slots idle.
+static int fixed_units(const Plan& pl, long long units, int per_cu, int cap) {
+  const long long slots = (long long)pl.num_cus * per_cu;
+  return (int)std::max<long long>(1, std::min<long long>(cap, (units + slots - 1) / slots));
 }
 struct FftLaunch {
   int count;
@@ -1233,9 +1242,10 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   if (stream_ok) {
     const int nrb = ((L + 1) / 2 + 15) / 16;
     const long long ur = (long long)nimg * nrb;
+    const int Ur = fixed_units(pl, ur, 2, kGridUnits);
     pl.prof.begin(ST_FWD_ROWS, st);
-    FB_LAUNCH_POW2(k_fwd_rows_stream, N, dim3((unsigned)((ur + kGridUnits - 1) / kGridUnits)), st,
-                       images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, kGridUnits,
+    FB_LAUNCH_POW2(k_fwd_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
+                       images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, Ur,
                        make_fastdiv(L / 4), make_fastdiv(N - L));
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
@@ -1277,7 +1287,7 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
                          fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
   if (stream_ok) {
     const int units = pl.n_xi * ngrp;
-    const int U = kAngularUnits;
+    const int U = fixed_units(pl, units, 2, kAngularUnits);
     pl.prof.begin(ST_FWD_ANGULAR, st);
     FB_LAUNCH_POW2(k_fwd_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, P,
                        Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, ngrp, U, scale);
@@ -1299,7 +1309,7 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
                          fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
   if (stream_ok) {
     const long long units = (long long)pl.n_xi * ngrp;
-    const int U = kAngularUnits;
+    const int U = fixed_units(pl, units, 2, kAngularUnits);
     const float sc = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
     pl.prof.begin(ST_ADJ_ANGULAR, st);
     FB_LAUNCH_POW2(k_adj_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, D, Q,
