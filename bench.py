@@ -130,6 +130,7 @@ def time_form(plan, images, coeffs, precision, steps, warmup, pass_images):
         st.G.zero_()
         st.S0.zero_()
         st.count = 0
+        st.shift_set = False  # each step takes the shift from its first images again
         plan.expand(images, precision=precision, out=coeffs, batch=pass_images)
         plan.covariance(coeffs, st, precision=precision)
 

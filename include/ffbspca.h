@@ -123,6 +123,13 @@ size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision);
  * FB_ERR_WORKSPACE, FB_ERR_NO_DEVICE, FB_ERR_HIP (launch failure). */
 int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision,
               void* ws, size_t ws_bytes, void* stream);
+/* fb_expand with a weight on the output: weight_mode 1 is fb_expand itself; weight_mode 0
+ * multiplies every k > 0 coefficient by 2, the +-k fold weight of the coefficient inner
+ * product below (w * T* g is the gradient of the synthesis fb_adjoint with respect to its
+ * coefficients; the multiplication is exact).  Same arguments and errors as fb_expand, plus
+ * FB_ERR_INVALID_ARG for a weight_mode other than 0 or 1. */
+int fb_expand_weighted(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision,
+                       int weight_mode, void* ws, size_t ws_bytes, void* stream);
 
 /* Synthesis I = T b, the transpose of fb_expand with respect to the coefficient
  * inner product sum_q b_{0q} c_{0q} + 2 Re sum_{k>0,q} conj(b_{kq}) c_{kq}
@@ -143,26 +150,45 @@ int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* i
                         const float* ring_filter, void* ws, size_t ws_bytes, void* stream);
 
 /* Accumulate the steerable covariance of n coefficient vectors (Eqs.(ck),(ck_0)):
- *   G[cov_off[k] + q p_k + q'] += sum_i Re(a^i_{kq} conj(a^i_{kq'}))   (FP64, full p_k x p_k blocks)
- *   S0[q] += sum_i a^i_{0q}                                           (FP64 [p_0])
- *   *count += n                                                       (host int64)
- * G and S0 are device memory owned by the caller (zero them before the first
- * call).  The n images are cut into at most 16 runs of consecutive images;
- * within a run, partial sums are formed in FP32 over at most 256 images and
- * added to FP64 in a fixed order, and the runs' FP64 sums are added into G in
- * run order, so results are bitwise reproducible.  ws: device scratch of at
- * least fb_covariance_workspace_bytes(plan, n) bytes, 8-byte aligned, owned by
- * the caller (contents on entry are ignored).  Asynchronous.  precision selects
- * FB_FP32 or FB_BF16X3 products.
- * Errors: FB_ERR_INVALID_ARG (NULL or misaligned pointers, n < 0, bad
+ *   G[cov_off[k] + q p_k + q'] += sum_i Re(b^i_{kq} conj(b^i_{kq'}))  (FP64, full p_k x p_k blocks)
+ *   S0[q] += sum_i b^i_{0q}                                          (FP64 [p_0])
+ *   Gi[cov_off[k] + q p_k + q'] += sum_i Im(a^i_{kq} conj(a^i_{kq'})) (FP64, nullable; k > 0)
+ *   *count += n                                                      (host int64)
+ * with b = a, except that the k = 0 coefficients enter as b_{0q} = a_{0q} - shift[q] when
+ * `shift` is given.  `shift` (device FP32 [p_0], nullable, read only) keeps the k = 0 sums of
+ * the order of the spread of the data instead of its mean, so that the FP32 (or BF16x3)
+ * products lose no accuracy to a large mean image.  Any fixed vector near the mean serves
+ * (fb_covariance_shift makes one from the first call's images); every call that adds into
+ * one G must pass the same values, and fb_eig must receive them too: C^(0) = G^(0)/count -
+ * d d^T with d = S0/count does not depend on the shift, and the mean is shift + d.
+ * Gi (nullable) accumulates the imaginary part of the Hermitian matrix sum_i a a^* of each
+ * k > 0 (the covariance of the data augmented by rotations only, before the reflections of
+ * Sec. III make it real; Eq.(cov) without the real part), Im(A A^*) = Ai Ar^T - Ar Ai^T:
+ * antisymmetric blocks; the k = 0 block is left unchanged (a_0 is real).  The SO(2)
+ * Hermitian covariance is (G + i Gi)/count for k > 0.
+ * G, S0 and Gi are device memory owned by the caller (zero them before the first call).
+ * The n images are cut into at most 16 runs of consecutive images; within a run, partial
+ * sums are formed in FP32 over at most 256 images and added to FP64 in a fixed order, and
+ * the runs' FP64 sums are added into G in run order, so results are bitwise reproducible.
+ * ws: device scratch of at least fb_covariance_workspace_bytes(plan, n, Gi != NULL) bytes,
+ * 8-byte aligned, owned by the caller (contents on entry are ignored).  Asynchronous.
+ * precision selects FB_FP32 or FB_BF16X3 products.
+ * Errors: FB_ERR_INVALID_ARG (NULL or misaligned pointers, n < 0, *count < 0, bad
  * precision), FB_ERR_WORKSPACE (ws too small), FB_ERR_NO_DEVICE (host-only plan). */
-int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
-                  int precision, void* ws, size_t ws_bytes, void* stream);
-/* Scratch bytes fb_covariance needs for n images (0 for n <= 0 or a NULL plan). */
-size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n);
+int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, double* Gi,
+                  const float* shift, int64_t* count, int precision, void* ws, size_t ws_bytes, void* stream);
+/* shift[q] = the mean of a^i_{0q} over the first min(n, 1024) of the n coefficient vectors
+ * (FP64 sum in image order, rounded to FP32): a shift for fb_covariance.  shift is device
+ * FP32 [p_0], caller-owned.  Asynchronous.  Errors: FB_ERR_INVALID_ARG (NULL pointers,
+ * n <= 0), FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+int fb_covariance_shift(fb_plan_t plan, const float* coeffs, int64_t n, float* shift, void* stream);
+/* Scratch bytes fb_covariance needs for n images, with (hermitian != 0) or without the
+ * imaginary parts (0 for n <= 0 or a NULL plan). */
+size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n, int hermitian);
 
 /* Finalise and diagonalise (Algorithm 2, steps 1 and 4), all FP64 on the device:
- *   m = S0 / count;  C^(0) = G^(0)/count - m m^T;  C^(k) = G^(k)/count (k > 0);
+ *   d = S0 / count;  C^(0) = G^(0)/count - d d^T;  C^(k) = G^(k)/count (k > 0);
+ *   m = shift + d (the k = 0 mean; shift as passed to fb_covariance, NULL meaning 0);
  *   evals [p_half]: eigenvalues of each C^(k), descending within block k (at coef_off[k]);
  *   evecs [cov_size]: block k at cov_off[k], p_k x p_k row-major, column l = u_l,
  *         sign-normalised so that its entry of largest magnitude is positive;
@@ -176,8 +202,8 @@ size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n);
  * block norm.
  * Asynchronous.
  * Errors: FB_ERR_INVALID_ARG if count <= 0 or a required pointer is NULL. */
-int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, double* evals, double* evecs,
-           double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream);
+int fb_eig(fb_plan_t plan, const double* G, const double* S0, const float* shift, int64_t count, double* evals,
+           double* evecs, double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream);
 size_t fb_eig_workspace_bytes(fb_plan_t plan);
 
 /* Steerable PCA back end (Algorithm 2, steps 5-6, and Sec. V), on the eigenpairs of

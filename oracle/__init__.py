@@ -40,6 +40,7 @@ from .fb import (  # noqa: F401
     expand,
     expand_sparse,
     expand_stages,
+    hermitian_covariance,
     mean_and_covariance,
     covariance_blocks,
     eig_blocks,

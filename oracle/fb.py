@@ -275,6 +275,21 @@ def mean_and_covariance(a: np.ndarray, pl: Plan):
     return mean0, C
 
 
+def hermitian_covariance(a: np.ndarray, pl: Plan):
+    """Blocks of the covariance of the data augmented by rotations only (Sec. III: Eq.(cov)
+    before the reflections make it real): C_H^(k) = (1/n) A^(k) A^(k)^*, complex Hermitian,
+    for k > 0, and C^(0) as in `mean_and_covariance` for k = 0 (the mean removed; real).
+    Its real part is the C^(k) of Eq.(ck); its imaginary part is (1/n)(Ai Ar^T - Ar Ai^T)."""
+    n = a.shape[0]
+    mean0, C = mean_and_covariance(a, pl)
+    out = [C[0].astype(np.complex128)]
+    for k in range(1, pl.k_max + 1):
+        o = pl.coef_off[k]
+        A = a[:, o:o + pl.p[k]].T
+        out.append(A @ A.conj().T / n)
+    return mean0, out
+
+
 def covariance_blocks(a: np.ndarray, pl: Plan):
     return mean_and_covariance(a, pl)[1]
 

@@ -45,10 +45,13 @@ SIGNATURES = [
     ("fb_workspace_bytes", c_size_t, [c_void_p, c_int64, c_int]),
     ("fb_expand", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
     ("fb_adjoint", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
-    ("fb_covariance", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, P(c_int64), c_int, c_void_p,
-                              c_size_t, c_void_p]),
-    ("fb_covariance_workspace_bytes", c_size_t, [c_void_p, c_int64]),
-    ("fb_eig", c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+    ("fb_expand_weighted", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_int, c_void_p, c_size_t,
+                                   c_void_p]),
+    ("fb_covariance", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64),
+                              c_int, c_void_p, c_size_t, c_void_p]),
+    ("fb_covariance_workspace_bytes", c_size_t, [c_void_p, c_int64, c_int]),
+    ("fb_covariance_shift", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    ("fb_eig", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                        c_void_p, c_size_t, c_void_p]),
     ("fb_eig_workspace_bytes", c_size_t, [c_void_p]),
     ("fb_spca_select", c_int, [c_void_p, c_void_p, c_int64, c_double, c_void_p, c_void_p, c_void_p]),

@@ -133,7 +133,12 @@ size_t fb_workspace_bytes(fb_plan_t plan, int64_t batch, int precision) {
 
 int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision, void* ws,
               size_t ws_bytes, void* stream) {
-  if (!plan || n < 0) return FB_ERR_INVALID_ARG;
+  return fb_expand_weighted(plan, images, n, coeffs, precision, 1, ws, ws_bytes, stream);
+}
+
+int fb_expand_weighted(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision,
+                       int weight_mode, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || n < 0 || (weight_mode != 0 && weight_mode != 1)) return FB_ERR_INVALID_ARG;
   if (precision != FB_FP32 && precision != FB_BF16X3) return FB_ERR_INVALID_ARG;
   if (n == 0) return FB_OK;
   if (!images || !coeffs || !ws) return FB_ERR_INVALID_ARG;
@@ -150,7 +155,8 @@ int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int
     int m = (int)std::min<int64_t>(nb, n - s);
     int rc = hip_rc(pl, fb::launch_forward_nufft(pl, images + s * img_stride, m, bufA, bufB, st));
     if (rc == FB_OK) rc = hip_rc(pl, fb::launch_forward_angular(pl, bufA, bufB, m, st));
-    if (rc == FB_OK) rc = hip_rc(pl, fb::launch_radial_forward(pl, bufB, coeffs + s * coef_stride, m, precision, st));
+    if (rc == FB_OK)
+      rc = hip_rc(pl, fb::launch_radial_forward(pl, bufB, coeffs + s * coef_stride, m, precision, weight_mode, st));
     if (rc != FB_OK) return rc;
   }
   return FB_OK;
@@ -186,35 +192,43 @@ int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* i
   return FB_OK;
 }
 
-size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n) {
+size_t fb_covariance_workspace_bytes(fb_plan_t plan, int64_t n, int hermitian) {
   if (!plan || n <= 0) return 0;
-  return fb::cov_split(plan->pl, n).bytes;
+  return fb::cov_split(plan->pl, n, hermitian != 0).bytes;
 }
 
-int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, int64_t* count,
-                  int precision, void* ws, size_t ws_bytes, void* stream) {
+int fb_covariance_shift(fb_plan_t plan, const float* coeffs, int64_t n, float* shift, void* stream) {
+  if (!plan || n <= 0 || !coeffs || !shift) return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  return hip_rc(pl, fb::launch_cov_shift(pl, coeffs, n, shift, (hipStream_t)stream));
+}
+
+int fb_covariance(fb_plan_t plan, const float* coeffs, int64_t n, double* G, double* S0, double* Gi,
+                  const float* shift, int64_t* count, int precision, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || n < 0) return FB_ERR_INVALID_ARG;
   if (precision != FB_FP32 && precision != FB_BF16X3) return FB_ERR_INVALID_ARG;
-  if (!G || !S0 || !count) return FB_ERR_INVALID_ARG;
+  if (!G || !S0 || !count || *count < 0) return FB_ERR_INVALID_ARG;
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   if (n == 0) return FB_OK;
   if (!coeffs || !ws || ((uintptr_t)ws & 7)) return FB_ERR_INVALID_ARG;
-  if (ws_bytes < fb::cov_split(pl, n).bytes) return FB_ERR_WORKSPACE;
-  int rc = hip_rc(pl, fb::launch_covariance(pl, coeffs, n, G, S0, precision, ws, (hipStream_t)stream));
+  if (ws_bytes < fb::cov_split(pl, n, Gi != nullptr).bytes) return FB_ERR_WORKSPACE;
+  int rc = hip_rc(pl, fb::launch_covariance(pl, coeffs, n, G, S0, Gi, shift, precision, ws, (hipStream_t)stream));
   if (rc == FB_OK) *count += n;
   return rc;
 }
 
 size_t fb_eig_workspace_bytes(fb_plan_t plan) { return plan ? fb::eig_workspace_bytes(plan->pl) : 0; }
 
-int fb_eig(fb_plan_t plan, const double* G, const double* S0, int64_t count, double* evals, double* evecs,
-           double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream) {
+int fb_eig(fb_plan_t plan, const double* G, const double* S0, const float* shift, int64_t count, double* evals,
+           double* evecs, double* C_out, double* mean_out, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || count <= 0 || !G || !S0 || !evals || !evecs || !ws) return FB_ERR_INVALID_ARG;
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   if (ws_bytes < fb::eig_workspace_bytes(pl)) return FB_ERR_WORKSPACE;
-  return hip_rc(pl, fb::launch_eig(pl, G, S0, count, evals, evecs, C_out, mean_out, (double*)ws, (hipStream_t)stream));
+  return hip_rc(pl, fb::launch_eig(pl, G, S0, shift, count, evals, evecs, C_out, mean_out, (double*)ws,
+                                   (hipStream_t)stream));
 }
 
 int fb_spca_select(fb_plan_t plan, const double* evals, int64_t count, double sigma2, int32_t* n_sel,

@@ -1,5 +1,7 @@
 // Algorithm 2, steps 1 and 4 in FP64 on the device: finalise each covariance
-// block C^(k) = G^(k)/n (k = 0: minus m m^T, m the mean of a_{0,q}) and
+// block C^(k) = G^(k)/n (k = 0: minus d d^T with d = S0/n, the mean of the k = 0
+// coefficients in the coordinates they were accumulated in: a_{0,q} - s_q when the
+// accumulation used a shift s; the mean itself is s + d) and
 // diagonalise it, one workgroup per k.  Where the block fits in LDS, by one-sided
 // Jacobi rotations on its columns in LDS; otherwise by cyclic two-sided Jacobi
 // rotations in global memory, every round applying p_k/2 disjoint rotations in
@@ -144,7 +146,7 @@ __device__ void eig_two_sided(double* A, double* V, int pk, int off_k, double* e
 
 // Two-sided form, A and V in global memory (any p_k up to EIG_MAX_P).
 __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ G, const double* __restrict__ S0,
-                                                     long long count, double* __restrict__ evals,
+                                                     const float* __restrict__ shift, long long count, double* __restrict__ evals,
                                                      double* __restrict__ evecs, double* __restrict__ C_out,
                                                      double* __restrict__ mean_out, double* __restrict__ work,
                                                      const int* __restrict__ p, const int* __restrict__ coef_off,
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ 
     V[i] = (i / pk == i % pk) ? 1.0 : 0.0;
   }
   if (k == 0 && mean_out)
-    for (int q = threadIdx.x; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
+    for (int q = threadIdx.x; q < pk; q += blockDim.x) mean_out[q] = (shift ? (double)shift[q] : 0.0) + S0[q] * inv;
   __syncthreads();
   eig_two_sided(A, V, pk, coef_off[k], evals);
 }
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ 
 // the columns of V are the eigenvectors, each accurate to the orthogonality tolerance times
 // ||C|| however small its eigenvalue; lambda_l = v_l . b_l (the Rayleigh quotient).
 __global__ __launch_bounds__(EIG_THREADS) void k_eig_lds(const double* __restrict__ G, const double* __restrict__ S0,
-                                                         long long count, double* __restrict__ evals,
+                                                         const float* __restrict__ shift, long long count, double* __restrict__ evals,
                                                          double* __restrict__ evecs, double* __restrict__ C_out,
                                                          double* __restrict__ mean_out, double* __restrict__ work,
                                                          const int* __restrict__ p, const int* __restrict__ coef_off,
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig_lds(const double* __restric
     if (C_out) C_out[base + i] = v;
   }
   if (k == 0 && mean_out)
-    for (int q = tid; q < pk; q += blockDim.x) mean_out[q] = S0[q] * inv;
+    for (int q = tid; q < pk; q += blockDim.x) mean_out[q] = (shift ? (double)shift[q] : 0.0) + S0[q] * inv;
   __syncthreads();
   one_sided_jacobi<true>(M, pk, &s_rot, V);
   for (int l = tid; l < pk; l += blockDim.x) {
@@ -242,16 +244,16 @@ hipError_t configure_eig_kernels() {
   return hipFuncSetAttribute((const void*)k_eig_lds, hipFuncAttributeMaxDynamicSharedMemorySize, kEigLdsLimit);
 }
 
-hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
-                      double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st) {
+hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, const float* shift, long long count,
+                      double* evals, double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st) {
   pl.prof.begin(ST_EIG, st);
   const size_t lds = eig_lds_bytes(pl);
   if (lds <= (size_t)kEigLdsLimit)
-    hipLaunchKernelGGL(k_eig_lds, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), lds, st, G, S0, count, evals,
-                       evecs, C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+    hipLaunchKernelGGL(k_eig_lds, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), lds, st, G, S0, shift, count,
+                       evals, evecs, C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
   else
-    hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, count, evals, evecs,
-                       C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
+    hipLaunchKernelGGL(k_eig, dim3((unsigned)(pl.k_max + 1)), dim3(EIG_THREADS), 0, st, G, S0, shift, count, evals,
+                       evecs, C_out, mean_out, work, pl.d_p, pl.d_coef_off, pl.d_cov_off);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -87,7 +87,8 @@ constexpr int RLDH = RBK + 8;
 __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ tab, const float* __restrict__ Fh,
                                                         float* __restrict__ coeffs, const GemmItem* __restrict__ items,
                                                         const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                        int n_xi, int nxp, int nk, int ncol, long long p_half) {
+                                                        int n_xi, int nxp, int nk, int ncol, long long p_half,
+    int weight_mode) {
   union Smem {
     float Bs[RBK][RBN + 4];      // F-hat chunk, [j][column]
     float Cs[RBN / 2][RBM + 4];  // half of the output tile, [column][row]
@@ -164,6 +165,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
   }
   // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
   const int nrow = min(RBM, pk - m0);
+  const float wk = (weight_mode == 0 && k > 0) ? 2.f : 1.f;  // +-k fold weight (exact)
   auto emit = [&](const f32x16& acc, int half) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
       const int il = i / nrow, q = i - il * nrow;
       const float re = S.Cs[2 * il][q];
       const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
-      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
+      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] =
+          make_float2(wk * re, wk * im);
     }
   };
   emit(acc0, 0);
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
                                                        const float* __restrict__ Fh, float* __restrict__ coeffs,
                                                        const GemmItem* __restrict__ items,
                                                        const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                       int n_xi, int nxp, int nk, int ncol, long long p_half) {
+                                                       int n_xi, int nxp, int nk, int ncol, long long p_half,
+    int weight_mode) {
   union Smem {
     struct {
       unsigned int Bh[RBN][RLDH / 2], Bl[RBN][RLDH / 2];  // [column][j / 2], two BF16 per word
@@ -293,6 +297,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   }
   // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
   const int nrow = min(RBM, pk - m0);
+  const float wk = (weight_mode == 0 && k > 0) ? 2.f : 1.f;  // +-k fold weight (exact)
   auto emit = [&](const f32x16& acc, int half) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
@@ -303,7 +308,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
       const int il = i / nrow, q = i - il * nrow;
       const float re = S.Cs[2 * il][q];
       const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
-      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] = make_float2(re, im);
+      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] =
+          make_float2(wk * re, wk * im);
     }
   };
   emit(acc0, 0);
@@ -368,7 +374,13 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
 // registers every COV_FLUSH_COLS columns; each block writes its FP64 tile (and the
 // mirrored tile) into its slice's partial copy of G, which k_cov_reduce then adds
 // into G in slice order, so the result does not depend on scheduling.
-// The k = 0 imaginary parts are masked; the k = 0 diagonal tiles also sum S0.
+// The k = 0 imaginary parts are masked; the k = 0 diagonal tiles also sum S0.  With a
+// shift s (FP32 [p_0]) the k = 0 rows enter as a_{0q} - s_q, before the BF16 split, so
+// the sums stay of the order of the spread of the data rather than of its mean.
+// HERM also forms the imaginary part of A A^* for k > 0 (the Hermitian covariance
+// under rotations only): Im(A A^*) = Ai Ar^T - Ar Ai^T = X Y^T with the second operand
+// taken as Y[q][2i] = -Im a^i_{kq}, Y[q][2i + 1] = Re a^i_{kq}: one more product per
+// chunk from the same staged tiles.
 // ---------------------------------------------------------------------------
 constexpr int COV_FLUSH_COLS = 512;
 constexpr int COV_IMG = 16;                 // images per K chunk
@@ -398,9 +410,56 @@ __device__ __forceinline__ void mma_f32_k32(const float (*As)[BM + 4], const flo
   }
 }
 
-template <int PREC>
+// X Y^T with Y[2i] = -X[2i + 1], Y[2i + 1] = X[2i] on the second operand (FP32 form)
+__device__ __forceinline__ void mma_f32_k32_im(const float (*As)[BM + 4], const float (*Bs)[BN + 4], f32x16& acc,
+                                               int wm, int wn, int lane) {
+  const int h = lane >> 5;
+#pragma unroll
+  for (int kk = 0; kk < COV_K; kk += 2) {
+    float a = As[kk + h][wm * 32 + (lane & 31)];
+    float b = Bs[kk + 1 - h][wn * 32 + (lane & 31)];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, h ? b : -b, acc, 0, 0, 0);
+  }
+}
+
+// (re, im) BF16 pairs of a fragment -> (-im, re): swap the halves of each word, negate the low one
+__device__ __forceinline__ bf16x8 swap_neg_pairs(bf16x8 x) {
+  uint4 u = __builtin_bit_cast(uint4, x);
+  u.x = ((u.x >> 16) | (u.x << 16)) ^ 0x8000u;
+  u.y = ((u.y >> 16) | (u.y << 16)) ^ 0x8000u;
+  u.z = ((u.z >> 16) | (u.z << 16)) ^ 0x8000u;
+  u.w = ((u.w >> 16) | (u.w << 16)) ^ 0x8000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// BF16x3 products of the real part (acc) and, when im, of the imaginary part (acc_im)
+template <bool IM>
+__device__ __forceinline__ void mma_bf16x3_cov(const unsigned short (*Ah)[LDH], const unsigned short (*Al)[LDH],
+                                               const unsigned short (*Bh)[LDH], const unsigned short (*Bl)[LDH],
+                                               f32x16& acc, f32x16& acc_im, bool im, int wm, int wn, int lane) {
+  const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31);
+#pragma unroll
+  for (int kb = 0; kb < BKH; kb += 16) {
+    const int c = kb + 8 * (lane >> 5);
+    bf16x8 ah = ld8(&Ah[ra][c]), al = ld8(&Al[ra][c]);
+    bf16x8 bh = ld8(&Bh[rb][c]), bl = ld8(&Bl[rb][c]);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    if (IM && im) {
+      const bf16x8 yh = swap_neg_pairs(bh), yl = swap_neg_pairs(bl);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, yh, acc_im, 0, 0, 0);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, yl, acc_im, 0, 0, 0);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, yh, acc_im, 0, 0, 0);
+    }
+  }
+}
+
+template <int PREC, bool HERM>
 __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ coeffs, double* __restrict__ partG,
-                                                    double* __restrict__ partS0, const GemmItem* __restrict__ items,
+                                                    double* __restrict__ partS0, double* __restrict__ partGi,
+                                                    const float* __restrict__ shift,
+                                                    const GemmItem* __restrict__ items,
                                                     const int* __restrict__ coef_off, const int* __restrict__ p,
                                                     const long long* __restrict__ cov_off, long long n,
                                                     long long p_half, int nitems, long long per, long long cov_size,
@@ -421,6 +480,10 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   const float2* srcA = (const float2*)coeffs + off + m0 + q;
   const float2* srcB = (const float2*)coeffs + off + n0 + q;
   const bool k0 = (k == 0);
+  const bool im = HERM && !k0;  // the imaginary part of a k = 0 block is zero
+  // k = 0 rows enter shifted (rows past p_0 and images past the run stay exactly zero)
+  const float sha = (k0 && shift && rowa) ? shift[m0 + q] : 0.f;
+  const float shb = (k0 && shift && rowb) ? shift[n0 + q] : 0.f;
   float2 ra[4], rb[4];
   auto gload = [&](long long c0) {
 #pragma unroll
@@ -430,6 +493,8 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
       ra[u] = (ok && rowa) ? srcA[img * p_half] : make_float2(0.f, 0.f);
       if (!diag) rb[u] = (ok && rowb) ? srcB[img * p_half] : make_float2(0.f, 0.f);
       if (k0) {
+        if (ok && rowa) ra[u].x -= sha;
+        if (!diag && ok && rowb) rb[u].x -= shb;
         ra[u].y = 0.f;
         rb[u].y = 0.f;
       }
@@ -461,10 +526,14 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
       }
     }
   };
-  f32x16 acc = {};
-  double dacc[16];
+  f32x16 acc = {}, acc_im = {};
+  double dacc[16], dacc_im[HERM ? 16 : 1];
 #pragma unroll
   for (int i = 0; i < 16; ++i) dacc[i] = 0.0;
+  if constexpr (HERM) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dacc_im[i] = 0.0;
+  }
   double dsum = 0.0;
   int since_flush = 0;
   gload(i0);
@@ -474,11 +543,12 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
     if (c0 + COV_IMG < i1) gload(c0 + COV_IMG);
     if constexpr (PREC == 0) {
       mma_f32_k32(S.As, diag ? S.As : S.Bs, acc, wm, wn, lane);
+      if (HERM && im) mma_f32_k32_im(S.As, diag ? S.As : S.Bs, acc_im, wm, wn, lane);
     } else {
       if (diag)
-        mma_bf16x3(S.Ah, S.Al, S.Ah, S.Al, acc, wm, wn, lane);
+        mma_bf16x3_cov<HERM>(S.Ah, S.Al, S.Ah, S.Al, acc, acc_im, im, wm, wn, lane);
       else
-        mma_bf16x3(S.Ah, S.Al, S.Bh, S.Bl, acc, wm, wn, lane);
+        mma_bf16x3_cov<HERM>(S.Ah, S.Al, S.Bh, S.Bl, acc, acc_im, im, wm, wn, lane);
     }
     __syncthreads();
     since_flush += COV_K;
@@ -488,6 +558,13 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
         dacc[i] += (double)acc[i];
         acc[i] = 0.f;
       }
+      if constexpr (HERM) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          dacc_im[i] += (double)acc_im[i];
+          acc_im[i] = 0.f;
+        }
+      }
       dsum += (double)ssum;
       ssum = 0.f;
       since_flush = 0;
@@ -495,6 +572,10 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) dacc[i] += (double)acc[i];
+  if constexpr (HERM) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dacc_im[i] += (double)acc_im[i];
+  }
   dsum += (double)ssum;
   double* gk = partG + (size_t)slice * cov_size + cov_off[k];
 #pragma unroll
@@ -503,6 +584,20 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
     if (r < pk && c < pk) {
       gk[(size_t)r * pk + c] = dacc[i];
       if (!diag) gk[(size_t)c * pk + r] = dacc[i];
+    }
+  }
+  if constexpr (HERM) {
+    // the imaginary part is antisymmetric: every value is written at (r, c) with r < c and
+    // negated at (c, r), the diagonal as zero (a diagonal tile keeps its upper triangle)
+    double* gi = partGi + (size_t)slice * cov_size + cov_off[k];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      int r = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
+      if (r < pk && c < pk && r <= c) {
+        const double v = (r == c) ? 0.0 : dacc_im[i];
+        gi[(size_t)r * pk + c] = v;
+        gi[(size_t)c * pk + r] = -v;
+      }
     }
   }
   if (do_sum) {
@@ -514,14 +609,21 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   }
 }
 
-// G[i] += sum over slices s = 0..S-1 (in that order) of partG[s][i]; the same for S0.
-__global__ void k_cov_reduce(const double* __restrict__ partG, const double* __restrict__ partS0, int S,
-                             long long cov_size, int p0, double* __restrict__ G, double* __restrict__ S0) {
+// G[i] += sum over slices s = 0..S-1 (in that order) of partG[s][i]; the same for S0
+// and, when partGi is given, for Gi.
+__global__ void k_cov_reduce(const double* __restrict__ partG, const double* __restrict__ partS0,
+                             const double* __restrict__ partGi, int S, long long cov_size, int p0,
+                             double* __restrict__ G, double* __restrict__ S0, double* __restrict__ Gi) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cov_size) {
     double t = 0.0;
     for (int s = 0; s < S; ++s) t += partG[(size_t)s * cov_size + i];
     G[i] += t;
+    if (partGi) {
+      double u = 0.0;
+      for (int s = 0; s < S; ++s) u += partGi[(size_t)s * cov_size + i];
+      Gi[i] += u;
+    }
   } else if (i < cov_size + p0) {
     const int m = (int)(i - cov_size);
     double t = 0.0;
@@ -530,19 +632,40 @@ __global__ void k_cov_reduce(const double* __restrict__ partG, const double* __r
   }
 }
 
+// shift[q] = mean of a_{0,q} over the first m images (FP64 sum in image order), rounded to FP32
+__global__ void k_cov_shift(const float* __restrict__ coeffs, int m, long long p_half, int p0,
+                            float* __restrict__ shift) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= p0) return;
+  // eight loads in flight, added in image order
+  double t = 0.0;
+  int i = 0;
+  for (; i + 8 <= m; i += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = coeffs[2 * ((size_t)(i + u) * p_half + q)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += (double)v[u];
+  }
+  for (; i < m; ++i) t += (double)coeffs[2 * ((size_t)i * p_half + q)];
+  shift[q] = (float)(t / m);
+}
+
 // ---------------------------------------------------------------------------
 hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs, int nimg, int precision,
-                                 hipStream_t st) {
+                                 int weight_mode, hipStream_t st) {
   const int ncol = 2 * nimg;
   dim3 g((unsigned)pl.items_fwd.size(), (unsigned)((ncol + RBN - 1) / RBN));
   const int nk = pl.k_max + 1;
   pl.prof.begin(ST_RADIAL_FWD, st);
   if (precision == FB_BF16X3)
     hipLaunchKernelGGL(k_radial_fwd_b3, g, dim3(256), 0, st, pl.d_radial_bf, (const float*)Fh, coeffs,
-                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half);
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half,
+                       weight_mode);
   else
     hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial_pad, (const float*)Fh, coeffs,
-                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half);
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half,
+                       weight_mode);
   pl.prof.end(st);
   return hipGetLastError();
 }
@@ -559,7 +682,7 @@ hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D,
   return hipGetLastError();
 }
 
-CovSplit cov_split(const Plan& pl, long long n) {
+CovSplit cov_split(const Plan& pl, long long n, bool hermitian) {
   CovSplit sp{};
   if (n <= 0) return sp;
   long long S = std::min<long long>(kCovMaxSlices, std::max<long long>(1, (n + kCovSliceImages - 1) / kCovSliceImages));
@@ -568,29 +691,43 @@ CovSplit cov_split(const Plan& pl, long long n) {
   sp.per = per;
   sp.slices = (int)((n + per - 1) / per);
   sp.bytes_g = (size_t)sp.slices * pl.cov_size * sizeof(double);
-  sp.bytes = sp.bytes_g + (size_t)sp.slices * pl.p0 * sizeof(double);
+  sp.bytes_gi = hermitian ? sp.bytes_g : 0;
+  sp.bytes = sp.bytes_g + sp.bytes_gi + (size_t)sp.slices * pl.p0 * sizeof(double);
   return sp;
 }
 
-hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
-                             void* ws, hipStream_t st) {
-  const CovSplit sp = cov_split(pl, n);
+hipError_t launch_cov_shift(const Plan& pl, const float* coeffs, long long n, float* shift, hipStream_t st) {
+  const int m = (int)std::min<long long>(n, kCovShiftImages);
+  hipLaunchKernelGGL(k_cov_shift, dim3((unsigned)((pl.p0 + 255) / 256)), dim3(256), 0, st, coeffs, m,
+                     (long long)pl.p_half, pl.p0, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, double* Gi,
+                             const float* shift, int precision, void* ws, hipStream_t st) {
+  const bool herm = Gi != nullptr;
+  const CovSplit sp = cov_split(pl, n, herm);
   const int nitems = (int)pl.items_cov.size();
   double* partG = (double*)ws;
-  double* partS0 = (double*)((char*)ws + sp.bytes_g);
+  double* partGi = herm ? (double*)((char*)ws + sp.bytes_g) : nullptr;
+  double* partS0 = (double*)((char*)ws + sp.bytes_g + sp.bytes_gi);
   dim3 g((unsigned)(nitems * sp.slices));
   pl.prof.begin(ST_COVARIANCE, st);
-  if (precision == FB_BF16X3)
-    hipLaunchKernelGGL(k_covariance<1>, g, dim3(256), 0, st, coeffs, partG, partS0, pl.d_items_cov, pl.d_coef_off,
-                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, (long long)pl.cov_size,
-                       pl.p0);
-  else
-    hipLaunchKernelGGL(k_covariance<0>, g, dim3(256), 0, st, coeffs, partG, partS0, pl.d_items_cov, pl.d_coef_off,
-                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, (long long)pl.cov_size,
-                       pl.p0);
+#define FB_COV(P, H)                                                                                              \
+  hipLaunchKernelGGL((k_covariance<P, H>), g, dim3(256), 0, st, coeffs, partG, partS0, partGi, shift,             \
+                     pl.d_items_cov, pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, \
+                     (long long)pl.cov_size, pl.p0)
+  if (precision == FB_BF16X3) {
+    if (herm) FB_COV(1, true);
+    else FB_COV(1, false);
+  } else {
+    if (herm) FB_COV(0, true);
+    else FB_COV(0, false);
+  }
+#undef FB_COV
   const long long tot = (long long)pl.cov_size + pl.p0;
-  hipLaunchKernelGGL(k_cov_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partG, partS0, sp.slices,
-                     (long long)pl.cov_size, pl.p0, G, S0);
+  hipLaunchKernelGGL(k_cov_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partG, partS0, partGi,
+                     sp.slices, (long long)pl.cov_size, pl.p0, G, S0, Gi);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -20,8 +20,9 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
 // Eq.(1DFFT): polar samples P -> angular spectrum Fh [k][j][image] (complex).
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st);
 // Eq.(a): Fh -> coefficients [image][p_half][2].
+// weight_mode 0 multiplies the k > 0 coefficients by 2 (the +-k fold), 1 leaves them as they are
 hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs, int nimg, int precision,
-                                 hipStream_t st);
+                                 int weight_mode, hipStream_t st);
 
 // transposes
 hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
@@ -35,19 +36,24 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
 // workspace and the runs are then added into G in order.
 constexpr int kCovMaxSlices = 16;
 constexpr int kCovSliceImages = 4096;  // images per slice at least, until kCovMaxSlices
+constexpr int kCovShiftImages = 1024;  // images whose k = 0 mean becomes the shift
 struct CovSplit {
   long long per = 0;
   int slices = 0;
-  size_t bytes_g = 0;  // slices * cov_size doubles
-  size_t bytes = 0;    // + slices * p0 doubles
+  size_t bytes_g = 0;   // slices * cov_size doubles
+  size_t bytes_gi = 0;  // the same again for the imaginary parts (Hermitian form), else 0
+  size_t bytes = 0;     // + slices * p0 doubles
 };
-CovSplit cov_split(const Plan& pl, long long n);
-hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, int precision,
-                             void* ws, hipStream_t st);
+CovSplit cov_split(const Plan& pl, long long n, bool hermitian);
+// shift = mean of the k = 0 coefficients of the first min(n, kCovShiftImages) images
+hipError_t launch_cov_shift(const Plan& pl, const float* coeffs, long long n, float* shift, hipStream_t st);
+// Gi (nullable): accumulate Im(A A^*) too; shift (nullable): FP32 [p_0] subtracted from a_0
+hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, double* G, double* S0, double* Gi,
+                             const float* shift, int precision, void* ws, hipStream_t st);
 
 // Algorithm 2, steps 1 and 4 (FP64).
-hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, long long count, double* evals,
-                      double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st);
+hipError_t launch_eig(const Plan& pl, const double* G, const double* S0, const float* shift, long long count,
+                      double* evals, double* evecs, double* C_out, double* mean_out, double* work, hipStream_t st);
 size_t eig_workspace_bytes(const Plan& pl);
 
 // Steerable PCA back end (Algorithm 2 steps 5-6; Sec. V selection and shrinkage).

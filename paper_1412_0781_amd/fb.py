@@ -46,10 +46,16 @@ def _need(t: torch.Tensor, dtype, shape, what):
 
 @dataclass
 class CovState:
-    """FP64 accumulators of fb_covariance: G (packed p_k x p_k blocks), S0 (k = 0 sums), count."""
+    """Accumulators of fb_covariance: G (FP64 packed p_k x p_k blocks), S0 (FP64 k = 0 sums of
+    a_0 - shift), count; shift (FP32 [p0], filled by fb_covariance_shift from the first call's
+    coefficients unless shift_set; None: no shift) and Gi (FP64, the imaginary parts of the
+    Hermitian blocks; None: not accumulated)."""
     G: torch.Tensor
     S0: torch.Tensor
     count: int = 0
+    shift: torch.Tensor | None = None
+    Gi: torch.Tensor | None = None
+    shift_set: bool = False
 
 
 class Plan:
@@ -122,16 +128,17 @@ class Plan:
 
     # -- compute -----------------------------------------------------------
     def expand(self, images: torch.Tensor, precision="fp32", out: torch.Tensor | None = None,
-               batch: int | None = None) -> torch.Tensor:
-        """a = T* I (Algorithm 1, steps 3-4).  images float32 [n, L, L] -> float32 [n, p_half, 2]."""
+               batch: int | None = None, weight_mode: int = 1) -> torch.Tensor:
+        """a = T* I (Algorithm 1, steps 3-4).  images float32 [n, L, L] -> float32 [n, p_half, 2].
+        weight_mode 0 multiplies the k > 0 coefficients by 2 (the +-k fold weight)."""
         n = images.shape[0]
         _need(images, torch.float32, (n, self.L, self.L), "images")
         if out is None:
             out = torch.empty((n, self.p_half, 2), dtype=torch.float32, device=images.device)
         _need(out, torch.float32, (n, self.p_half, 2), "out")
         ws, wsb = self._ws_for(n, batch)
-        check(lib().fb_expand(self._h, images.data_ptr(), n, out.data_ptr(), _prec(precision), ws.data_ptr(), wsb,
-                              _stream_ptr(images.device)), self._h)
+        check(lib().fb_expand_weighted(self._h, images.data_ptr(), n, out.data_ptr(), _prec(precision),
+                                       int(weight_mode), ws.data_ptr(), wsb, _stream_ptr(images.device)), self._h)
         return out
 
     def adjoint(self, coeffs: torch.Tensor, weight_mode: int = 0, out: torch.Tensor | None = None,
@@ -206,24 +213,42 @@ class Plan:
         R, c = out.cpu().tolist()
         return int(R), c
 
-    def new_covariance(self) -> CovState:
-        return CovState(G=torch.zeros(self.cov_size, dtype=torch.float64, device=self.device),
-                        S0=torch.zeros(self.p0, dtype=torch.float64, device=self.device), count=0)
+    def new_covariance(self, shift: bool = True, hermitian: bool = False) -> CovState:
+        """Zeroed accumulators; shift=True lets the first call centre the k = 0 sums on its
+        mean, hermitian=True also accumulates the imaginary parts Gi."""
+        dev = self.device
+        return CovState(G=torch.zeros(self.cov_size, dtype=torch.float64, device=dev),
+                        S0=torch.zeros(self.p0, dtype=torch.float64, device=dev), count=0,
+                        shift=torch.zeros(self.p0, dtype=torch.float32, device=dev) if shift else None,
+                        Gi=torch.zeros(self.cov_size, dtype=torch.float64, device=dev) if hermitian else None)
 
-    def covariance(self, coeffs: torch.Tensor, state: CovState | None = None, precision="fp32") -> CovState:
-        """Accumulate G^(k) += Re(A A^*) and the k = 0 sums (Eqs.(ck),(ck_0))."""
+    def covariance(self, coeffs: torch.Tensor, state: CovState | None = None, precision="fp32",
+                   ws: torch.Tensor | None = None) -> CovState:
+        """Accumulate G^(k) += Re(A A^*), the k = 0 sums and, if the state holds Gi,
+        Gi^(k) += Im(A A^*) (Eqs.(ck),(ck_0); Eq.(cov) before the real part)."""
         n = coeffs.shape[0]
         _need(coeffs, torch.float32, (n, self.p_half, 2), "coeffs")
         if state is None:
             state = self.new_covariance()
+        if n > 0 and state.shift is not None and not state.shift_set:
+            check(lib().fb_covariance_shift(self._h, coeffs.data_ptr(), n, state.shift.data_ptr(),
+                                            _stream_ptr(coeffs.device)), self._h)
+            state.shift_set = True
         cnt = ctypes.c_int64(state.count)
-        wsb = int(lib().fb_covariance_workspace_bytes(self._h, n))
-        ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=coeffs.device)
+        wsb = int(lib().fb_covariance_workspace_bytes(self._h, n, 1 if state.Gi is not None else 0))
+        if ws is None or ws.numel() * ws.element_size() < wsb:
+            ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=coeffs.device)
         check(lib().fb_covariance(self._h, coeffs.data_ptr(), n, state.G.data_ptr(), state.S0.data_ptr(),
+                                  state.Gi.data_ptr() if state.Gi is not None else None,
+                                  state.shift.data_ptr() if state.shift is not None else None,
                                   ctypes.byref(cnt), _prec(precision), ws.data_ptr(), wsb,
                                   _stream_ptr(coeffs.device)), self._h)
         state.count = int(cnt.value)
         return state
+
+    def covariance_workspace(self, n: int, hermitian: bool = False) -> torch.Tensor:
+        wsb = int(lib().fb_covariance_workspace_bytes(self._h, int(n), 1 if hermitian else 0))
+        return torch.empty(max(wsb, 8), dtype=torch.uint8, device=self.device)
 
     def eig(self, state: CovState):
         """Finalise C^(k) and diagonalise (Algorithm 2, steps 1 and 4).
@@ -236,7 +261,8 @@ class Plan:
         mean = torch.empty(self.p0, dtype=torch.float64, device=dev)
         wsb = int(lib().fb_eig_workspace_bytes(self._h))
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-        check(lib().fb_eig(self._h, state.G.data_ptr(), state.S0.data_ptr(), state.count, evals.data_ptr(),
+        check(lib().fb_eig(self._h, state.G.data_ptr(), state.S0.data_ptr(),
+                           state.shift.data_ptr() if state.shift is not None else None, state.count, evals.data_ptr(),
                            evecs.data_ptr(), C.data_ptr(), mean.data_ptr(), ws.data_ptr(), wsb,
                            _stream_ptr(dev)), self._h)
         return evals, evecs, C, mean
@@ -394,11 +420,7 @@ class FBSynth(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        plan = ctx.plan
-        a = plan.expand(g.contiguous(), precision="fp32")
-        w = torch.full((plan.p_half, 1), 2.0, dtype=a.dtype, device=a.device)
-        w[:plan.p0] = 1.0
-        return a * w, None
+        return ctx.plan.expand(g.contiguous(), precision="fp32", weight_mode=0), None
 
 
 def fb_expand(images, plan: Plan, precision="fp32"):

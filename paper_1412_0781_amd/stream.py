@@ -2,7 +2,7 @@
 checkpoint and resume (Algorithm 2, step 1, over a dataset larger than one call).
 
 The images are produced and expanded chunk by chunk; after every chunk the FP64
-accumulators {G^(k), S0, count} and the index of the next chunk are written to a
+accumulators {G^(k), S0, the k = 0 shift, count} and the index of the next chunk are written to a
 checkpoint file (written to a temporary name, then renamed).  A run started with an
 existing checkpoint of the same configuration continues after its last chunk.  The
 accumulation order is fixed, so an interrupted and resumed run reproduces the
@@ -44,20 +44,24 @@ class ChunkFailure(RuntimeError):
     """Raised by the failure-injection hook (tests of resume)."""
 
 
-def save_checkpoint(path: str, cfg: StreamConfig, G: np.ndarray, S0: np.ndarray, count: int, next_chunk: int):
+def save_checkpoint(path: str, cfg: StreamConfig, arrays: dict, count: int, next_chunk: int):
+    """Write the named accumulator arrays, the image count and the next chunk index."""
     tmp = path + ".tmp"
     with open(tmp, "wb") as f:
-        np.savez(f, G=G, S0=S0, count=np.int64(count), next_chunk=np.int64(next_chunk),
-                 config=np.frombuffer(cfg.key().encode(), dtype=np.uint8))
+        np.savez(f, count=np.int64(count), next_chunk=np.int64(next_chunk),
+                 config=np.frombuffer(cfg.key().encode(), dtype=np.uint8),
+                 **{"acc_" + k: v for k, v in arrays.items()})
     os.replace(tmp, path)
 
 
 def load_checkpoint(path: str, cfg: StreamConfig):
+    """(arrays, count, next_chunk) of a checkpoint written for the same configuration."""
     with np.load(path, allow_pickle=False) as z:
         key = bytes(z["config"]).decode()
         if key != cfg.key():
             raise ValueError(f"checkpoint {path} was written for another configuration: {key}")
-        return z["G"].copy(), z["S0"].copy(), int(z["count"]), int(z["next_chunk"])
+        arrays = {k[4:]: z[k].copy() for k in z.files if k.startswith("acc_")}
+        return arrays, int(z["count"]), int(z["next_chunk"])
 
 
 def run_stream(cfg: StreamConfig, make_chunk, expand, accumulate, state, to_host, from_host,
@@ -66,15 +70,15 @@ def run_stream(cfg: StreamConfig, make_chunk, expand, accumulate, state, to_host
 
     make_chunk(first, m) -> images of indices first .. first+m-1
     expand(images) -> coefficients;  accumulate(coeffs, state) adds them into state
-    to_host(state) -> (G, S0, count) as numpy;  from_host(G, S0, count) -> state
+    to_host(state) -> ({name: numpy array}, count);  from_host(arrays, count) -> state
     fail_at_chunk: raise ChunkFailure after expanding that chunk, before accumulating it
     Returns the state after the last chunk.
     """
     nchunks = (cfg.n + cfg.chunk - 1) // cfg.chunk
     start = 0
     if checkpoint and os.path.exists(checkpoint):
-        G, S0, count, start = load_checkpoint(checkpoint, cfg)
-        state = from_host(G, S0, count)
+        arrays, count, start = load_checkpoint(checkpoint, cfg)
+        state = from_host(arrays, count)
         if log:
             log(f"resuming at chunk {start}/{nchunks} ({count} images accumulated)")
     for ch in range(start, nchunks):
@@ -85,8 +89,8 @@ def run_stream(cfg: StreamConfig, make_chunk, expand, accumulate, state, to_host
             raise ChunkFailure(f"injected failure at chunk {ch}")
         accumulate(a, state)
         if checkpoint:
-            G, S0, count = to_host(state)
-            save_checkpoint(checkpoint, cfg, G, S0, count, ch + 1)
+            arrays, count = to_host(state)
+            save_checkpoint(checkpoint, cfg, arrays, count, ch + 1)
         if log:
             log(f"chunk {ch + 1}/{nchunks} done ({first + m} images)")
     return state
@@ -114,10 +118,12 @@ def run_on_device(cfg: StreamConfig, checkpoint: str | None = None, fail_at_chun
         plan.covariance(a, st, precision=cfg.precision)
 
     def to_host(st):
-        return st.G.cpu().numpy(), st.S0.cpu().numpy(), st.count
+        return {"G": st.G.cpu().numpy(), "S0": st.S0.cpu().numpy(), "shift": st.shift.cpu().numpy()}, st.count
 
-    def from_host(G, S0, count):
-        return CovState(G=torch.tensor(G, device=plan.device), S0=torch.tensor(S0, device=plan.device), count=count)
+    def from_host(arrays, count):
+        return CovState(G=torch.tensor(arrays["G"], device=plan.device),
+                        S0=torch.tensor(arrays["S0"], device=plan.device), count=count,
+                        shift=torch.tensor(arrays["shift"], device=plan.device), shift_set=True)
 
     st = run_stream(cfg, make_chunk, expand, accumulate, plan.new_covariance(), to_host, from_host,
                     checkpoint=checkpoint, fail_at_chunk=fail_at_chunk, log=log)

@@ -3,6 +3,7 @@ rejects bad arguments, and its host-built plan tables (Algorithm 1, steps 1-2)
 match the oracle's: the (k, q) index tables bit for bit, the FP64 tables to
 rounding level.  No compute call is made (no GPU here)."""
 
+import ctypes
 import os
 import re
 
@@ -52,7 +53,15 @@ def test_host_plan_rejects_compute_without_device():
     assert lib.fb_expand(p._h, 1, -1, 1, 0, 1, 1 << 20, None) == -1       # n < 0
     assert lib.fb_expand(p._h, 1, 1, 1, 7, 1, 1 << 20, None) == -1        # bad precision
     assert lib.fb_expand(p._h, None, 0, None, 0, None, 0, None) == 0      # n = 0 is a no-op
-    assert lib.fb_eig(p._h, 1, 1, 0, 1, 1, None, None, 1, 1 << 20, None) == -1   # count <= 0
+    assert lib.fb_eig(p._h, 1, 1, None, 0, 1, 1, None, None, 1, 1 << 20, None) == -1   # count <= 0
+    assert lib.fb_expand_weighted(p._h, 1, 1, 1, 0, 2, 1, 1 << 20, None) == -1       # bad weight mode
+    assert lib.fb_expand_weighted(p._h, 1, 1, 1, 0, 0, 1, 1 << 20, None) == -5
+    cnt = ctypes.c_int64(0)
+    assert lib.fb_covariance(p._h, 1, 1, 1, 1, None, None, ctypes.byref(cnt), 0, 8, 1 << 20, None) == -5
+    cnt.value = -1
+    assert lib.fb_covariance(p._h, 1, 1, 1, 1, None, None, ctypes.byref(cnt), 0, 8, 1 << 20, None) == -1
+    # the imaginary parts need a second set of per-run partial sums
+    assert lib.fb_covariance_workspace_bytes(p._h, 5000, 1) > lib.fb_covariance_workspace_bytes(p._h, 5000, 0) > 0
 
 
 CONFIGS = [(8, 0.5, 4), (15, 0.5, 7.5), (32, 0.5, 16), (42, 1 / 3, 21), (121, 1 / 3, 60), (128, 0.5, 64),

@@ -113,11 +113,100 @@ def test_covariance_deterministic_and_additive():
     s2 = plan.covariance(a)
     s3 = plan.covariance(a[:350])
     plan.covariance(a[350:], s3)
+    u1 = plan.covariance(a, plan.new_covariance(shift=False))
+    u3 = plan.covariance(a[:350], plan.new_covariance(shift=False))
+    plan.covariance(a[350:], u3)
     torch.cuda.synchronize()
-    assert torch.equal(s1.G, s2.G) and torch.equal(s1.S0, s2.S0)
+    assert torch.equal(s1.G, s2.G) and torch.equal(s1.S0, s2.S0) and torch.equal(s1.shift, s2.shift)
     # splitting the images over two calls only moves FP32 partial-sum boundaries
-    assert float((s1.G - s3.G).norm() / s1.G.norm()) <= 1e-6
-    assert float((s1.S0 - s3.S0).norm() / s1.S0.norm()) <= 1e-6
+    assert float((u1.G - u3.G).norm() / u1.G.norm()) <= 1e-6
+    assert float((u1.S0 - u3.S0).norm() / u1.S0.norm()) <= 1e-6
+    # the shift of s3 comes from its first 350 images, that of s1 from the first 700: the
+    # finalised blocks and means agree all the same
+    e1, _, C1, m1 = plan.eig(s1)
+    e3, _, C3, m3 = plan.eig(s3)
+    eu, _, Cu, mu = plan.eig(u1)
+    torch.cuda.synchronize()
+    for C, m in [(C3, m3), (Cu, mu)]:
+        assert float((C1 - C).norm() / C1.norm()) <= 1e-6
+        assert float((m1 - m).norm() / m1.norm()) <= 1e-6
+    # with no shift the k = 0 sums are the plain sums
+    a0 = a[:, :plan.p0, 0].double()
+    assert float((u1.S0 - a0.sum(0)).norm() / a0.sum(0).norm()) <= 1e-6
+    assert float((s1.shift.double() + s1.S0 / 700 - a0.mean(0)).norm() / a0.mean(0).norm()) <= 1e-6
+
+
+def _mean_image_workload(po, n, seed, ratio):
+    """The workload's images plus one fixed image whose k = 0 coefficients are ratio times
+    the standard deviation of each a_{0,q} (a large mean image, as in real data)."""
+    img = structured_images(po, n, seed=seed, snr=0.1)
+    m = np.zeros((1, po.p_half), np.complex128)
+    q = np.arange(1, po.p[0] + 1)
+    m[0, :po.p[0]] = ratio * (1.0 + q) ** -1.0
+    mean_img = oracle.adjoint(m, po)[0]
+    return (img + mean_img[None]).astype(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_covariance_large_mean(precision):
+    """A mean image 10x the spread of the k = 0 coefficients: the shifted accumulation keeps
+    C^(0) and its eigenvalues within 1e-5 of the oracle in both forms (Algorithm 2 step 1
+    subtracts the mean before the products)."""
+    L, c, R, n = 32, 0.5, 16, 1000
+    print(f"[cov] large mean L={L} n={n} {precision}", flush=True)
+    po = oracle.plan(L, c, R)
+    img = _mean_image_workload(po, n, seed=4, ratio=10.0)
+    a_ref = oracle.expand(img.astype(np.float64), po)
+    mean_ref, C_ref = oracle.mean_and_covariance(a_ref, po)
+    lam_ref, _ = oracle.eig_blocks(C_ref)
+    plan = Plan(L, c, R)
+    a = plan.expand(torch.tensor(img, device="cuda"), precision=precision)
+    errs = {}
+    for shift in (True, False):
+        st = plan.new_covariance(shift=shift)
+        for s in range(0, n, 300):
+            plan.covariance(a[s:s + 300], st, precision=precision)
+        evals, _, C, mean = plan.eig(st)
+        torch.cuda.synchronize()
+        C0 = plan.blocks(C.cpu().numpy())[0]
+        lam0 = evals.cpu().numpy()[:po.p[0]]
+        errs[shift] = (rel_l2(C0, C_ref[0]), np.max(np.abs(lam0 - lam_ref[0])) / lam_ref[0][0],
+                       rel_l2(mean.cpu().numpy(), mean_ref))
+    print(f"  C^(0), lambda^(0), mean rel err: shifted {errs[True]}, unshifted {errs[False]}", flush=True)
+    assert max(errs[True]) <= TOL
+    assert np.linalg.norm(mean_ref) > 5 * np.sqrt(np.trace(C_ref[0]))  # the mean dominates
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_hermitian_covariance(precision):
+    """The imaginary parts Im(A A^*) of the rotation-only (SO(2)) covariance: (G + i Gi)/n
+    within 1e-5 of the oracle's Hermitian blocks for every k, and G bitwise the same as
+    without them."""
+    L, c, R, n = 32, 0.5, 16, 1000
+    print(f"[cov] hermitian L={L} n={n} {precision}", flush=True)
+    po = oracle.plan(L, c, R)
+    img = structured_images(po, n, seed=6, snr=0.1)
+    a_ref = oracle.expand(img.astype(np.float64), po)
+    _, CH = oracle.hermitian_covariance(a_ref, po)
+    plan = Plan(L, c, R)
+    a = plan.expand(torch.tensor(img, device="cuda"), precision=precision)
+    st = plan.new_covariance(hermitian=True)
+    plain = plan.new_covariance()
+    for s in range(0, n, 400):
+        plan.covariance(a[s:s + 400], st, precision=precision)
+        plan.covariance(a[s:s + 400], plain, precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(st.G, plain.G) and torch.equal(st.S0, plain.S0)
+    G = plan.blocks(st.G.cpu().numpy())
+    Gi = plan.blocks(st.Gi.cpu().numpy())
+    assert np.all(Gi[0] == 0.0)
+    worst = 0.0
+    for k in range(1, po.k_max + 1):
+        got = (G[k] + 1j * Gi[k]) / n
+        worst = max(worst, np.linalg.norm(got - CH[k]) / np.linalg.norm(CH[k]))
+        assert np.array_equal(Gi[k], -Gi[k].T)
+    print(f"  worst per-k Hermitian rel {worst:.3e}", flush=True)
+    assert worst <= TOL
 
 
 @pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (31, 0.5, 15.5), (64, 0.3, 32),

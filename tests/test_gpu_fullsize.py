@@ -76,12 +76,20 @@ def test_full_n_sampled(L, R, precision):
     ev = evals.cpu().numpy()
     S0 = st.S0.cpu().numpy()
     a0 = a[:, :plan.p0, 0].double().cpu().numpy()
-    # S0 sums FP32 partials of at most 256 terms: |error| <= 256 * 2^-24 * sum_i |a0_i| per q
-    assert np.all(np.abs(S0 - a0.sum(axis=0)) <= 256 * 2.0 ** -24 * np.abs(a0).sum(axis=0))
+    sh = st.shift.double().cpu().numpy()
+    d0 = (a[:, :plan.p0, 0] - st.shift[None, :]).double().cpu().numpy()  # the FP32 shifted values
+    # S0 sums FP32 partials of at most 256 terms: |error| <= 256 * 2^-24 * sum_i |a0_i - s| per q
+    assert np.all(np.abs(S0 - d0.sum(axis=0)) <= 256 * 2.0 ** -24 * np.abs(d0).sum(axis=0))
+    # the mean is shift + S0 / n, within the same partial-sum bound of the plain mean
+    m = mean.cpu().numpy()
+    assert np.allclose(sh + S0 / n, m, rtol=1e-13, atol=0)
+    assert np.all(np.abs(m - a0.mean(axis=0)) <= 256 * 2.0 ** -24 * np.abs(d0).mean(axis=0) + 1e-12 * np.abs(sh))
     for k in [0, 1, plan.k_max // 3, plan.k_max]:
         o, pk = int(plan.coef_off[k]), int(plan.p[k])
         A = a[:, o:o + pk, :].double().cpu().numpy()
         Ar, Ai = A[..., 0], (A[..., 1] if k > 0 else np.zeros_like(A[..., 1]))
+        if k == 0:
+            Ar = d0
         Gk_ref = Ar.T @ Ar + Ai.T @ Ai
         Gk = G[plan.cov_off[k]:plan.cov_off[k + 1]].reshape(pk, pk)
         e = rel_l2(Gk, Gk_ref)

@@ -24,8 +24,12 @@ def test_stream_resume_on_device(tmp_path):
     _, st = run_on_device(cfg, checkpoint=ck)
     assert st.count == ref.count == cfg.n
     assert torch.equal(st.G, ref.G) and torch.equal(st.S0, ref.S0)
+    assert torch.equal(st.shift, ref.shift)
     x = synthetic_images(plan, 0, cfg.n, cfg.seed, cfg.snr)
-    one = plan.covariance(plan.expand(x, precision=cfg.precision), precision=cfg.precision)
+    one = plan.new_covariance()
+    one.shift.copy_(ref.shift)  # the shift the chunked run took from its first chunk
+    one.shift_set = True
+    plan.covariance(plan.expand(x, precision=cfg.precision), one, precision=cfg.precision)
     torch.cuda.synchronize()
     assert float((one.G - ref.G).norm() / one.G.norm()) <= 1e-6
     assert float((one.S0 - ref.S0).norm() / one.S0.norm()) <= 1e-6

@@ -97,3 +97,35 @@ def test_eig_blocks_properties():
             i = int(np.argmax(np.abs(U[k][:, col])))
             assert U[k][i, col] > 0
         assert lam[k].min() > -1e-12               # positive semidefinite (Sec. III)
+
+
+def test_hermitian_covariance_equals_rotation_average():
+    """Average over the data augmented by rotations only (no reflections), alpha on a uniform
+    grid of M > 2 k_max angles: the augmented covariance (1/N) sum v v^* is block diagonal
+    in k and its (k, k) block is the oracle's Hermitian C_H^(k) (Sec. III, Eq.(cov) before
+    the reflection average takes the real part); for k < 0 it is the conjugate."""
+    pl = oracle.plan(12, 0.5, 6)
+    n = 6
+    rng = np.random.default_rng(21)
+    I = rng.standard_normal((n, 12, 12)) + 0.2
+    a = oracle.expand(I, pl)
+    full, ks = _full_vector(a, pl)
+    M = 2 * pl.k_max + 3
+    aug = np.concatenate([full * np.exp(-1j * ks * (2 * np.pi * m / M))[None, :] for m in range(M)], axis=0)
+    cen = aug - aug.mean(axis=0)[None, :]
+    Caug = cen.T @ cen.conj() / aug.shape[0]
+    mean0, CH = oracle.hermitian_covariance(a, pl)
+    _, C = oracle.mean_and_covariance(a, pl)
+    scale = np.abs(Caug).max()
+    for k1 in range(-pl.k_max, pl.k_max + 1):
+        for k2 in (k1 - 1, k1 + 1):
+            if abs(k2) <= pl.k_max:
+                assert np.max(np.abs(Caug[np.ix_(ks == k1, ks == k2)])) < 1e-12 * scale
+        blk = Caug[np.ix_(ks == k1, ks == k1)]
+        want = CH[abs(k1)] if k1 >= 0 else np.conj(CH[abs(k1)])
+        assert np.max(np.abs(blk - want)) < 1e-12 * scale, k1
+    # real part = the O(2) covariance; the imaginary part is antisymmetric and not zero
+    for k in range(1, pl.k_max + 1):
+        assert np.max(np.abs(CH[k].real - C[k])) < 1e-14 * scale
+        assert np.max(np.abs(CH[k].imag + CH[k].imag.T)) < 1e-15 * scale
+    assert max(np.abs(CH[k].imag).max() for k in range(1, pl.k_max + 1)) > 1e-3 * scale

@@ -38,10 +38,10 @@ def _setup(n=40, chunk=16):
         return {"G": np.zeros(cov_off[-1]), "S0": np.zeros(p[0]), "count": 0}
 
     def to_host(st):
-        return st["G"].copy(), st["S0"].copy(), st["count"]
+        return {"G": st["G"].copy(), "S0": st["S0"].copy()}, st["count"]
 
-    def from_host(G, S0, count):
-        return {"G": G.copy(), "S0": S0.copy(), "count": count}
+    def from_host(arrays, count):
+        return {"G": arrays["G"].copy(), "S0": arrays["S0"].copy(), "count": count}
 
     return cfg, po, (make_chunk, expand, accumulate), new, to_host, from_host
 
@@ -67,7 +67,8 @@ def test_interrupted_and_resumed_is_bit_identical(tmp_path):
     ck = str(tmp_path / "b.npz")
     with pytest.raises(ChunkFailure):
         run_stream(cfg, *fns, new(), to_host, from_host, checkpoint=ck, fail_at_chunk=1)
-    G, S0, count, nxt = load_checkpoint(ck, cfg)
+    arrays, count, nxt = load_checkpoint(ck, cfg)
+    assert sorted(arrays) == ["G", "S0"]
     assert (count, nxt) == (cfg.chunk, 1)
     st = run_stream(cfg, *fns, new(), to_host, from_host, checkpoint=ck)
     assert np.array_equal(st["G"], ref["G"]) and np.array_equal(st["S0"], ref["S0"])
