@@ -54,6 +54,7 @@ typedef struct fb_plan_s* fb_plan_t;
 #define FB_ERR_UNSUPPORTED (-4)        /* e.g. odd n_theta, FFT length with a prime factor > 31 */
 #define FB_ERR_NO_DEVICE (-5)          /* compute call on a plan built with fb_plan_host */
 #define FB_ERR_WORKSPACE (-6)          /* workspace too small for even one image */
+#define FB_ERR_SCRATCH_LIMIT (-7)      /* fb_expand_noalloc: a pass of 16 images exceeds its fixed scratch */
 
 /* Arithmetic of the two dense contractions (radial quadrature Eq.(a) and covariance Eq.(ck)). */
 #define FB_FP32 0    /* FP32 matrix-core products, FP32 accumulation */
@@ -130,6 +131,24 @@ int fb_expand(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int
  * FB_ERR_INVALID_ARG for a weight_mode other than 0 or 1. */
 int fb_expand_weighted(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision,
                        int weight_mode, void* ws, size_t ws_bytes, void* stream);
+
+/* fb_expand without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The pass buffers live in a fixed array of FB_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library (256 MiB: passes of 112 images at L = 256, 48 at L = 360), one copy per device,
+ * loaded with the library and held by each device it runs on until the process ends.
+ * Same arguments, layout and result as fb_expand with that array as ws; nothing is
+ * allocated (no hipMalloc, hipFree or allocating library call) and nothing needs to be
+ * cleared first (every pass writes what it later reads).  Calls on one device share that
+ * device's array: two calls that overlap in time on one device (different streams, or
+ * different host threads without ordering) race on it and give wrong results; calls
+ * ordered on one stream are safe.  The current device must be the plan's device.
+ * Errors: those of fb_expand; FB_ERR_SCRATCH_LIMIT (checked first) when one pass of 16 images
+ * does not fit the array (above about 16.7 MB of pass buffers per image, e.g. L = 1024, whose
+ * oversampled grid side is 2048); FB_ERR_INVALID_ARG also when the plan was built on another
+ * device or its per-kernel timer is enabled (the timer creates HIP events). */
+#define FB_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int fb_expand_noalloc(fb_plan_t plan, const float* images, int64_t n, float* coeffs, int precision, void* stream);
 
 /* Synthesis I = T b, the transpose of fb_expand with respect to the coefficient
  * inner product sum_q b_{0q} c_{0q} + 2 Re sum_{k>0,q} conj(b_{kq}) c_{kq}

@@ -44,6 +44,7 @@ SIGNATURES = [
     ("fb_plan_host_tables", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fb_workspace_bytes", c_size_t, [c_void_p, c_int64, c_int]),
     ("fb_expand", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
+    ("fb_expand_noalloc", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p]),
     ("fb_adjoint", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
     ("fb_expand_weighted", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_int, c_void_p, c_size_t,
                                    c_void_p]),

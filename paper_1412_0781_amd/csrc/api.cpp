@@ -8,10 +8,6 @@
 #include "kernels.h"
 #include "plan.h"
 
-struct fb_plan_s {
-  fb::Plan pl;
-};
-
 namespace {
 
 constexpr int64_t kMaxPassImages = 16384;  // gridDim.y of the per-image kernels stays far below 65535
@@ -423,6 +419,7 @@ const char* fb_error_string(int code) {
     case FB_ERR_UNSUPPORTED: return "unsupported plan parameters";
     case FB_ERR_NO_DEVICE: return "plan has no device tables";
     case FB_ERR_WORKSPACE: return "workspace too small";
+    case FB_ERR_SCRATCH_LIMIT: return "one pass of 16 images needs more than the fixed device scratch of fb_expand_noalloc";
     default: return "unknown error";
   }
 }

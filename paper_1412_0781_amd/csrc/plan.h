@@ -273,3 +273,8 @@ struct PassLayout {
 PassLayout pass_layout(const Plan& pl);
 
 }  // namespace fb
+
+// The handle behind fb_plan_t.
+struct fb_plan_s {
+  fb::Plan pl;
+};

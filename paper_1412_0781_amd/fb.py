@@ -141,6 +141,16 @@ class Plan:
                                        int(weight_mode), ws.data_ptr(), wsb, _stream_ptr(images.device)), self._h)
         return out
 
+    def expand_noalloc(self, images: torch.Tensor, out: torch.Tensor, precision="fp32") -> torch.Tensor:
+        """expand() through fb_expand_noalloc: the pass buffers are the library's fixed device
+        array, so neither the library nor this call allocates (out must be given)."""
+        n = images.shape[0]
+        _need(images, torch.float32, (n, self.L, self.L), "images")
+        _need(out, torch.float32, (n, self.p_half, 2), "out")
+        check(lib().fb_expand_noalloc(self._h, images.data_ptr(), n, out.data_ptr(), _prec(precision),
+                                      _stream_ptr(images.device)), self._h)
+        return out
+
     def adjoint(self, coeffs: torch.Tensor, weight_mode: int = 0, out: torch.Tensor | None = None,
                 batch: int | None = None, ring_filter: torch.Tensor | None = None) -> torch.Tensor:
         """I = T b: synthesis, the transpose of expand (weight_mode 0: +-k folded; 1: plain transpose).

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_error_strings():
     lib = _lib.lib()
-    for code in [0, -1, -2, -3, -4, -5, -6]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
         assert lib.fb_error_string(code)
     assert lib.fb_error_string(-1) == b"invalid argument"
 
@@ -100,3 +100,18 @@ def test_odd_n_theta_is_unsupported():
     # n_theta = ceil(16 c R) = 107 is odd: the half-ring symmetry of the kernels needs it even
     with pytest.raises(FBError, match="unsupported"):
         Plan(40, 1 / 3, 20, device=False)
+
+
+def test_noalloc_scratch_limit_and_host_plan():
+    """fb_expand_noalloc checks first that one pass of 16 images fits its fixed 256 MiB array:
+    L = 1024 (grid side 2048, 33.7 MB of pass buffers per image) does not, L = 768 (14.3 MB)
+    does and then meets the host-only plan."""
+    lib = _lib.lib()
+    big = Plan(1024, 0.5, 32, device=False)
+    assert lib.fb_expand_noalloc(big._h, 1, 1, 1, 0, None) == -7
+    assert b"scratch" in lib.fb_error_string(-7)
+    ok = Plan(768, 0.5, 32, device=False)
+    assert lib.fb_expand_noalloc(ok._h, 1, 1, 1, 0, None) == -5
+    assert lib.fb_expand_noalloc(ok._h, 1, -1, 1, 0, None) == -1     # n < 0
+    assert lib.fb_expand_noalloc(ok._h, 1, 1, 1, 5, None) == -1      # bad precision
+    assert lib.fb_expand_noalloc(None, 1, 1, 1, 0, None) == -1
