@@ -39,6 +39,7 @@ from .fb import (  # noqa: F401
     radial_quadrature,
     expand,
     expand_sparse,
+    expand_pixel_combinations,
     expand_stages,
     hermitian_covariance,
     mean_and_covariance,

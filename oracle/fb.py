@@ -251,6 +251,20 @@ def expand_sparse(pixels, pl: Plan) -> np.ndarray:
     return out
 
 
+def expand_pixel_combinations(weights: np.ndarray, rows, cols, pl: Plan) -> np.ndarray:
+    """a = T* I for the images I_i = sum_d weights[i, d] delta_d, delta_d the image with a single
+    1 at pixel (rows[d], cols[d]) and 0 elsewhere.
+
+    Every step of Algorithm 1 (Eqs.(nufft),(1DFFT),(a)) is linear in the image, so the
+    expansion of such an image is the same combination of the expansions of the delta
+    images, which `expand_sparse` evaluates term by term.  weights: real [n, D]; returns
+    complex128 [n, p_half]."""
+    weights = np.asarray(weights, dtype=np.float64)
+    deltas = [(np.array([r]), np.array([c]), np.array([1.0])) for r, c in zip(rows, cols)]
+    basis = expand_sparse(deltas, pl)                                    # [D, p_half]
+    return weights @ basis
+
+
 # ----------------------------------------------------------------------------
 # Algorithm 2, steps 1, 3, 4
 # ----------------------------------------------------------------------------

@@ -47,3 +47,30 @@ def sparse_images(L, n, npix, seed):
         dense[i, r, c] = v
         pix.append((r, c, v.astype(np.float64)))
     return dense, pix
+
+
+def max_block_rel(got, ref, coef_off):
+    """Largest relative L2 error of one angular-frequency block: max over k of
+    ||a_k - a_k,ref|| / ||a_k,ref||, each block taken over all images and q."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    worst = 0.0
+    for k in range(len(coef_off) - 1):
+        o0, o1 = int(coef_off[k]), int(coef_off[k + 1])
+        d = np.linalg.norm(got[..., o0:o1] - ref[..., o0:o1])
+        worst = max(worst, float(d / np.linalg.norm(ref[..., o0:o1])))
+    return worst
+
+
+def dictionary_images(L, n, D, seed, offset=0.0):
+    """n float32 images that combine D pixels of a fixed random dictionary: image i holds
+    V[i, d] at pixel (rows[d], cols[d]) and 0 elsewhere, V ~ N(offset, 1) rounded to float32
+    (offset > 0 gives a large mean image).  numpy's seeded generator; host only.  Returns the
+    dense images, V (float64 copy of the float32 values), rows and cols."""
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(L * L, size=D, replace=False)
+    rows, cols = flat // L, flat % L
+    V = (rng.standard_normal((n, D)) + offset).astype(np.float32)
+    dense = np.zeros((n, L, L), np.float32)
+    dense[:, rows, cols] = V
+    return dense, V.astype(np.float64), rows, cols

@@ -9,8 +9,13 @@
   N(0,1) noise images and compared with the oracle; the covariance blocks of sampled k are
   compared with an FP64 host recomputation from the library's own coefficients, and their
   eigenvalues with LAPACK on the library's finalised blocks.
-Tolerances: 1e-5 relative L2 (coefficients per image, covariance blocks); the k = 0
-sums within the FP32 partial-sum bound; eigenvalues 1e-9 of the block's largest.
+* End to end at L = 256 against the FP64 oracle: 4000 images that combine a dictionary of
+  192 pixels (their oracle coefficients are the same combination of the oracle expansions
+  of the 192 single-pixel images), with a k = 0 mean far above the spread: coefficients,
+  every C^(k), the mean and every eigenvalue, in both forms.
+Tolerances: 1e-5 relative L2 (coefficients per image and per k block, covariance blocks);
+the k = 0 sums within the FP32 partial-sum bound; eigenvalues 1e-9 of the block's largest
+against LAPACK on the same blocks, 1e-5 against the oracle's.
 """
 
 import numpy as np
@@ -18,7 +23,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import as_complex, rel_l2, sparse_images
+from gpu_util import as_complex, dictionary_images, max_block_rel, rel_l2, sparse_images
 from paper_1412_0781_amd import Plan
 from paper_1412_0781_amd.fb import synth_normals
 
@@ -45,6 +50,9 @@ def test_l360_shape_matches_oracle(precision):
         e = rel_l2(got[i], ref[i])
         print(f"  image {i}: rel-L2 {e:.3e}", flush=True)
         assert e <= TOL
+    blk = max_block_rel(got, ref, po.coef_off)
+    print(f"  worst k block {blk:.3e}", flush=True)
+    assert blk <= TOL
     assert np.all(got[:, :po.p[0]].imag == 0.0)
 
 
@@ -66,6 +74,9 @@ def test_full_n_sampled(L, R, precision):
         e = rel_l2(got[i], ref[i])
         print(f"  image {j}: rel-L2 {e:.3e}", flush=True)
         assert e <= TOL
+    blk = max_block_rel(got, ref, po.coef_off)
+    print(f"  worst k block {blk:.3e}", flush=True)
+    assert blk <= TOL
 
     st = plan.covariance(a, precision=precision)
     evals, evecs, C, mean = plan.eig(st)
@@ -99,6 +110,50 @@ def test_full_n_sampled(L, R, precision):
         lam_ref = np.sort(np.linalg.eigvalsh(Ck))[::-1]
         lam = ev[o:o + pk]
         assert np.abs(lam - lam_ref).max() <= 1e-9 * abs(lam_ref[0])
+
+
+@pytest.fixture(scope="module")
+def c3_dictionary():
+    """The L = 256, R = 128 shape: 4000 images combining 192 dictionary pixels with values
+    N(3, 1) (a mean image far above the spread), and their FP64 oracle coefficients, the
+    covariance blocks and eigenvalues (Algorithm 2, steps 1 and 4) from those coefficients."""
+    L, c, R, n, D = 256, 0.5, 128.0, 4000, 192
+    po = oracle.plan(L, c, R)
+    dense, V, rows, cols = dictionary_images(L, n, D, seed=21, offset=3.0)
+    a_ref = oracle.expand_pixel_combinations(V, rows, cols, po)
+    mean_ref, C_ref = oracle.mean_and_covariance(a_ref, po)
+    lam_ref, _ = oracle.eig_blocks(C_ref)
+    return po, dense, a_ref, mean_ref, C_ref, lam_ref
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_c3_covariance_and_eigenvalues_against_oracle(c3_dictionary, precision):
+    """End to end at L = 256: coefficients (whole and per k block), every C^(k) (relative
+    Frobenius, max over k), the k = 0 mean and every eigenvalue (per block, relative to the
+    block's largest) against the FP64 oracle's, for images whose k = 0 mean dominates."""
+    po, dense, a_ref, mean_ref, C_ref, lam_ref = c3_dictionary
+    print(f"[fullsize] C3 dictionary n={dense.shape[0]} {precision}", flush=True)
+    plan = Plan(po.L, po.c, po.R)
+    x = torch.tensor(dense, device="cuda")
+    a = plan.expand(x, precision=precision)
+    st = plan.new_covariance()
+    for s0 in range(0, x.shape[0], 1500):
+        plan.covariance(a[s0:s0 + 1500], st, precision=precision)
+    evals, _, C, mean = plan.eig(st)
+    torch.cuda.synchronize()
+    got = as_complex(a)
+    e_a, e_blk = rel_l2(got, a_ref), max_block_rel(got, a_ref, po.coef_off)
+    Cb = plan.blocks(C.cpu().numpy())
+    e_C = max(rel_l2(Cb[k], C_ref[k]) for k in range(po.k_max + 1))
+    ev = evals.cpu().numpy()
+    e_lam = max(np.max(np.abs(ev[po.coef_off[k]:po.coef_off[k + 1]] - lam_ref[k])) / lam_ref[k][0]
+                for k in range(po.k_max + 1))
+    e_m = rel_l2(mean.cpu().numpy(), mean_ref)
+    print(f"  coefficients {e_a:.3e} (worst k block {e_blk:.3e}); C^(k) max over k {e_C:.3e}; "
+          f"eigenvalues {e_lam:.3e}; mean {e_m:.3e}", flush=True)
+    assert np.linalg.norm(mean_ref) > 3 * np.sqrt(np.trace(C_ref[0]))  # the mean dominates
+    assert e_a <= TOL and e_blk <= TOL
+    assert e_C <= TOL and e_lam <= TOL and e_m <= TOL
 
 
 def test_l360_eig_two_sided_form():

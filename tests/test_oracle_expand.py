@@ -154,6 +154,23 @@ def test_sparse_evaluation_matches_dense(L):
     assert np.linalg.norm(a_sparse - a_dense) <= 1e-12 * np.linalg.norm(a_dense)
 
 
+def test_pixel_combinations_match_dense_expansion():
+    # images built from a pixel dictionary: the combination of the delta expansions equals the
+    # dense evaluation of the same images (Algorithm 1 is linear in the image)
+    L = 24
+    po = oracle.plan(L, 0.5, L / 2)
+    rng = np.random.default_rng(8)
+    D, n = 10, 4
+    flat = rng.choice(L * L, size=D, replace=False)
+    rows, cols = flat // L, flat % L
+    V = rng.standard_normal((n, D)) + 2.0
+    dense = np.zeros((n, L, L))
+    dense[:, rows, cols] = V
+    a = oracle.expand_pixel_combinations(V, rows, cols, po)
+    ref = oracle.expand(dense, po)
+    assert np.linalg.norm(a - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_single_pixel_closed_form():
     # one unit pixel at (x0, y0): F(xi, theta) = exp(-2 pi i xi (x0 cos theta + y0 sin theta))
     L = 20
