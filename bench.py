@@ -31,11 +31,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "images/s (FB coeffs + covariance) at L=256, BF16x3 vs FP32, ≤1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA on the vector ALUs without packed (two-wide) FP32 instructions, which this
-# library does not emit: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.  (The
-# published 157.3 TFLOP/s counts the packed FMA.)
-ALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-ALU_FP32_PUBLISHED_TFLOPS = 157.3
+# Published MI355X peaks: FP32 vector (and FP32 matrix) 157.3 TFLOP/s, dense BF16 matrix
+# 2.5 PFLOP/s.  The library emits no packed (two-wide) FP32 instructions, so its vector
+# FP32 code can issue at most half the published rate: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flop x 2.4 GHz = 78.6 TFLOP/s, reported beside the published-peak fraction.
+FP32_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+ALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # LDS read rate of ds_read_b128 measured on the device (a plain read loop): the practical
 # limit of the gather, whose every tap is one 16-byte LDS read per lane
 LDS_MEASURED_TBS = 116.0
@@ -71,10 +73,75 @@ def algorithmic_bytes_per_image(plan) -> dict:
 
 
 def algorithmic_flops_per_image(plan) -> dict:
-    """Vector-ALU flops of the separable W x W interpolation (the gather): per polar node and
-    image, W rows of W complex-by-real products plus W row combinations, as FMAs."""
-    W = plan.kernel_w
-    return {"fwd_gather": plan.n_xi * (plan.n_theta // 2) * (2 * W * W + 2 * W) * 2}
+    """Textbook flops per image of each stage (the counts of the method's work, not of this
+    implementation's instructions):
+      2-D FFT of the N x N oversampled grid   2.5 N^2 log2(N^2)   (shared by rows and columns
+                                                                   in proportion to their transforms)
+      interpolation (gather)                  4 w^2 per polar node of the half rings
+      angular FFT                             5 H log2 H per ring (complex FFT of length H = n_theta/2)
+      radial quadrature Eq.(a)                4 n_xi sum_{k>0} p_k + 2 n_xi p_0
+      covariance Eq.(ck)                      4 sum_k p_k^2"""
+    W, N, H = plan.kernel_w, plan.grid_n, plan.n_theta // 2
+    M2 = N // 2 + 2 * (W // 2 + 1) + 1
+    fft2 = 2.5 * N * N * math.log2(N * N)
+    rows_share = (plan.L / 2) / (plan.L / 2 + M2)  # row-pair transforms vs column transforms
+    p = [int(x) for x in plan.p]
+    return {
+        "fwd_rows": fft2 * rows_share,
+        "fwd_cols": fft2 * (1 - rows_share),
+        "fwd_gather": 4 * W * W * plan.n_xi * H,
+        "fwd_angular": plan.n_xi * 5 * H * math.log2(H),
+        "radial_fwd": 4 * plan.n_xi * sum(p[1:]) + 2 * plan.n_xi * p[0],
+        "covariance": 4 * sum(x * x for x in p),
+    }
+
+
+def stage_peak_tflops(stage: str, precision: str) -> float:
+    """Peak of the unit that does a stage's arithmetic: the matrix cores for the two
+    contractions (BF16 at three products per FP32 product in the BF16x3 form), the FP32
+    vector units otherwise."""
+    if stage in ("radial_fwd", "covariance") and precision == "bf16x3":
+        return BF16_MFMA_PEAK_TFLOPS / 3.0
+    return FP32_PEAK_TFLOPS
+
+
+def step_roofline(plan, precision: str, stages: dict, images: int, step_ms: float, n: int) -> dict:
+    """Whole-step roofline: sum over stages of max(bytes / HBM peak, flops / peak) per image,
+    divided by the measured time per image; also each stage's own fraction (its bound over
+    its measured average time per image) and the bound of a fully fused path, which moves
+    only the image and its coefficients through HBM."""
+    bpi = algorithmic_bytes_per_image(plan)
+    fpi = algorithmic_flops_per_image(plan)
+    bound = 0.0
+    per_stage = {}
+    for st, b in bpi.items():
+        t = max(b / (HBM_PEAK_GBS * 1e9), fpi[st] / (stage_peak_tflops(st, precision) * 1e12))
+        bound += t
+        if st in stages and stages[st]["launches"]:
+            meas = stages[st]["total_ms"] * 1e-3 / images
+            per_stage[st] = round(t / meas, 4)
+    measured = step_ms * 1e-3 / n  # `images` = images over all timed steps, n = images per step
+    irreducible = 4 * plan.L * plan.L + 8 * plan.p_half
+    fused = max(irreducible / (HBM_PEAK_GBS * 1e9),
+                sum(fpi[st] / (stage_peak_tflops(st, precision) * 1e12) for st in fpi))
+    return {"bound_us_per_image": round(bound * 1e6, 4), "measured_us_per_image": round(measured * 1e6, 4),
+            "frac": round(bound / measured, 4), "fused_bound_us_per_image": round(fused * 1e6, 4),
+            "fused_frac": round(fused / measured, 4), "stage_frac": per_stage,
+            "mflop_per_image": round(sum(fpi.values()) / 1e6, 2),
+            "unfused_MB_per_image": round(sum(bpi.values()) / 1e6, 3),
+            "irreducible_MB_per_image": round(irreducible / 1e6, 3)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def source_digest() -> str:
@@ -190,8 +257,55 @@ def cpu_baseline(plan_args, sample, seed, snr):
     oracle.mean_and_covariance(coef, po)
     dt = time.perf_counter() - t0
     return img, coef, po, {"value": sample / dt, "unit": "images/s", "cores": int(cores), "kind": "oracle",
+                           "cpu": cpu_model(),
                            "sample": f"{sample} images of the same workload (L={L}, R={R}, c={c}), "
-                                     f"expansion + covariance in FP64, {dt:.1f} s"}
+                                     f"expansion + covariance in FP64, {dt:.1f} s (bounded to about half a "
+                                     f"minute of host time)"}
+
+
+def dictionary_accuracy(plan, po, n, D, precisions, seed=21, offset=3.0):
+    """Error of every result against the FP64 oracle at the benchmark's shape: n images that
+    combine D random pixels with values N(offset, 1) (a dominant mean image), whose oracle
+    coefficients are the same combination of the oracle expansions of the D single-pixel
+    images; coefficients (whole and worst k block), C^(k) (relative Frobenius, max over k),
+    the eigenvalues (per block, relative to the block's largest) and the k = 0 mean."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    L = po.L
+    flat = rng.choice(L * L, size=D, replace=False)
+    rows, cols = flat // L, flat % L
+    V = (rng.standard_normal((n, D)) + offset).astype(np.float32)
+    log(f"accuracy: oracle expansion of {D} single-pixel images (L={L}) on the host")
+    a_ref = oracle.expand_pixel_combinations(V.astype(np.float64), rows, cols, po)
+    mean_ref, C_ref = oracle.mean_and_covariance(a_ref, po)
+    lam_ref, _ = oracle.eig_blocks(C_ref)
+    dense = np.zeros((n, L, L), np.float32)
+    dense[:, rows, cols] = V
+    x = torch.tensor(dense, device=plan.device)
+    out = {}
+    off = po.coef_off
+    for prec in precisions:
+        a = plan.expand(x, precision=prec)
+        st = plan.covariance(a, precision=prec)
+        evals, _, C, mean = plan.eig(st)
+        torch.cuda.synchronize()
+        g = a.cpu().numpy().astype(np.float64)
+        g = g[..., 0] + 1j * g[..., 1]
+        blk = max(np.linalg.norm(g[:, off[k]:off[k + 1]] - a_ref[:, off[k]:off[k + 1]])
+                  / np.linalg.norm(a_ref[:, off[k]:off[k + 1]]) for k in range(po.k_max + 1))
+        Cb = plan.blocks(C.cpu().numpy())
+        eC = max(np.linalg.norm(Cb[k] - C_ref[k]) / np.linalg.norm(C_ref[k]) for k in range(po.k_max + 1))
+        ev = evals.cpu().numpy()
+        el = max(np.max(np.abs(ev[off[k]:off[k + 1]] - lam_ref[k])) / lam_ref[k][0] for k in range(po.k_max + 1))
+        out[prec] = {"coeff_rel_l2": float(np.linalg.norm(g - a_ref) / np.linalg.norm(a_ref)),
+                     "coeff_worst_k_block": float(blk), "cov_max_over_k": float(eC), "eigenvalue_max": float(el),
+                     "mean_rel_l2": float(np.linalg.norm(mean.cpu().numpy() - mean_ref) / np.linalg.norm(mean_ref)),
+                     "sample": f"{n} images combining {D} pixels, values N({offset:g}, 1)"}
+    return out
 
 
 def main():
@@ -206,6 +320,9 @@ def main():
     ap.add_argument("--pass-images", type=int, default=2048)
     ap.add_argument("--forms", default="fp32,bf16x3")
     ap.add_argument("--cpu-sample", type=int, default=8)
+    ap.add_argument("--dict-images", type=int, default=2000,
+                    help="images of the pixel-dictionary accuracy check (0 skips it)")
+    ap.add_argument("--dict-pixels", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (calibrates HBM byte counters) and exit")
@@ -337,9 +454,10 @@ def main():
                "c": round(c_est, 4), "workload": "CTF-filtered synthesis, support R=L/2, SNR 1/2"}
     log(f"support estimate: {support}")
 
-    # per-kernel figures of the headline form; dominant kernel against the HBM roofline
+    # per-kernel figures of the headline form; dominant kernel against its roofline
     prof = profs[head]
     bpi = algorithmic_bytes_per_image(plan)
+    fpi = algorithmic_flops_per_image(plan)
     stages = {}
     for name, (ms, cnt) in prof.items():
         stages[name] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / max(cnt, 1)}
@@ -348,27 +466,44 @@ def main():
     sec = stages[dom]["avg_ms"] * 1e-3
     alg_bytes = bpi[dom] * per_launch_images
     hbm_achieved = alg_bytes / sec / 1e9
-    fpi = algorithmic_flops_per_image(plan)
     tpi = stored_traffic_per_image(dom, L)
     traffic = round(tpi * per_launch_images) if tpi is not None else None
     flops = fpi.get(dom, 0) * per_launch_images
-    if flops / alg_bytes > (ALU_FP32_PEAK_TFLOPS * 1e12) / (HBM_PEAK_GBS * 1e9):
-        # arithmetic intensity above the ridge point: bound by the FP32 vector ALUs
+    peak = stage_peak_tflops(dom, head)
+    if flops / alg_bytes > (peak * 1e12) / (HBM_PEAK_GBS * 1e9):
+        # arithmetic intensity above the ridge point: bound by the arithmetic units
         ach = flops / sec / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": round(ALU_FP32_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(ach / ALU_FP32_PEAK_TFLOPS, 4), "traffic": traffic,
-                    "flops_per_launch": int(flops), "frac_of_published_fp32_peak": round(ach / ALU_FP32_PUBLISHED_TFLOPS, 4),
-                    "hbm_algorithmic_GBps": round(hbm_achieved, 1), "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
+        mfma = dom in ("radial_fwd", "covariance")
+        roofline = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": round(ach, 2),
+                    "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
+                    "flops_per_launch": int(flops), "hbm_algorithmic_GBps": round(hbm_achieved, 1),
+                    "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
+        if not mfma:
+            roofline["frac_of_nonpacked_fp32_issue_rate"] = round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)
         if dom == "fwd_gather":
             # W x W taps per node and image pair, one 16-byte LDS read each (8 bytes per image)
             lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
             roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
             roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
     else:
+        # arithmetic intensity below the ridge point: the attainable rate is set by HBM
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+        if flops:
+            ach = flops / sec / 1e12
+            roofline.update({"flops_per_launch": int(flops), "flop_rate_TFLOPs": round(ach, 2),
+                             "flop_frac_of_published_peak": round(ach / peak, 4),
+                             "frac_of_nonpacked_fp32_issue_rate": round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)})
+        if dom == "fwd_gather":
+            lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
+            roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
+            roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
     roofline.update({"bytes_per_launch": int(alg_bytes), "images_per_launch": round(per_launch_images, 1),
                      "avg_launch_ms": round(stages[dom]["avg_ms"], 4)})
+    step = {prec: step_roofline(plan, prec, {k: {"total_ms": v[0], "launches": v[1]} for k, v in profs[prec].items()},
+                                args.n * args.steps, forms[prec]["ms_per_step"], args.n)
+            for prec in forms}
+    log(f"step roofline: {step}")
 
     # accuracy on a host-generated sample, and the CPU oracle baseline
     accuracy = None
@@ -380,8 +515,14 @@ def main():
         for prec in forms:
             got = plan.expand(xs, precision=prec).cpu().numpy().astype(np.float64)
             gc = got[..., 0] + 1j * got[..., 1]
-            accuracy[prec] = float(np.linalg.norm(gc - coef_ref) / np.linalg.norm(coef_ref))
+            accuracy[prec] = {"coeff_rel_l2_workload_sample": float(np.linalg.norm(gc - coef_ref)
+                                                                    / np.linalg.norm(coef_ref))}
         log(f"coefficient rel-L2 vs FP64 oracle on the sample: {accuracy}")
+        if args.dict_images > 0:
+            dict_acc = dictionary_accuracy(plan, po, args.dict_images, args.dict_pixels, list(forms))
+            for prec, d in dict_acc.items():
+                accuracy[prec].update(d)
+            log(f"accuracy vs FP64 oracle (pixel-dictionary images): {accuracy}")
 
     f = forms[head]
     out = {
@@ -413,6 +554,7 @@ def main():
         "support_estimate": support,
         "plan_s": round(plan_s, 2),
         "roofline": roofline,
+        "step_roofline": step,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -13,4 +13,9 @@ __device__ __forceinline__ int xcd_remap(int lin, int total) {
   return x * q + min(x, r) + (lin >> 3);
 }
 
+// Workgroup barrier that waits only for this wave's LDS operations, not for its global
+// loads: loads issued for a later stage stay in flight across it.  Only LDS data may be
+// exchanged through it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 }  // namespace fb

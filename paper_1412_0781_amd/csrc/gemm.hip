@@ -75,6 +75,10 @@ __device__ __forceinline__ void mma_bf16x3(const unsigned short (*Ah)[LDH], cons
 // A wave owns 32 rows x 64 columns (two 32x32 MFMA tiles).  The next K chunk is
 // loaded into registers while the current one is multiplied from LDS; the output
 // tile is transposed through LDS so that each image's rows are written as one run.
+// The K loop starts at the chunk holding ring jmin[k]: on the rings before it every table
+// entry of block k is below 2^-30 of its row's largest (J_k far below its turning point),
+// and the angular step does not write F-hat there.  The workgroup barriers wait for LDS
+// operations only, so the F-hat loads issued ahead stay in flight across them.
 // ---------------------------------------------------------------------------
 constexpr int RBM = 128, RBN = 64, RBK = 32;
 constexpr int RLDH = RBK + 8;
@@ -87,15 +91,15 @@ constexpr int RLDH = RBK + 8;
 __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict__ tab, const float* __restrict__ Fh,
                                                         float* __restrict__ coeffs, const GemmItem* __restrict__ items,
                                                         const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                        int n_xi, int nxp, int nk, int ncol, long long p_half,
-    int weight_mode) {
+                                                        const int* __restrict__ jmin, int n_xi, int nxp, int nk,
+                                                        int ncol, long long p_half, int weight_mode) {
   union Smem {
     float Bs[RBK][RBN + 4];      // F-hat chunk, [j][column]
     float Cs[RBN / 2][RBM + 4];  // half of the output tile, [column][row]
   };
   __shared__ __attribute__((aligned(16))) Smem S;
   const GemmItem it = items[blockIdx.x];
-  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
+  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k], jm = jmin[k];
   const int n0 = blockIdx.y * RBN;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6, hf = lane >> 5;
   const bool live = m0 + wm * 32 < pk;  // uniform over the wave
@@ -121,12 +125,13 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
     for (int u = 0; u < 2; ++u) {
       const int kc = k0 + 2 * jp + u;
       const float* src = fk + (size_t)kc * nk * (2 * kImgGroup);
-      if (kc < n_xi && col + 3 < ncol) {
+      const bool ring = kc >= jm && kc < n_xi;  // rings before jmin[k] hold no F-hat for this k
+      if (ring && col + 3 < ncol) {
         dst[u] = *(const float4*)src;
       } else {
         float t[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] = (kc < n_xi && col + e < ncol) ? src[e] : 0.f;
+        for (int e = 0; e < 4; ++e) t[e] = (ring && col + e < ncol) ? src[e] : 0.f;
         dst[u] = make_float4(t[0], t[1], t[2], t[3]);
       }
     }
@@ -137,12 +142,13 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
   };
   f32x16 acc0 = {}, acc1 = {};
   const int nch = nxp / RBK;
-  load_b(0, b1);
-  load_a(0);
+  const int cb = jm / RBK;  // the chunks before the one holding ring jmin[k] add nothing
+  load_b(cb * RBK, b1);
+  load_a(cb * RBK);
   lstore();
-  if (1 < nch) load_b(RBK, b1);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
+  if (cb + 1 < nch) load_b((cb + 1) * RBK, b1);
+  lds_barrier();
+  for (int c = cb; c < nch; ++c) {
     if (c + 2 < nch) load_b((c + 2) * RBK, b2);
     if (live) {
       const float av[16] = {a_cu[0].x, a_cu[0].y, a_cu[0].z, a_cu[0].w, a_cu[1].x, a_cu[1].y, a_cu[1].z, a_cu[1].w,
@@ -155,12 +161,12 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
       }
     }
     if (c + 1 < nch) load_a((c + 1) * RBK);
-    __syncthreads();
+    lds_barrier();
     if (c + 1 < nch) {
       lstore();
       b1[0] = b2[0];
       b1[1] = b2[1];
-      __syncthreads();
+      lds_barrier();
     }
   }
   // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
   auto emit = [&](const f32x16& acc, int half) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
-    __syncthreads();
+    lds_barrier();
     const int c0 = n0 + 32 * half;
     const int nimg_t = max(0, min(32, ncol - c0)) / 2;
     for (int i = tid; i < nimg_t * nrow; i += 256) {
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
     }
   };
   emit(acc0, 0);
-  __syncthreads();
+  lds_barrier();
   emit(acc1, 1);
 }
 
@@ -196,8 +202,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
                                                        const float* __restrict__ Fh, float* __restrict__ coeffs,
                                                        const GemmItem* __restrict__ items,
                                                        const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                       int n_xi, int nxp, int nk, int ncol, long long p_half,
-    int weight_mode) {
+                                                       const int* __restrict__ jmin, int n_xi, int nxp, int nk,
+                                                       int ncol, long long p_half, int weight_mode) {
   union Smem {
     struct {
       unsigned int Bh[RBN][RLDH / 2], Bl[RBN][RLDH / 2];  // [column][j / 2], two BF16 per word
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   };
   __shared__ __attribute__((aligned(16))) Smem S;
   const GemmItem it = items[blockIdx.x];
-  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k];
+  const int k = it.k, m0 = it.t0, pk = p[k], off = coef_off[k], jm = jmin[k];
   const int n0 = blockIdx.y * RBN;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
   const bool live = m0 + wm * 32 < pk;  // uniform over the wave
@@ -239,12 +245,13 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
     for (int u = 0; u < 2; ++u) {
       const int kc = k0 + 2 * jp + u;
       const float* src = fk + (size_t)kc * nk * (2 * kImgGroup);
-      if (kc < n_xi && col + 3 < ncol) {
+      const bool ring = kc >= jm && kc < n_xi;  // rings before jmin[k] hold no F-hat for this k
+      if (ring && col + 3 < ncol) {
         dst[u] = *(const float4*)src;
       } else {
         float t[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] = (kc < n_xi && col + e < ncol) ? src[e] : 0.f;
+        for (int e = 0; e < 4; ++e) t[e] = (ring && col + e < ncol) ? src[e] : 0.f;
         dst[u] = make_float4(t[0], t[1], t[2], t[3]);
       }
     }
@@ -262,14 +269,15 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   };
   f32x16 acc0 = {}, acc1 = {};
   const int nch = nxp / RBK;
-  load_b(0, b1);
-  load_a(0);
+  const int cb = jm / RBK;  // the chunks before the one holding ring jmin[k] add nothing
+  load_b(cb * RBK, b1);
+  load_a(cb * RBK);
   lstore();
-  if (1 < nch) load_b(RBK, b1);
-  __syncthreads();
+  if (cb + 1 < nch) load_b((cb + 1) * RBK, b1);
+  lds_barrier();
   const unsigned short* Bh = (const unsigned short*)&S.b.Bh[0][0];
   const unsigned short* Bl = (const unsigned short*)&S.b.Bl[0][0];
-  for (int c = 0; c < nch; ++c) {
+  for (int c = cb; c < nch; ++c) {
     if (c + 2 < nch) load_b((c + 2) * RBK, b2);
     if (live) {
 #pragma unroll
@@ -287,12 +295,12 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
       }
     }
     if (c + 1 < nch) load_a((c + 1) * RBK);
-    __syncthreads();
+    lds_barrier();
     if (c + 1 < nch) {
       lstore();
       b1[0] = b2[0];
       b1[1] = b2[1];
-      __syncthreads();
+      lds_barrier();
     }
   }
   // the 128 x 64 tile leaves through LDS in two halves of 32 columns: Cs[column][row]
@@ -301,7 +309,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
   auto emit = [&](const f32x16& acc, int half) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) S.Cs[lane & 31][wm * 32 + acc_row(i, lane)] = acc[i];
-    __syncthreads();
+    lds_barrier();
     const int c0 = n0 + 32 * half;
     const int nimg_t = max(0, min(32, ncol - c0)) / 2;
     for (int i = tid; i < nimg_t * nrow; i += 256) {
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
     }
   };
   emit(acc0, 0);
-  __syncthreads();
+  lds_barrier();
   emit(acc1, 1);
 }
 
@@ -658,14 +666,15 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
   dim3 g((unsigned)pl.items_fwd.size(), (unsigned)((ncol + RBN - 1) / RBN));
   const int nk = pl.k_max + 1;
   pl.prof.begin(ST_RADIAL_FWD, st);
-  if (precision == FB_BF16X3)
+  if (precision == FB_BF16X3) {
     hipLaunchKernelGGL(k_radial_fwd_b3, g, dim3(256), 0, st, pl.d_radial_bf, (const float*)Fh, coeffs,
-                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half,
-                       weight_mode);
-  else
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.d_jmin, pl.n_xi, pl.n_xi_pad, nk, ncol,
+                       (long long)pl.p_half, weight_mode);
+  } else {
     hipLaunchKernelGGL(k_radial_fwd_f32, g, dim3(256), 0, st, pl.d_radial_pad, (const float*)Fh, coeffs,
-                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.n_xi, pl.n_xi_pad, nk, ncol, (long long)pl.p_half,
-                       weight_mode);
+                       pl.d_items_fwd, pl.d_coef_off, pl.d_p, pl.d_jmin, pl.n_xi, pl.n_xi_pad, nk, ncol,
+                       (long long)pl.p_half, weight_mode);
+  }
   pl.prof.end(st);
   return hipGetLastError();
 }

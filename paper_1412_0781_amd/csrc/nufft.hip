@@ -506,7 +506,8 @@ constexpr int kAngStreamH = 512;  // largest angular half length of the streamin
 template <int NC>
 __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __restrict__ P, float2* __restrict__ Fh,
                                                              FftDesc fd, const float2* __restrict__ tw,
-                                                             const float2* __restrict__ angtw, int n_xi, int K,
+                                                             const float2* __restrict__ angtw,
+                                                             const int* __restrict__ kring, int n_xi, int K,
                                                              int ngrp, int U, float scale) {
   constexpr int G = kImgGroup;
   constexpr int PF = kAngStreamH * G / 2 / 1024;  // (m, gg) items per thread at H = 512
@@ -556,7 +557,9 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
     const int j = u / ngrp, grp = u - j * ngrp;
     const int gg = tid & (G - 1);
     float2* dst = Fh + (((size_t)grp * n_xi + j) * (K + 1)) * G + gg;
-    for (int k = tid / G; k <= K; k += nthr / G) {
+    // only the k whose radial sums read ring j (the table of every larger k is negligible there)
+    const int Kj = kring[j];
+    for (int k = tid / G; k <= Kj; k += nthr / G) {
       float2 zk = s_buf[gg * S + fpad(k)];
       float2 zc = cconj(s_buf[gg * S + fpad(k == 0 ? 0 : H - k)]);
       // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
@@ -1290,7 +1293,7 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
     const int U = fixed_units(pl, units, 2, kAngularUnits);
     pl.prof.begin(ST_FWD_ANGULAR, st);
     FB_LAUNCH_POW2(k_fwd_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, P,
-                       Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, ngrp, U, scale);
+                       Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.d_kring, pl.n_xi, pl.k_max, ngrp, U, scale);
     pl.prof.end(st);
     return hipGetLastError();
   }

@@ -114,6 +114,22 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     for (auto& x : th) x.join();
   }
 
+  // rings each block's radial sum needs (the rest of each row is below kRadialNegligible of
+  // the row's largest entry), and per ring the largest k that reads it
+  pl.jmin.assign(pl.k_max + 1, pl.n_xi);
+  for (int k = 0; k <= pl.k_max; ++k)
+    for (int q = 0; q < pl.p[k]; ++q) {
+      const double* r = &pl.radial[(size_t)(pl.coef_off[k] + q) * pl.n_xi];
+      double m = 0.0;
+      for (int j = 0; j < pl.n_xi; ++j) m = std::max(m, std::fabs(r[j]));
+      int j = 0;
+      while (j < pl.n_xi && !(std::fabs(r[j]) >= kRadialNegligible * m)) ++j;
+      pl.jmin[k] = std::min(pl.jmin[k], j);
+    }
+  pl.kring.assign(pl.n_xi, -1);
+  for (int k = 0; k <= pl.k_max; ++k)
+    for (int j = pl.jmin[k]; j < pl.n_xi; ++j) pl.kring[j] = std::max(pl.kring[j], k);
+
   // Non-uniform FFT: oversampled grid N >= 2L (2,3,5-smooth), kernel width 7, and the
   // kernel shape beta = 0.97 pi (1 - 1/(2 sigma)) w for oversampling sigma = N / L.
   pl.N = next_smooth_235(2 * L);
@@ -482,6 +498,8 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_items_adj, pl.items_adj.data(), pl.items_adj.size()));
   FB_HIP_TRY(upload(&pl.d_items_cov, pl.items_cov.data(), pl.items_cov.size()));
   FB_HIP_TRY(upload(&pl.d_items_spca, pl.items_spca.data(), pl.items_spca.size()));
+  FB_HIP_TRY(upload(&pl.d_jmin, pl.jmin.data(), pl.jmin.size()));
+  FB_HIP_TRY(upload(&pl.d_kring, pl.kring.data(), pl.kring.size()));
   pl.has_device = true;
   return FB_OK;
 }
@@ -491,7 +509,8 @@ void free_device(Plan& pl) {
   void* ptrs[] = {pl.d_radial,    pl.d_radial_bf, pl.d_radial_pad, pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
-                  pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca};
+                  pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca,
+                  pl.d_jmin,      pl.d_kring};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
@@ -515,6 +534,7 @@ void free_device(Plan& pl) {
   pl.d_sseg = nullptr;
   pl.d_sent = nullptr;
   pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = pl.d_items_spca = nullptr;
+  pl.d_jmin = pl.d_kring = nullptr;
   pl.has_device = false;
 }
 

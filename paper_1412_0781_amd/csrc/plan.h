@@ -174,6 +174,11 @@ struct Profiler {
 
 constexpr int kRadialRows = 128;  // row tile of the radial quadrature GEMM
 constexpr int kRadialK = 32;      // K chunk of the radial quadrature GEMM (rows of the BF16 table padded to it)
+// Radial table entries below this fraction of their row's largest entry are treated as zero:
+// J_k(x) decays faster than exponentially for x below its turning point x ~ k, so for large k
+// the inner rings add nothing an FP32 sum can hold (the dropped terms of a row sum to less
+// than n_xi 2^-30 of its largest term).
+constexpr double kRadialNegligible = 1.0 / (1u << 30);
 
 struct GemmItem {  // one (k, tile) work item of a grouped GEMM
   int k;
@@ -220,6 +225,10 @@ struct Plan {
   std::vector<int> sseg;
   std::vector<SpreadLocal> sent;
   std::vector<GemmItem> items_fwd, items_adj, items_cov, items_spca;
+  // rings the radial sum of block k reads: j >= jmin[k] (the first ring where some row of
+  // block k reaches kRadialNegligible of its largest entry); kring[j] = the largest k with
+  // jmin[k] <= j (-1 if none): the angular step writes F-hat(j, k) for k <= kring[j] only
+  std::vector<int> jmin, kring;
   int bm = 64, bn = 64;            // GEMM tile
 
   mutable Profiler prof;
@@ -256,6 +265,8 @@ struct Plan {
   GemmItem* d_items_adj = nullptr;
   GemmItem* d_items_cov = nullptr;
   GemmItem* d_items_spca = nullptr;   // (k, 64-wide column tile) of the steerable-PCA products
+  int* d_jmin = nullptr;              // k_max + 1
+  int* d_kring = nullptr;             // n_xi
 };
 
 // Build host tables; returns FB_OK or an FB_ERR_* code.
