@@ -42,9 +42,6 @@ ALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # limit of the gather, whose every tap is one 16-byte LDS read per lane
 LDS_MEASURED_TBS = 116.0
 PROFILES = os.path.join(ROOT, "profiles")
-# sources whose change invalidates stored HBM counter readings of the forward kernels
-KERNEL_SOURCES = ["paper_1412_0781_amd/csrc/" + f for f in
-                  ("nufft.hip", "fft_dev.h", "dev_common.h", "plan.h", "plan.cpp", "gemm.hip", "api.cpp")]
 
 
 def log(msg):
@@ -144,15 +141,6 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def source_digest() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic_per_image(stage: str, L: int):
     """HBM bytes per image of `stage` from the committed counter summary (rocprofv3 FETCH_SIZE /
     WRITE_SIZE, scaled by the plain-copy calibration), or None if the kernel sources changed
@@ -166,6 +154,7 @@ def stored_traffic_per_image(stage: str, L: int):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+    from paper_1412_0781_amd.prof_summary import source_digest
     if kv.get("source_digest") != source_digest():
         return None
     try:

@@ -378,7 +378,10 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
 // grid: work items (k, 64-row tile m0, 64-column tile n0 >= m0) x S image slices.
 // The K dimension is (image, re/im): X[q][2i + r] = (Re, Im) a^i_{kq}, so
 // Re(A A^*) = X X^T.  A K chunk is 16 images = 32 columns; the next chunk is held in
-// registers while the current one is multiplied.  FP32 tile sums are moved to FP64
+// registers while the current one is multiplied (the workgroup barriers wait for LDS
+// operations only, so those loads stay in flight across them).  In the BF16x3 form each
+// thread stores the hi and lo parts of four consecutive images of its row as two 16-byte
+// runs, which keeps the 64 rows' stores free of LDS bank conflicts.  FP32 tile sums are moved to FP64
 // registers every COV_FLUSH_COLS columns; each block writes its FP64 tile (and the
 // mirrored tile) into its slice's partial copy of G, which k_cov_reduce then adds
 // into G in slice order, so the result does not depend on scheduling.
@@ -482,7 +485,8 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   const bool do_sum = (k == 0 && diag);
   const long long i0 = (long long)slice * per, i1 = min(n, i0 + per);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  // loader: thread owns row q = tid & 63 of the tile for images (tid >> 6) + 4u, u < 4
+  // loader: thread owns row q = tid & 63 of the tile for the four consecutive images
+  // 4 (tid >> 6) + u, u < 4, of each chunk (one 16-byte LDS store per operand in the BF16x3 form)
   const int q = tid & 63, ib = tid >> 6;
   const bool rowa = m0 + q < pk, rowb = n0 + q < pk;
   const float2* srcA = (const float2*)coeffs + off + m0 + q;
@@ -492,11 +496,15 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   // k = 0 rows enter shifted (rows past p_0 and images past the run stay exactly zero)
   const float sha = (k0 && shift && rowa) ? shift[m0 + q] : 0.f;
   const float shb = (k0 && shift && rowb) ? shift[n0 + q] : 0.f;
-  float2 ra[4], rb[4];
-  auto gload = [&](long long c0) {
+  struct Regs {
+    float2 a[4], b[4];
+  };
+  auto gload = [&](long long c0, Regs& R) {
+    float2* ra = R.a;
+    float2* rb = R.b;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      long long img = c0 + ib + 4 * u;
+      long long img = c0 + 4 * ib + u;
       bool ok = img < i1;
       ra[u] = (ok && rowa) ? srcA[img * p_half] : make_float2(0.f, 0.f);
       if (!diag) rb[u] = (ok && rowb) ? srcB[img * p_half] : make_float2(0.f, 0.f);
@@ -509,28 +517,40 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
     }
   };
   float ssum = 0.f;
-  auto lstore = [&]() {
+  auto lstore = [&](const Regs& R) {
+    const float2* ra = R.a;
+    const float2* rb = R.b;
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int col = 2 * (ib + 4 * u);
-      if (do_sum) ssum += ra[u].x;
-      if constexpr (PREC == 0) {
+      for (int u = 0; u < 4; ++u) {
+        const int col = 2 * (4 * ib + u);
+        if (do_sum) ssum += ra[u].x;
         S.As[col][q] = ra[u].x;
         S.As[col + 1][q] = ra[u].y;
         if (!diag) {
           S.Bs[col][q] = rb[u].x;
           S.Bs[col + 1][q] = rb[u].y;
         }
-      } else {
-        unsigned h, l;
-        split_bf16_pair(ra[u].x, ra[u].y, h, l);
-        *(unsigned*)&S.Ah[q][col] = h;
-        *(unsigned*)&S.Al[q][col] = l;
-        if (!diag) {
-          split_bf16_pair(rb[u].x, rb[u].y, h, l);
-          *(unsigned*)&S.Bh[q][col] = h;
-          *(unsigned*)&S.Bl[q][col] = l;
-        }
+      }
+    } else {
+      // columns 8 ib .. 8 ib + 7 of row q: four (re, im) pairs, hi and lo, 16 bytes each
+      uint4 h4, l4, hb, lb;
+      unsigned* h = (unsigned*)&h4;
+      unsigned* l = (unsigned*)&l4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (do_sum) ssum += ra[u].x;
+        split_bf16_pair(ra[u].x, ra[u].y, h[u], l[u]);
+      }
+      *(uint4*)&S.Ah[q][8 * ib] = h4;
+      *(uint4*)&S.Al[q][8 * ib] = l4;
+      if (!diag) {
+        unsigned* h2 = (unsigned*)&hb;
+        unsigned* l2 = (unsigned*)&lb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) split_bf16_pair(rb[u].x, rb[u].y, h2[u], l2[u]);
+        *(uint4*)&S.Bh[q][8 * ib] = hb;
+        *(uint4*)&S.Bl[q][8 * ib] = lb;
       }
     }
   };
@@ -544,11 +564,12 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   }
   double dsum = 0.0;
   int since_flush = 0;
-  gload(i0);
-  for (long long c0 = i0; c0 < i1; c0 += COV_IMG) {
-    lstore();
-    __syncthreads();
-    if (c0 + COV_IMG < i1) gload(c0 + COV_IMG);
+  // chunk c0 is staged from R, then the loads of the next chunk go into R and stay in flight
+  // through the products (the barriers wait for LDS operations only)
+  auto step = [&](long long c0, Regs& R) {
+    lstore(R);
+    lds_barrier();
+    if (c0 + COV_IMG < i1) gload(c0 + COV_IMG, R);
     if constexpr (PREC == 0) {
       mma_f32_k32(S.As, diag ? S.As : S.Bs, acc, wm, wn, lane);
       if (HERM && im) mma_f32_k32_im(S.As, diag ? S.As : S.Bs, acc_im, wm, wn, lane);
@@ -558,7 +579,7 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
       else
         mma_bf16x3_cov<HERM>(S.Ah, S.Al, S.Bh, S.Bl, acc, acc_im, im, wm, wn, lane);
     }
-    __syncthreads();
+    lds_barrier();
     since_flush += COV_K;
     if (since_flush >= COV_FLUSH_COLS) {
 #pragma unroll
@@ -577,7 +598,10 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
       ssum = 0.f;
       since_flush = 0;
     }
-  }
+  };
+  Regs R0;
+  gload(i0, R0);
+  for (long long c0 = i0; c0 < i1; c0 += COV_IMG) step(c0, R0);
 #pragma unroll
   for (int i = 0; i < 16; ++i) dacc[i] += (double)acc[i];
   if constexpr (HERM) {
