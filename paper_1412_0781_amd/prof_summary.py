@@ -44,6 +44,7 @@ STAGES = {
     "covariance": ("k_covariance", "k_cov_reduce"),
 }
 SIMDS = 256 * 4  # MI355X: 256 compute units of 4 SIMDs
+XCDS = 8         # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs (each counts the same busy cycles)
 
 
 def source_digest() -> str:
@@ -114,14 +115,15 @@ def cmd_trace(a):
             print(f"  {name:44s} grid={g:>10d} dispatches={len(d):5d} avg_ms={sum(d) / len(d):9.4f}")
 
 
-def _counter_table(dirpath: str):
-    """{kernel: {counter: [values per dispatch of the largest grid]}}"""
+def _counter_table(dirpath: str, ours: bool = True):
+    """{kernel: (grid, dispatches, {counter: mean value per dispatch of the largest grid})}; ours:
+    this library's kernels only (names k_*)"""
     rows = _csv(dirpath, "_counter_collection.csv")
     per = defaultdict(lambda: defaultdict(dict))  # kernel -> dispatch -> counter -> value
     grid = {}
     for r in rows:
         name = _short(r["Kernel_Name"])
-        if not name.startswith("k_"):
+        if ours and not name.startswith("k_"):
             continue
         d = r.get("Dispatch_Id", r.get("Correlation_Id"))
         per[name][d][r["Counter_Name"]] = per[name][d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
@@ -140,8 +142,8 @@ def _counter_table(dirpath: str):
 
 def cmd_calib(a):
     nbytes_kib = a.gib * (1 << 20)
-    f = _counter_table(a.fetch)
-    w = _counter_table(a.write)
+    f = _counter_table(a.fetch, ours=False)
+    w = _counter_table(a.write, ours=False)
 
     def total(t, c):
         # the copy is the only large dispatch: take the kernel with the largest counter value
@@ -222,14 +224,21 @@ def cmd_counters(a):
     print()
     head = f"{'kernel':44s} {'disp':>5s} " + " ".join(f"{c:>28s}" for c in counters)
     mfma = "SQ_VALU_MFMA_BUSY_CYCLES" in counters and "GRBM_GUI_ACTIVE" in counters
+    mops = [c for c in counters if c.startswith("SQ_INSTS_VALU_MFMA_MOPS_")]
     if mfma:
         head += f" {'MFMA_busy_%':>12s}"
+    if mops:
+        head += f" {'MFMA_GFLOP':>11s}"
     print(head)
     for name in sorted(t, key=lambda n: -max(t[n][2].values(), default=0.0)):
         g, nd, v = t[name]
         line = f"{name:44s} {nd:5d} " + " ".join(f"{v.get(c, 0.0):28.1f}" for c in counters)
         if mfma and v.get("GRBM_GUI_ACTIVE", 0.0) > 0:
-            line += f" {100.0 * v['SQ_VALU_MFMA_BUSY_CYCLES'] / (v['GRBM_GUI_ACTIVE'] * SIMDS):12.2f}"
+            # busy cycles summed over all SIMDs / (the kernel's active cycles x SIMDs)
+            line += f" {100.0 * v['SQ_VALU_MFMA_BUSY_CYCLES'] / (v['GRBM_GUI_ACTIVE'] / XCDS * SIMDS):12.2f}"
+        if mops:
+            # each MOPS count is 512 flops
+            line += f" {sum(v.get(c, 0.0) for c in mops) * 512 / 1e9:11.2f}"
         print(line)
 
 
