@@ -73,7 +73,7 @@ typedef struct fb_info {
   int64_t cov_size;   /* sum_k p_k^2: doubles in a packed covariance / eigenvector array */
   int32_t grid_n;     /* side of the oversampled Cartesian grid of the non-uniform FFT */
   int32_t kernel_w;   /* spreading kernel width, in grid points */
-  double kernel_beta; /* shape parameter of the exp(beta(sqrt(1-z^2)-1)) kernel */
+  double kernel_beta; /* shape of the Kaiser-Bessel kernel I_0(beta sqrt(1-z^2)) / I_0(beta) */
   int32_t has_device; /* 1 for fb_plan, 0 for fb_plan_host */
 } fb_info;
 

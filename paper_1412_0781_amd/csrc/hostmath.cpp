@@ -133,19 +133,37 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
-double es_kernel(double z, double beta) {
-  if (std::fabs(z) > 1.0) return 0.0;
-  return std::exp(beta * (std::sqrt(1.0 - z * z) - 1.0));
+double bessel_i0(double x) {
+  // sum_{m >= 0} ((x/2)^m / m!)^2: every term positive, so the sum loses nothing to cancellation
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int m = 1; m < 1000; ++m) {
+    term *= q / ((double)m * (double)m);
+    sum += term;
+    if (term <= 1e-17 * sum) break;
+  }
+  return sum;
 }
 
-double es_kernel_ft(double t, int w, double beta) {
-  static thread_local std::vector<double> gx, gw;
-  const int nq = 400;
-  if ((int)gx.size() != nq) gauss_legendre(nq, gx, gw);
+double kb_kernel(double z, double beta) {
+  if (std::fabs(z) > 1.0) return 0.0;
+  return bessel_i0(beta * std::sqrt(1.0 - z * z)) / bessel_i0(beta);
+}
+
+double kb_kernel_ft(double t, int w, double beta) {
+  // int_{-1}^{1} I_0(beta sqrt(1 - z^2)) cos(a z) dz = 2 sinh(s) / s, s = sqrt(beta^2 - a^2)
+  // (2 sin(s) / s with s = sqrt(a^2 - beta^2) once a > beta), here a = pi w t
   const double pi = 3.14159265358979323846;
-  double s = 0.0;
-  for (int i = 0; i < nq; ++i) s += gw[i] * es_kernel(gx[i], beta) * std::cos(pi * w * gx[i] * t);
-  return 0.5 * w * s;
+  const double a = pi * w * t;
+  const double d = beta * beta - a * a;
+  double f;
+  if (std::fabs(d) < 1e-12)
+    f = 2.0;
+  else if (d > 0.0)
+    f = 2.0 * std::sinh(std::sqrt(d)) / std::sqrt(d);
+  else
+    f = 2.0 * std::sin(std::sqrt(-d)) / std::sqrt(-d);
+  return 0.5 * w * f / bessel_i0(beta);
 }
 
 int next_smooth_235(int m) {

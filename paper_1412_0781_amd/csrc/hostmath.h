@@ -24,16 +24,20 @@ std::vector<std::vector<double>> bessel_zeros_upto(double bound);
 // method on the three-term Legendre recurrence.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
-// Spreading kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1, 0 outside
-// ("exponential of semicircle", Barnett, Magland, af Klinteberg, SIAM J. Sci.
-// Comput. 41 (2019)).  In grid units u the kernel is phi(2u / w).
-double es_kernel(double z, double beta);
+// Modified Bessel function I_0(x), x >= 0, by its power series.
+double bessel_i0(double x);
 
-// Its Fourier transform in grid units:
+// Spreading kernel: the Kaiser-Bessel window phi(z) = I_0(beta sqrt(1 - z^2)) / I_0(beta) on
+// |z| <= 1, 0 outside (Jackson, Meyer, Nishimura, Macovski, IEEE Trans. Med. Imaging 10 (1991);
+// shape beta of Beatty, Nishimura, Pauly, IEEE Trans. Med. Imaging 24 (2005)).  In grid units u
+// the kernel is phi(2u / w).
+double kb_kernel(double z, double beta);
+
+// Its Fourier transform in grid units, in closed form:
 //   phi_hat(t) = int_{-w/2}^{w/2} phi(2u/w) exp(-2 pi i u t) du
-//              = (w/2) int_{-1}^{1} phi(z) cos(pi w z t) dz,
-// by Gauss-Legendre quadrature.
-double es_kernel_ft(double t, int w, double beta);
+//              = (w/2) int_{-1}^{1} phi(z) cos(pi w z t) dz
+//              = w sinh(sqrt(beta^2 - (pi w t)^2)) / (sqrt(beta^2 - (pi w t)^2) I_0(beta)).
+double kb_kernel_ft(double t, int w, double beta);
 
 // Smallest n >= m that factors into 2, 3 and 5 only.
 int next_smooth_235(int m);

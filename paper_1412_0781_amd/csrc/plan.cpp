@@ -130,20 +130,20 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
   for (int k = 0; k <= pl.k_max; ++k)
     for (int j = pl.jmin[k]; j < pl.n_xi; ++j) pl.kring[j] = std::max(pl.kring[j], k);
 
-  // Non-uniform FFT: oversampled grid N >= 2L (2,3,5-smooth), kernel width 7, and the
-  // kernel shape beta = 0.97 pi (1 - 1/(2 sigma)) w for oversampling sigma = N / L.
+  // Non-uniform FFT: oversampled grid N >= 2L (2,3,5-smooth), Kaiser-Bessel kernel of width 7
+  // with the shape beta = pi sqrt((w / sigma)^2 (sigma - 1/2)^2 - 0.8) for oversampling sigma = N / L.
   pl.N = next_smooth_235(2 * L);
   if (pl.N % 2) pl.N = next_smooth_235(pl.N + 1);
   pl.w = 7;
   double sigma = (double)pl.N / L;
-  pl.beta = 0.97 * kPi * (1.0 - 1.0 / (2.0 * sigma)) * pl.w;
+  pl.beta = kPi * std::sqrt((pl.w / sigma) * (pl.w / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
   pl.hw = pl.w / 2 + 1;
   pl.M2 = pl.N / 2 + 2 * pl.hw + 1;
   pl.H = pl.n_theta / 2;
 
   int x0 = -(int)std::ceil((L - 1) / 2.0);
   pl.deconv.resize(L);
-  for (int a = 0; a < L; ++a) pl.deconv[a] = 1.0 / es_kernel_ft((double)(x0 + a) / pl.N, pl.w, pl.beta);
+  for (int a = 0; a < L; ++a) pl.deconv[a] = 1.0 / kb_kernel_ft((double)(x0 + a) / pl.N, pl.w, pl.beta);
 
   // polar half-ring nodes theta_l = 2 pi l / n_theta, l < n_theta / 2
   if (pl.n_xi > 65535 || pl.H > 65535) return FB_ERR_UNSUPPORTED;  // node records hold 16-bit j, l
@@ -206,8 +206,8 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
             g.l = (unsigned short)l;
             g.off = (t.b2 - cy * CS) * BW + (t.b1 - cx * CS);
             for (int a2 = 0; a2 < pl.w; ++a2) {
-              g.w1[a2] = (float)es_kernel(2.0 * (t1 - (b1 + a2)) / pl.w, pl.beta);
-              g.w2[a2] = (float)es_kernel(2.0 * (t2 - (b2 + a2)) / pl.w, pl.beta);
+              g.w1[a2] = (float)kb_kernel(2.0 * (t1 - (b1 + a2)) / pl.w, pl.beta);
+              g.w2[a2] = (float)kb_kernel(2.0 * (t2 - (b2 + a2)) / pl.w, pl.beta);
             }
             pl.gnodes.push_back(g);
           }
@@ -249,10 +249,10 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
         int b1 = (int)std::ceil(t1 - pl.w / 2.0), b2 = (int)std::ceil(t2 - pl.w / 2.0);
         for (int bb = 0; bb < pl.w; ++bb) {
           int m2 = b2 + bb;
-          double w2 = es_kernel(2.0 * (t2 - m2) / pl.w, pl.beta);
+          double w2 = kb_kernel(2.0 * (t2 - m2) / pl.w, pl.beta);
           for (int a = 0; a < pl.w; ++a) {
             int m1 = b1 + a;
-            double om = 0.5 * w2 * es_kernel(2.0 * (t1 - m1) / pl.w, pl.beta);
+            double om = 0.5 * w2 * kb_kernel(2.0 * (t1 - m1) / pl.w, pl.beta);
             int m1p = ((m1 % N) + N) % N;
             if (m2 >= 0 && m2 <= N / 2) fn((size_t)m2 * N + m1p, (uint32_t)n, (float)om);
             if (m2 <= 0 || m2 >= N / 2) {
