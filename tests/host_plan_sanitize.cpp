@@ -1,0 +1,83 @@
+// Host-side plan construction under AddressSanitizer and UndefinedBehaviorSanitizer.
+//
+// Built by tests/test_host_sanitizers.py with g++ -fsanitize=address,undefined from the
+// library's plan.cpp and hostmath.cpp (host code only; no HIP call is made): builds the
+// plans of several shapes and rejects the invalid ones, and checks the FP64 host numerics
+// against values they must reproduce.  Any memory error or undefined behaviour aborts the
+// run; a wrong value makes it exit non-zero.
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "hostmath.h"
+#include "plan.h"
+
+namespace fb {
+// upload_plan references these kernel set-up calls; no device work is done here
+hipError_t configure_kernels() { return hipSuccess; }
+hipError_t configure_eig_kernels() { return hipSuccess; }
+hipError_t configure_svd_kernels() { return hipSuccess; }
+}  // namespace fb
+
+static int failures = 0;
+static void check(bool ok, const char* what) {
+  if (!ok) {
+    std::printf("FAIL: %s\n", what);
+    ++failures;
+  }
+}
+
+int main() {
+  struct Shape {
+    int L;
+    double c, R;
+    int want;
+  };
+  const Shape shapes[] = {
+      {8, 0.5, 4, FB_OK},      {16, 0.5, 8, FB_OK},      {31, 0.5, 15.5, FB_OK},   {24, 0.375, 12, FB_OK},
+      {64, 0.3, 32, FB_OK},    {128, 0.5, 64, FB_OK},    {256, 0.5, 128, FB_OK},   {1024, 0.5, 32, FB_OK},
+      {1, 0.5, 0.5, FB_ERR_INVALID_ARG}, {32, 0.6, 16, FB_ERR_INVALID_ARG}, {32, 0.5, 17, FB_ERR_INVALID_ARG},
+      {4, 0.5, 0.5, FB_ERR_INVALID_ARG},
+  };
+  for (const Shape& s : shapes) {
+    fb::Plan pl;
+    const int rc = fb::build_host_plan(s.L, s.c, s.R, pl);
+    std::printf("plan L=%d c=%g R=%g: rc %d", s.L, s.c, s.R, rc);
+    if (rc == FB_OK) {
+      std::printf(" n_xi %d n_theta %d k_max %d p_half %lld grid %d\n", pl.n_xi, pl.n_theta, pl.k_max,
+                  (long long)pl.p_half, pl.N);
+      check(pl.coef_off.back() == pl.p_half, "coefficient offsets end at p_half");
+      check((int)pl.jmin.size() == pl.k_max + 1 && (int)pl.kring.size() == pl.n_xi, "ring tables sized");
+      bool ok = true;
+      for (int k = 0; k <= pl.k_max; ++k) ok = ok && pl.jmin[k] >= 0 && pl.jmin[k] < pl.n_xi;
+      check(ok, "every block reads at least one ring");
+    } else {
+      std::printf("\n");
+    }
+    check(rc == s.want, "plan return code");
+  }
+
+  // I_0 at tabulated points (Abramowitz and Stegun, Table 9.8)
+  check(std::fabs(fb::bessel_i0(1.0) - 1.266065877752008) < 1e-14, "I_0(1)");
+  check(std::fabs(fb::bessel_i0(10.0) / 2815.716628466254 - 1.0) < 1e-13, "I_0(10)");
+  // the closed-form kernel transform against a Gauss-Legendre quadrature of the kernel
+  std::vector<double> x, w;
+  fb::gauss_legendre(200, x, w);
+  double wsum = 0.0;
+  for (double v : w) wsum += v;
+  check(std::fabs(wsum - 2.0) < 1e-13, "Gauss-Legendre weights sum to 2");
+  const double beta = 16.25, pi = 3.14159265358979323846;
+  for (double t : {0.0, 0.1, 0.25, 0.5, 1.0}) {
+    double q = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) q += w[i] * fb::kb_kernel(x[i], beta) * std::cos(pi * 7 * x[i] * t);
+    q *= 3.5;
+    const double f = fb::kb_kernel_ft(t, 7, beta);
+    check(std::fabs(q - f) <= 1e-9 * std::fabs(fb::kb_kernel_ft(0.0, 7, beta)), "kernel transform");
+  }
+  // the zeros of J_0 below 8 (2.4048, 5.5201; the next is 8.6537) and the first of J_1
+  const auto z = fb::bessel_zeros_upto(8.0);
+  check(z.size() >= 2 && z[0].size() == 2 && std::fabs(z[0][0] - 2.404825557695773) < 1e-12, "zeros of J_0");
+  check(z.size() >= 2 && std::fabs(z[1][0] - 3.831705970207512) < 1e-12, "first zero of J_1");
+  std::printf("%d failure(s)\n", failures);
+  return failures ? 1 : 0;
+}
