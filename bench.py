@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the Fourier-Bessel expansion + steerable covariance on one MI355X.
 
-Workload (the headline configuration): n = 100 000 synthetic cryo-EM-shaped
-images, L = 256, support radius R = 128, band limit c = 1/2.  Each image is the
-synthesis T a of random Fourier-Bessel coefficients with variance
-(1+q)^-2 (1+|k|)^-1 plus white Gaussian noise at SNR 1/20, generated on the
-device from seed 0 (Philox-4x32-10) before timing starts; inputs are resident
-in HBM when the timed region starts.
+Default workload (the headline configuration, --workload c3): n = 100 000 synthetic
+cryo-EM-shaped images, L = 256, support radius R = 128, band limit c = 1/2.  Each image is
+the synthesis T a of random Fourier-Bessel coefficients with variance (1+q)^-2 (1+|k|)^-1
+plus white Gaussian noise at SNR 1/20, generated on the device from seed 0
+(Philox-4x32-10) before timing starts; inputs are resident in HBM when the timed region
+starts.
 
-One step = the whole hot path over all n images: fb_expand (polar NUFFT,
-angular FFT, radial quadrature) then fb_covariance (G^(k) += Re(A A^*), k = 0
-sums).  Both arithmetic forms are timed, FP32 and split-BF16x3; `value` is the
-BF16x3 form.  The plan (tables) and the eigendecomposition are outside the
-timed region (the eigendecomposition is timed on its own and reported).
+One step = the whole hot path over all n images: fb_expand (polar NUFFT, angular FFT,
+radial quadrature) then fb_covariance (G^(k) += Re(A A^*), k = 0 sums).  Both arithmetic
+forms are timed, FP32 and split-BF16x3; `value` is the BF16x3 form.  The plan (tables) and
+the eigendecomposition are outside the timed region (the eigendecomposition is timed on
+its own and reported).
+
+Other workloads (not the headline line):
+  --workload c2  n = 100 000, L = 128, R = 64, SNR 1/20, resident; value = the FP32 form
+  --workload c4  differentiation: n = 20 000, L = 128, forward expansion, fixed Wiener-like
+                 shrinkage, adjoint synthesis and the backward pass of both (autograd);
+                 value = images/s of forward + backward, FP32
+  --workload c5  L = 360, R = 180, SNR 1/50, images generated on the device chunk by chunk
+                 (16 384 per chunk) and the covariance accumulated across chunks; value =
+                 images/s of expansion + covariance (generation untimed).  --n sets the
+                 images streamed (default two chunks; 500 000 is the whole set)
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -43,6 +53,19 @@ ALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 LDS_MEASURED_TBS = 116.0
 PROFILES = os.path.join(ROOT, "profiles")
 
+# workload -> defaults (kind: resident = all images in HBM, stream = generated chunk by
+# chunk, autograd = forward + backward of the differentiation workload)
+WORKLOADS = {
+    "c3": {"L": 256, "n": 100000, "snr": 1 / 20, "cpu_sample": 8, "head": "bf16x3", "kind": "resident",
+           "forms": "fp32,bf16x3", "dict_images": 2000, "dict_pixels": 128},
+    "c2": {"L": 128, "n": 100000, "snr": 1 / 20, "cpu_sample": 48, "head": "fp32", "kind": "resident",
+           "forms": "fp32,bf16x3", "dict_images": 2000, "dict_pixels": 128},
+    "c4": {"L": 128, "n": 20000, "snr": 1 / 20, "cpu_sample": 16, "head": "fp32", "kind": "autograd",
+           "forms": "fp32", "dict_images": 0, "dict_pixels": 0},
+    "c5": {"L": 360, "n": 2 * 16384, "snr": 1 / 50, "cpu_sample": 4, "head": "bf16x3", "kind": "stream",
+           "forms": "fp32,bf16x3", "dict_images": 1000, "dict_pixels": 64, "chunk": 16384},
+}
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -59,6 +82,8 @@ def algorithmic_bytes_per_image(plan) -> dict:
     P = c8 * plan.n_xi * H
     fh = c8 * (plan.k_max + 1) * plan.n_xi
     co = c8 * plan.p_half
+    y = c8 * (N // 2 + 1) * N        # folded half-plane grid of the adjoint
+    y1 = c8 * (N // 2 + 1) * L       # adjoint column-pass output
     return {
         "fwd_rows": img + g1,
         "fwd_cols": g1 + g,
@@ -66,6 +91,11 @@ def algorithmic_bytes_per_image(plan) -> dict:
         "fwd_angular": P + fh,
         "radial_fwd": fh + co,
         "covariance": co,
+        "radial_adj": co + fh,
+        "adj_angular": fh + P,
+        "adj_spread": P + y,
+        "adj_cols": y + y1,
+        "adj_rows": y1 + img,
     }
 
 
@@ -74,22 +104,30 @@ def algorithmic_flops_per_image(plan) -> dict:
     implementation's instructions):
       2-D FFT of the N x N oversampled grid   2.5 N^2 log2(N^2)   (shared by rows and columns
                                                                    in proportion to their transforms)
-      interpolation (gather)                  4 w^2 per polar node of the half rings
+      interpolation (gather, spread)          4 w^2 per polar node of the half rings
       angular FFT                             5 H log2 H per ring (complex FFT of length H = n_theta/2)
-      radial quadrature Eq.(a)                4 n_xi sum_{k>0} p_k + 2 n_xi p_0
+      radial quadrature Eq.(a), its transpose 4 n_xi sum_{k>0} p_k + 2 n_xi p_0
       covariance Eq.(ck)                      4 sum_k p_k^2"""
     W, N, H = plan.kernel_w, plan.grid_n, plan.n_theta // 2
     M2 = N // 2 + 2 * (W // 2 + 1) + 1
     fft2 = 2.5 * N * N * math.log2(N * N)
     rows_share = (plan.L / 2) / (plan.L / 2 + M2)  # row-pair transforms vs column transforms
     p = [int(x) for x in plan.p]
+    radial = 4 * plan.n_xi * sum(p[1:]) + 2 * plan.n_xi * p[0]
+    ang = plan.n_xi * 5 * H * math.log2(H)
+    gather = 4 * W * W * plan.n_xi * H
     return {
         "fwd_rows": fft2 * rows_share,
         "fwd_cols": fft2 * (1 - rows_share),
-        "fwd_gather": 4 * W * W * plan.n_xi * H,
-        "fwd_angular": plan.n_xi * 5 * H * math.log2(H),
-        "radial_fwd": 4 * plan.n_xi * sum(p[1:]) + 2 * plan.n_xi * p[0],
+        "fwd_gather": gather,
+        "fwd_angular": ang,
+        "radial_fwd": radial,
         "covariance": 4 * sum(x * x for x in p),
+        "radial_adj": radial,
+        "adj_angular": ang,
+        "adj_spread": gather,
+        "adj_cols": fft2 * (1 - rows_share),
+        "adj_rows": fft2 * rows_share,
     }
 
 
@@ -103,30 +141,75 @@ def stage_peak_tflops(stage: str, precision: str) -> float:
 
 
 def step_roofline(plan, precision: str, stages: dict, images: int, step_ms: float, n: int) -> dict:
-    """Whole-step roofline: sum over stages of max(bytes / HBM peak, flops / peak) per image,
-    divided by the measured time per image; also each stage's own fraction (its bound over
-    its measured average time per image) and the bound of a fully fused path, which moves
-    only the image and its coefficients through HBM."""
+    """Whole-step roofline: sum over the step's stages of max(bytes / HBM peak, flops / peak)
+    per image, divided by the measured time per image; also each stage's own fraction (its
+    bound over its measured average time per image) and the bound of a fully fused path,
+    which moves only the image and its coefficients through HBM.  `images` = images over all
+    timed steps (the stage totals' span), n = images per step."""
     bpi = algorithmic_bytes_per_image(plan)
     fpi = algorithmic_flops_per_image(plan)
     bound = 0.0
     per_stage = {}
-    for st, b in bpi.items():
-        t = max(b / (HBM_PEAK_GBS * 1e9), fpi[st] / (stage_peak_tflops(st, precision) * 1e12))
+    present = [st for st in bpi if st in stages and stages[st]["launches"]]
+    for st in present:
+        t = max(bpi[st] / (HBM_PEAK_GBS * 1e9), fpi[st] / (stage_peak_tflops(st, precision) * 1e12))
         bound += t
-        if st in stages and stages[st]["launches"]:
-            meas = stages[st]["total_ms"] * 1e-3 / images
-            per_stage[st] = round(t / meas, 4)
-    measured = step_ms * 1e-3 / n  # `images` = images over all timed steps, n = images per step
+        per_stage[st] = round(t / (stages[st]["total_ms"] * 1e-3 / images), 4)
+    measured = step_ms * 1e-3 / n
     irreducible = 4 * plan.L * plan.L + 8 * plan.p_half
     fused = max(irreducible / (HBM_PEAK_GBS * 1e9),
-                sum(fpi[st] / (stage_peak_tflops(st, precision) * 1e12) for st in fpi))
+                sum(fpi[st] / (stage_peak_tflops(st, precision) * 1e12) for st in present))
     return {"bound_us_per_image": round(bound * 1e6, 4), "measured_us_per_image": round(measured * 1e6, 4),
             "frac": round(bound / measured, 4), "fused_bound_us_per_image": round(fused * 1e6, 4),
             "fused_frac": round(fused / measured, 4), "stage_frac": per_stage,
-            "mflop_per_image": round(sum(fpi.values()) / 1e6, 2),
-            "unfused_MB_per_image": round(sum(bpi.values()) / 1e6, 3),
+            "mflop_per_image": round(sum(fpi[st] for st in present) / 1e6, 2),
+            "unfused_MB_per_image": round(sum(bpi[st] for st in present) / 1e6, 3),
             "irreducible_MB_per_image": round(irreducible / 1e6, 3)}
+
+
+def kernel_roofline(plan, stages: dict, images: int, precision: str) -> dict:
+    """The dominant kernel (largest total time among the stages with known algorithmic bytes)
+    against its roofline: HBM when its arithmetic intensity is below the ridge point of its
+    unit, else that unit's peak.  achieved = algorithmic bytes (or flops) of one launch over
+    the average launch duration measured with HIP events on the launch stream."""
+    bpi = algorithmic_bytes_per_image(plan)
+    fpi = algorithmic_flops_per_image(plan)
+    dom = max((s for s in stages if s in bpi), key=lambda s: stages[s]["total_ms"])
+    per_launch_images = images / stages[dom]["launches"]
+    sec = stages[dom]["avg_ms"] * 1e-3
+    alg_bytes = bpi[dom] * per_launch_images
+    hbm_achieved = alg_bytes / sec / 1e9
+    tpi = stored_traffic_per_image(dom, plan.L)
+    traffic = round(tpi * per_launch_images) if tpi is not None else None
+    flops = fpi.get(dom, 0) * per_launch_images
+    peak = stage_peak_tflops(dom, precision)
+    mfma = dom in ("radial_fwd", "covariance", "radial_adj")
+    if flops / alg_bytes > (peak * 1e12) / (HBM_PEAK_GBS * 1e9):
+        ach = flops / sec / 1e12
+        roofline = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": round(ach, 2),
+                    "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
+                    "flops_per_launch": int(flops), "hbm_algorithmic_GBps": round(hbm_achieved, 1),
+                    "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
+        if not mfma:
+            roofline["frac_of_nonpacked_fp32_issue_rate"] = round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)
+    else:
+        # arithmetic intensity below the ridge point: the attainable rate is set by HBM
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+        if flops:
+            ach = flops / sec / 1e12
+            roofline.update({"flops_per_launch": int(flops), "flop_rate_TFLOPs": round(ach, 2),
+                             "flop_frac_of_published_peak": round(ach / peak, 4)})
+            if not mfma:
+                roofline["frac_of_nonpacked_fp32_issue_rate"] = round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)
+    if dom in ("fwd_gather", "adj_spread"):
+        # w x w taps per node and image pair, one 16-byte LDS read each (8 bytes per image)
+        lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
+        roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
+        roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
+    roofline.update({"bytes_per_launch": int(alg_bytes), "images_per_launch": round(per_launch_images, 1),
+                     "avg_launch_ms": round(stages[dom]["avg_ms"], 4)})
+    return roofline
 
 
 def cpu_model() -> str:
@@ -176,7 +259,12 @@ def make_images(plan, n, seed, snr, chunk=4096):
     return images, noise_sigma(plan, snr)
 
 
+def _stage_totals(prof: dict) -> dict:
+    return {name: {"total_ms": ms, "launches": cnt, "avg_ms": ms / max(cnt, 1)} for name, (ms, cnt) in prof.items()}
+
+
 def time_form(plan, images, coeffs, precision, steps, warmup, pass_images):
+    """`steps` timed steps of expansion + covariance over all resident images."""
     import torch
 
     st = plan.new_covariance()
@@ -213,8 +301,104 @@ def time_form(plan, images, coeffs, precision, steps, warmup, pass_images):
     return wall, ev_ms, prof, st
 
 
-def cpu_baseline(plan_args, sample, seed, snr):
-    """The FP64 oracle, timed on the host on a bounded sample of the same workload."""
+def time_stream(plan, n, chunk, seed, snr, precision, pass_images, warmup=1):
+    """Images generated on the device chunk by chunk (untimed), each chunk expanded and added to
+    one covariance accumulator (timed with HIP events); `warmup` chunks first, not counted.
+    Returns (timed ms, chunks timed, per-kernel profile, covariance state)."""
+    import torch
+
+    from paper_1412_0781_amd.workload import synthetic_images
+
+    images = torch.empty((chunk, plan.L, plan.L), dtype=torch.float32, device=plan.device)
+    coeffs = torch.empty((chunk, plan.p_half, 2), dtype=torch.float32, device=plan.device)
+    stream = torch.cuda.current_stream()
+    for w in range(warmup):
+        synthetic_images(plan, 0, chunk, seed, snr, out=images)
+        plan.covariance(plan.expand(images, precision=precision, out=coeffs, batch=pass_images),
+                        precision=precision)
+        torch.cuda.synchronize()
+        log(f"{precision}: warm-up chunk {w + 1}/{warmup} done")
+    st = plan.new_covariance()
+    plan.profile_read(reset=True)
+    total_ms = 0.0
+    nch = (n + chunk - 1) // chunk
+    for ch in range(nch):
+        first = ch * chunk
+        m = min(chunk, n - first)
+        synthetic_images(plan, first, m, seed, snr, out=images[:m])
+        torch.cuda.synchronize()
+        plan.profile(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.expand(images[:m], precision=precision, out=coeffs[:m], batch=pass_images)
+        plan.covariance(coeffs[:m], st, precision=precision)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plan.profile(False)
+        total_ms += e0.elapsed_time(e1)
+        log(f"{precision}: chunk {ch + 1}/{nch} ({first + m} images) done")
+    prof = plan.profile_read(reset=True)
+    return total_ms, nch, prof, st
+
+
+def time_autograd(plan, n, seed, snr, steps, warmup, pass_images):
+    """The differentiation workload: I -> a = T* I (FBExpand) -> h . a with the fixed Wiener-like
+    shrinkage h = v / (v + sigma^2) -> T(h . a) (FBSynth) -> loss = ||T(h . a) - I_clean||^2, and
+    the backward pass to dloss/dI; `steps` timed forward + backward steps over all n images."""
+    import numpy as np
+    import torch
+
+    from paper_1412_0781_amd import fb_expand, fb_synth, synth
+    from paper_1412_0781_amd.fb import synth_normals
+    from paper_1412_0781_amd.workload import coefficient_scale, noise_sigma
+
+    L = plan.L
+    a = synth_normals(seed, synth.STREAM_COEF, 0, n, 2 * plan.p_half, 1.0, plan.device).view(n, plan.p_half, 2)
+    a.mul_(coefficient_scale(plan))
+    clean = plan.adjoint(a, batch=pass_images)
+    del a
+    sig = noise_sigma(plan, snr)
+    noisy = clean + synth_normals(seed, synth.STREAM_NOISE, 0, n, L * L, sig, plan.device).view(n, L, L)
+    v = synth.coef_variance(plan.k.astype(np.float64), plan.q.astype(np.float64))
+    h = torch.tensor((v / (v + sig * sig)).astype(np.float32), device=plan.device)[None, :, None]
+    x = noisy.detach().requires_grad_(True)
+    torch.cuda.synchronize()
+
+    def step():
+        x.grad = None
+        rec = fb_synth(fb_expand(x, plan) * h, plan)
+        loss = ((rec - clean) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"autograd: warmup step {i + 1}/{warmup} done")
+    plan.profile_read(reset=True)
+    plan.profile(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.profile(False)
+    prof = plan.profile_read(reset=True)
+    log(f"autograd: {steps} steps in {wall:.3f} s")
+    return wall, e0.elapsed_time(e1), prof, sig
+
+
+def cpu_baseline(plan_args, sample, seed, snr, kind):
+    """The FP64 oracle, timed on the host on a bounded sample of the same workload: expansion +
+    covariance, or for the differentiation workload the forward expansion, shrinkage and synthesis
+    and the backward pass (two expansions and two syntheses per image)."""
     import numpy as np
 
     import oracle
@@ -227,9 +411,11 @@ def cpu_baseline(plan_args, sample, seed, snr):
     a = synth.random_coefficients(seed, idx, kk, qq)
     sigma = math.sqrt(synth.noise_sigma2(kk, qq, L, snr))
     img = np.empty((sample, L, L), np.float32)
+    clean = np.empty((sample, L, L))
     noise = synth.noise_images(seed, idx, L, sigma)
     for i in range(sample):
-        img[i] = (oracle.adjoint(a[i:i + 1], po)[0] + noise[i]).astype(np.float32)
+        clean[i] = oracle.adjoint(a[i:i + 1], po)[0]
+        img[i] = (clean[i] + noise[i]).astype(np.float32)
         log(f"cpu baseline: synthesised sample image {i + 1}/{sample} on the host (not timed)")
     _ = po.B  # radial table: part of the plan, outside the timed region
     try:
@@ -240,16 +426,30 @@ def cpu_baseline(plan_args, sample, seed, snr):
     log(f"cpu baseline: timing the oracle on {sample} images with {cores} BLAS threads")
     t0 = time.perf_counter()
     coef = np.empty((sample, po.p_half), np.complex128)
-    for i in range(sample):
-        coef[i] = oracle.expand(img[i:i + 1].astype(np.float64), po)[0]
-        log(f"cpu baseline: oracle expansion of image {i + 1}/{sample} done")
-    oracle.mean_and_covariance(coef, po)
+    if kind == "autograd":
+        v = synth.coef_variance(kk, qq)
+        h = v / (v + sigma * sigma)
+        w = np.where(kk > 0, 2.0, 1.0)
+        for i in range(sample):
+            x = img[i:i + 1].astype(np.float64)
+            coef[i] = oracle.expand(x, po)[0]
+            rec = oracle.adjoint(h * coef[i:i + 1], po)
+            g = 2.0 * (rec - clean[i:i + 1])
+            gb = w * oracle.expand(g, po)               # gradient of the synthesis
+            _ = oracle.adjoint(h * gb / w, po)          # transpose of the expansion (weight 1)
+            log(f"cpu baseline: oracle forward + backward of image {i + 1}/{sample} done")
+        what = "forward expansion, shrinkage, synthesis and the backward pass in FP64"
+    else:
+        for i in range(sample):
+            coef[i] = oracle.expand(img[i:i + 1].astype(np.float64), po)[0]
+            log(f"cpu baseline: oracle expansion of image {i + 1}/{sample} done")
+        oracle.mean_and_covariance(coef, po)
+        what = "expansion + covariance in FP64"
     dt = time.perf_counter() - t0
     return img, coef, po, {"value": sample / dt, "unit": "images/s", "cores": int(cores), "kind": "oracle",
                            "cpu": cpu_model(),
-                           "sample": f"{sample} images of the same workload (L={L}, R={R}, c={c}), "
-                                     f"expansion + covariance in FP64, {dt:.1f} s (bounded to about half a "
-                                     f"minute of host time)"}
+                           "sample": f"{sample} images of the same workload (L={L}, R={R}, c={c}), {what}, "
+                                     f"{dt:.1f} s (bounded to about half a minute of host time)"}
 
 
 def dictionary_accuracy(plan, po, n, D, precisions, seed=21, offset=3.0):
@@ -297,21 +497,108 @@ def dictionary_accuracy(plan, po, n, D, precisions, seed=21, offset=3.0):
     return out
 
 
+def extra_legs(plan, coeffs, evals, evecs, mean, n, sigma, pass_images):
+    """Figures outside images/s at the headline shape: the SVD route, the steerable-PCA back end
+    with the real-space eigenimages, the adjoint synthesis and the R / c estimate."""
+    import torch
+
+    L = plan.L
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        r = fn()
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    # principal components by the SVD of the coefficient matrices (Sec. III-C): the same
+    # eigenvalues without forming C^(k)
+    svd_ws = torch.empty(plan.svd_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    plan.svd(coeffs[:64], ws=svd_ws)  # warm-up
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    sv_evals, _, _ = plan.svd(coeffs, ws=svd_ws)
+    torch.cuda.synchronize()
+    svd_ms = 1e3 * (time.perf_counter() - ts)
+    del svd_ws
+    lam = evals.cpu().tolist()
+    d = (sv_evals - evals).abs().cpu().tolist()
+    rel = max(d[i] / max(lam[int(plan.coef_off[k])], 1e-300)
+              for k in range(plan.k_max + 1) for i in range(int(plan.coef_off[k]), int(plan.coef_off[k + 1])))
+    svd = {"images": n, "ms": round(svd_ms, 3), "max_eval_diff_vs_eig": rel}
+    log(f"svd route: {svd}")
+
+    # steerable-PCA back end: selection with the workload's noise variance, sPCA coefficients
+    # of every image, filtered reconstruction of their FB coefficients
+    n_sel, w = plan.spca_select(evals, n, sigma * sigma)
+    plan.spca_coeffs(coeffs[:64], evecs, mean)  # warm-up
+    cs, c_ms = timed(lambda: plan.spca_coeffs(coeffs, evecs, mean))
+    _, r_ms = timed(lambda: plan.spca_reconstruct(cs, evecs, mean, w))
+    del cs
+    spca_bytes = 2 * 8 * plan.p_half * n
+    spca = {"selected_components": int(n_sel.sum().item()), "coeffs_ms": round(c_ms, 3),
+            "reconstruct_ms": round(r_ms, 3), "coeffs_images_per_s": round(n / (c_ms * 1e-3), 1),
+            "coeffs_hbm_GBps": round(spca_bytes / (c_ms * 1e-3) / 1e9, 1)}
+    # real-space eigenimages of the selected components (Eq.(IFT_FB) combinations, FP64)
+    sel = n_sel.cpu().numpy()
+    ks = [k for k in range(plan.k_max + 1) if sel[k] > 0]
+    cap = max([int(sel[k]) for k in ks] + [1])
+    ebuf = torch.empty((cap, L, L), dtype=torch.complex128, device="cuda")
+    plan.eigenimages(evecs, 0, 0, 1, out=ebuf[:1])  # warm-up
+    _, e_ms = timed(lambda: [plan.eigenimages(evecs, k, 0, int(sel[k]), out=ebuf[:int(sel[k])]) for k in ks])
+    del ebuf
+    spca["eigenimages"] = int(sel.sum())
+    spca["eigenimages_ms"] = round(e_ms, 3)
+    log(f"spca back end: {spca}")
+
+    # adjoint synthesis T a (the differentiation and reconstruction path)
+    na = min(n, 16384)
+    plan.adjoint(coeffs[:64], batch=pass_images)  # warm-up
+    _, adj_ms = timed(lambda: plan.adjoint(coeffs[:na], batch=pass_images))
+    adjoint = {"images": na, "ms": round(adj_ms, 3), "images_per_s": round(na / (adj_ms * 1e-3), 1)}
+    log(f"adjoint: {adjoint}")
+
+    # estimation of R and c (Sec. VI-C) on a CTF-filtered workload (Eq.(CTFenv), 1 A per pixel,
+    # noise at SNR 1/2 over the filtered clean power)
+    from paper_1412_0781_amd import workload as wl
+    ne = min(n, 20000)
+    Hf = wl.ctf_ring_filter(plan)
+    clean = wl.synthetic_images(plan, 0, 256, seed=1, snr=1.0, ring_filter=Hf, sigma=0.0)
+    sig = float((clean.double().pow(2).mean() / 0.5).sqrt())
+    del clean
+    imgs_e = wl.synthetic_images(plan, 0, ne, seed=1, snr=1.0, ring_filter=Hf, sigma=sig)
+    plan.pixel_moments(imgs_e[:64])  # warm-up
+
+    def estimate_rc():
+        s1, s2 = plan.pixel_moments(imgs_e)
+        pw = plan.polar_power(imgs_e, pixel_sum=s1, count=ne, batch=pass_images)
+        return plan.estimate_support(s1, s2, ne, pw, sig * sig, 0.999)
+
+    (R_est, c_est), est_ms = timed(estimate_rc)
+    del imgs_e
+    support = {"images": ne, "ms": round(est_ms, 3), "images_per_s": round(ne / (est_ms * 1e-3), 1), "R": R_est,
+               "c": round(c_est, 4), "workload": "CTF-filtered synthesis, support R=L/2, SNR 1/2"}
+    log(f"support estimate: {support}")
+    return {"svd": svd, "spca": spca, "adjoint": adjoint, "support_estimate": support}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=100000)
-    ap.add_argument("--L", type=int, default=256)
-    ap.add_argument("--snr", type=float, default=1 / 20)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--L", type=int, default=None)
+    ap.add_argument("--snr", type=float, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--pass-images", type=int, default=2048)
-    ap.add_argument("--forms", default="fp32,bf16x3")
-    ap.add_argument("--cpu-sample", type=int, default=8)
-    ap.add_argument("--dict-images", type=int, default=2000,
+    ap.add_argument("--forms", default=None)
+    ap.add_argument("--cpu-sample", type=int, default=None)
+    ap.add_argument("--dict-images", type=int, default=None,
                     help="images of the pixel-dictionary accuracy check (0 skips it)")
-    ap.add_argument("--dict-pixels", type=int, default=128)
+    ap.add_argument("--dict-pixels", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (calibrates HBM byte counters) and exit")
@@ -319,6 +606,11 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    wk = WORKLOADS[args.workload]
+    for key in ("n", "L", "snr", "forms", "cpu_sample", "dict_images", "dict_pixels"):
+        if getattr(args, key) is None:
+            setattr(args, key, wk[key])
+    kind = wk["kind"]
 
     import numpy as np
     import torch
@@ -337,168 +629,77 @@ def main():
         return
     L = args.L
     c, R = 0.5, L / 2
-    log(f"plan L={L} R={R} c={c}")
+    log(f"workload {args.workload} ({kind}): plan L={L} R={R} c={c}")
     t0 = time.perf_counter()
     plan = Plan(L, c, R)
     plan_s = time.perf_counter() - t0
     log(f"plan built in {plan_s:.2f} s: n_xi={plan.n_xi} n_theta={plan.n_theta} k_max={plan.k_max} "
         f"p_half={plan.p_half}")
-    log(f"generating {args.n} images on the device")
-    t0 = time.perf_counter()
-    images, sigma = make_images(plan, args.n, args.seed, args.snr)
-    log(f"images ready in {time.perf_counter() - t0:.1f} s (noise sigma {sigma:.4g})")
-    coeffs = torch.empty((args.n, plan.p_half, 2), dtype=torch.float32, device=plan.device)
     plan.workspace(args.pass_images)
+    precs = [f.strip() for f in args.forms.split(",") if f.strip()]
 
-    forms = {}
-    profs = {}
-    for prec in [f.strip() for f in args.forms.split(",") if f.strip()]:
-        wall, ev_ms, prof, st = time_form(plan, images, coeffs, prec, args.steps, args.warmup, args.pass_images)
-        forms[prec] = {"images_per_s": args.n * args.steps / wall, "ms_per_step": 1e3 * wall / args.steps,
-                       "event_ms_per_step": ev_ms / args.steps}
-        profs[prec] = prof
-    head = "bf16x3" if "bf16x3" in forms else next(iter(forms))
+    forms, profs = {}, {}
+    images = coeffs = st = None
+    steps_done = args.steps
+    from paper_1412_0781_amd.workload import noise_sigma
+    sigma = noise_sigma(plan, args.snr)
+    if kind == "resident":
+        log(f"generating {args.n} images on the device")
+        t0 = time.perf_counter()
+        images, sigma = make_images(plan, args.n, args.seed, args.snr)
+        log(f"images ready in {time.perf_counter() - t0:.1f} s (noise sigma {sigma:.4g})")
+        coeffs = torch.empty((args.n, plan.p_half, 2), dtype=torch.float32, device=plan.device)
+        for prec in precs:
+            wall, ev_ms, prof, st = time_form(plan, images, coeffs, prec, args.steps, args.warmup, args.pass_images)
+            forms[prec] = {"images_per_s": args.n * args.steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+                           "event_ms_per_step": ev_ms / args.steps}
+            profs[prec] = prof
+        timed_images = args.n * args.steps
+        n_step = args.n
+    elif kind == "stream":
+        for prec in precs:
+            ms, nch, prof, st = time_stream(plan, args.n, wk["chunk"], args.seed, args.snr, prec, args.pass_images)
+            forms[prec] = {"images_per_s": args.n / (ms * 1e-3), "ms_per_step": ms / nch, "chunks": nch}
+            profs[prec] = prof
+        steps_done = (args.n + wk["chunk"] - 1) // wk["chunk"]
+        timed_images = args.n
+        n_step = min(args.n, wk["chunk"])
+    else:  # autograd
+        wall, ev_ms, prof, sigma = time_autograd(plan, args.n, args.seed, args.snr, args.steps, args.warmup,
+                                                 args.pass_images)
+        forms["fp32"] = {"images_per_s": args.n * args.steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+                         "event_ms_per_step": ev_ms / args.steps}
+        profs["fp32"] = prof
+        timed_images = args.n * args.steps
+        n_step = args.n
+    head = wk["head"] if wk["head"] in forms else next(iter(forms))
 
-    # eigendecomposition of the accumulated covariance (outside images/s)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    evals, evecs, _, mean = plan.eig(st)
-    torch.cuda.synchronize()
-    eig_ms = 1e3 * (time.perf_counter() - te)
-
-    # principal components by the SVD of the coefficient matrices (Sec. III-C), outside
-    # images/s: the same eigenvalues without forming C^(k)
-    svd_ws = torch.empty(plan.svd_workspace_bytes(args.n), dtype=torch.uint8, device="cuda")
-    plan.svd(coeffs[:64], ws=svd_ws)  # warm-up
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    sv_evals, _, _ = plan.svd(coeffs, ws=svd_ws)
-    torch.cuda.synchronize()
-    svd_ms = 1e3 * (time.perf_counter() - ts)
-    del svd_ws
-    lam = evals.cpu().tolist()
-    d = (sv_evals - evals).abs().cpu().tolist()
-    rel = max(d[i] / max(lam[int(plan.coef_off[k])], 1e-300)
-              for k in range(plan.k_max + 1) for i in range(int(plan.coef_off[k]), int(plan.coef_off[k + 1])))
-    svd = {"images": args.n, "ms": round(svd_ms, 3), "max_eval_diff_vs_eig": rel}
-    log(f"svd route: {svd}")
-
-    # steerable-PCA back end (outside images/s): selection with the workload's noise variance,
-    # sPCA coefficients of every image, filtered reconstruction of their FB coefficients
-    def timed(fn):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(torch.cuda.current_stream())
-        r = fn()
-        e1.record(torch.cuda.current_stream())
+    eig_ms = None
+    legs = {}
+    if st is not None:
+        # eigendecomposition of the accumulated covariance (outside images/s)
         torch.cuda.synchronize()
-        return r, e0.elapsed_time(e1)
+        te = time.perf_counter()
+        evals, evecs, _, mean = plan.eig(st)
+        torch.cuda.synchronize()
+        eig_ms = 1e3 * (time.perf_counter() - te)
+        if args.workload == "c3":
+            legs = extra_legs(plan, coeffs, evals, evecs, mean, args.n, sigma, args.pass_images)
+    del images, coeffs
 
-    n_sel, w = plan.spca_select(evals, args.n, sigma * sigma)
-    plan.spca_coeffs(coeffs[:64], evecs, mean)  # warm-up
-    cs, c_ms = timed(lambda: plan.spca_coeffs(coeffs, evecs, mean))
-    _, r_ms = timed(lambda: plan.spca_reconstruct(cs, evecs, mean, w))
-    del cs
-    spca_bytes = 2 * 8 * plan.p_half * args.n
-    spca = {"selected_components": int(n_sel.sum().item()), "coeffs_ms": round(c_ms, 3),
-            "reconstruct_ms": round(r_ms, 3), "coeffs_images_per_s": round(args.n / (c_ms * 1e-3), 1),
-            "coeffs_hbm_GBps": round(spca_bytes / (c_ms * 1e-3) / 1e9, 1)}
-    # real-space eigenimages of the selected components (Eq.(IFT_FB) combinations, FP64)
-    sel = n_sel.cpu().numpy()
-    ks = [k for k in range(plan.k_max + 1) if sel[k] > 0]
-    cap = max([int(sel[k]) for k in ks] + [1])
-    ebuf = torch.empty((cap, L, L), dtype=torch.complex128, device="cuda")
-    plan.eigenimages(evecs, 0, 0, 1, out=ebuf[:1])  # warm-up
-    _, e_ms = timed(lambda: [plan.eigenimages(evecs, k, 0, int(sel[k]), out=ebuf[:int(sel[k])]) for k in ks])
-    del ebuf
-    spca["eigenimages"] = int(sel.sum())
-    spca["eigenimages_ms"] = round(e_ms, 3)
-    log(f"spca back end: {spca}")
-
-    # adjoint synthesis T a (the differentiation and reconstruction path), outside images/s
-    na = min(args.n, 16384)
-    plan.adjoint(coeffs[:64], batch=args.pass_images)  # warm-up
-    _, adj_ms = timed(lambda: plan.adjoint(coeffs[:na], batch=args.pass_images))
-    adjoint = {"images": na, "ms": round(adj_ms, 3), "images_per_s": round(na / (adj_ms * 1e-3), 1)}
-    log(f"adjoint: {adjoint}")
-
-    # estimation of R and c (Sec. VI-C) on a CTF-filtered workload (Eq.(CTFenv), 1 A per pixel,
-    # noise at SNR 1/2 over the filtered clean power), outside images/s
-    from paper_1412_0781_amd import workload as wl
-    ne = min(args.n, 20000)
-    Hf = wl.ctf_ring_filter(plan)
-    clean = wl.synthetic_images(plan, 0, 256, seed=1, snr=1.0, ring_filter=Hf, sigma=0.0)
-    sig = float((clean.double().pow(2).mean() / 0.5).sqrt())
-    del clean
-    imgs_e = wl.synthetic_images(plan, 0, ne, seed=1, snr=1.0, ring_filter=Hf, sigma=sig)
-    plan.pixel_moments(imgs_e[:64])  # warm-up
-
-    def estimate_rc():
-        s1, s2 = plan.pixel_moments(imgs_e)
-        pw = plan.polar_power(imgs_e, pixel_sum=s1, count=ne, batch=args.pass_images)
-        return plan.estimate_support(s1, s2, ne, pw, sig * sig, 0.999)
-
-    (R_est, c_est), est_ms = timed(estimate_rc)
-    del imgs_e
-    support = {"images": ne, "ms": round(est_ms, 3), "images_per_s": round(ne / (est_ms * 1e-3), 1), "R": R_est,
-               "c": round(c_est, 4), "workload": "CTF-filtered synthesis, support R=L/2, SNR 1/2"}
-    log(f"support estimate: {support}")
-
-    # per-kernel figures of the headline form; dominant kernel against its roofline
-    prof = profs[head]
-    bpi = algorithmic_bytes_per_image(plan)
-    fpi = algorithmic_flops_per_image(plan)
-    stages = {}
-    for name, (ms, cnt) in prof.items():
-        stages[name] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / max(cnt, 1)}
-    dom = max((s for s in stages if s in bpi), key=lambda s: stages[s]["total_ms"])
-    per_launch_images = args.n * args.steps / stages[dom]["launches"]
-    sec = stages[dom]["avg_ms"] * 1e-3
-    alg_bytes = bpi[dom] * per_launch_images
-    hbm_achieved = alg_bytes / sec / 1e9
-    tpi = stored_traffic_per_image(dom, L)
-    traffic = round(tpi * per_launch_images) if tpi is not None else None
-    flops = fpi.get(dom, 0) * per_launch_images
-    peak = stage_peak_tflops(dom, head)
-    if flops / alg_bytes > (peak * 1e12) / (HBM_PEAK_GBS * 1e9):
-        # arithmetic intensity above the ridge point: bound by the arithmetic units
-        ach = flops / sec / 1e12
-        mfma = dom in ("radial_fwd", "covariance")
-        roofline = {"bound": "mfma" if mfma else "alu", "kernel": dom, "achieved": round(ach, 2),
-                    "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
-                    "flops_per_launch": int(flops), "hbm_algorithmic_GBps": round(hbm_achieved, 1),
-                    "hbm_frac": round(hbm_achieved / HBM_PEAK_GBS, 4)}
-        if not mfma:
-            roofline["frac_of_nonpacked_fp32_issue_rate"] = round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)
-        if dom == "fwd_gather":
-            # W x W taps per node and image pair, one 16-byte LDS read each (8 bytes per image)
-            lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
-            roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
-            roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
-    else:
-        # arithmetic intensity below the ridge point: the attainable rate is set by HBM
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
-        if flops:
-            ach = flops / sec / 1e12
-            roofline.update({"flops_per_launch": int(flops), "flop_rate_TFLOPs": round(ach, 2),
-                             "flop_frac_of_published_peak": round(ach / peak, 4),
-                             "frac_of_nonpacked_fp32_issue_rate": round(ach / ALU_FP32_NONPACKED_TFLOPS, 4)})
-        if dom == "fwd_gather":
-            lds = plan.kernel_w ** 2 * 8 * plan.n_xi * (plan.n_theta // 2) * per_launch_images
-            roofline["lds_read_TBs"] = round(lds / sec / 1e12, 1)
-            roofline["lds_frac_of_measured"] = round(lds / sec / 1e12 / LDS_MEASURED_TBS, 4)
-    roofline.update({"bytes_per_launch": int(alg_bytes), "images_per_launch": round(per_launch_images, 1),
-                     "avg_launch_ms": round(stages[dom]["avg_ms"], 4)})
-    step = {prec: step_roofline(plan, prec, {k: {"total_ms": v[0], "launches": v[1]} for k, v in profs[prec].items()},
-                                args.n * args.steps, forms[prec]["ms_per_step"], args.n)
+    stages = _stage_totals(profs[head])
+    roofline = kernel_roofline(plan, stages, timed_images, head)
+    step = {prec: step_roofline(plan, prec, _stage_totals(profs[prec]), timed_images, forms[prec]["ms_per_step"],
+                                n_step)
             for prec in forms}
+    log(f"roofline: {roofline}")
     log(f"step roofline: {step}")
 
     # accuracy on a host-generated sample, and the CPU oracle baseline
     accuracy = None
     cpu = None
     if not args.no_cpu_baseline:
-        img_s, coef_ref, po, cpu = cpu_baseline((L, c, R), args.cpu_sample, args.seed, args.snr)
+        img_s, coef_ref, po, cpu = cpu_baseline((L, c, R), args.cpu_sample, args.seed, args.snr, kind)
         xs = torch.tensor(img_s, device=plan.device)
         accuracy = {}
         for prec in forms:
@@ -514,33 +715,36 @@ def main():
             log(f"accuracy vs FP64 oracle (pixel-dictionary images): {accuracy}")
 
     f = forms[head]
+    what = {"resident": "FB expansion + covariance",
+            "stream": f"FB expansion + covariance, streamed in chunks of {wk.get('chunk')}",
+            "autograd": "FB expansion, shrinkage, synthesis, forward + backward"}[kind]
+    metric = METRIC if args.workload == "c3" else \
+        f"images/s ({what}) at L={L}, " + ("FP32" if kind == "autograd" else "BF16x3 vs FP32")
     out = {
-        "metric": METRIC,
+        "metric": metric,
         "value": round(f["images_per_s"], 1),
         "unit": "images/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps_done,
         "warmup": args.warmup,
         "ms_per_step": round(f["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"{head} matrix-core contractions, f32 NUFFT",
+        "dtype": "f32 (autograd path)" if kind == "autograd" else f"{head} matrix-core contractions, f32 NUFFT",
         "data": "synthetic",
-        "config": {"workload": f"FB expansion + covariance, n={args.n} images L={L} R={R:g} c={c} "
+        "config": {"workload": f"{what}, n={args.n} images L={L} R={R:g} c={c} "
                                f"SNR=1/{round(1 / args.snr)} (synthetic, device-generated, seed {args.seed})",
-                   "n": args.n, "L": L, "R": R, "c": c, "precision": head, "pass_images": args.pass_images},
+                   "name": args.workload, "n": args.n, "L": L, "R": R, "c": c, "precision": head,
+                   "pass_images": args.pass_images},
         "forms": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in forms.items()},
         "bf16x3_over_fp32": round(forms["bf16x3"]["images_per_s"] / forms["fp32"]["images_per_s"], 3)
         if "bf16x3" in forms and "fp32" in forms else None,
         "accuracy_rel_l2": accuracy,
         "stages": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                    for k, v in stages.items()},
-        "eig_ms": round(eig_ms, 2),
-        "svd": svd,
-        "spca": spca,
-        "adjoint": adjoint,
-        "support_estimate": support,
+        "eig_ms": round(eig_ms, 2) if eig_ms is not None else None,
+        **legs,
         "plan_s": round(plan_s, 2),
         "roofline": roofline,
         "step_roofline": step,

@@ -314,8 +314,10 @@ int fb_estimate_support(fb_plan_t plan, const double* sum, const double* sumsq, 
  *            8-byte aligned, caller-owned (mean, per-range factors, p_k x p_k blocks).
  * Asynchronous on `stream`; allocates nothing.  Errors: FB_ERR_INVALID_ARG (NULL
  * pointers, n <= 0, misaligned ws), FB_ERR_WORKSPACE, FB_ERR_UNSUPPORTED (max p_k above
- * 128: two threads per column of a 256-thread workgroup, and the p_k x p_k Jacobi block
- * in its LDS), FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+ * 199: the packed triangular factor of the largest block is kept in LDS; two threads per
+ * column, in workgroups of 512 threads when max p_k > 128; blocks whose p_k x p_k rotation
+ * matrix does not fit in LDS (p_k > 141) are rotated in global memory), FB_ERR_NO_DEVICE,
+ * FB_ERR_HIP. */
 size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n);
 int fb_svd(fb_plan_t plan, const float* coeffs, int64_t n, double* evals, double* evecs, double* mean_out, void* ws,
            size_t ws_bytes, void* stream);

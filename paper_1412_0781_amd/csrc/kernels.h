@@ -66,7 +66,7 @@ hipError_t launch_spca_radial(const Plan& pl, const double* evecs, float* f, hip
 // SVD route (Sec. III-C): rows per level-1 workgroup, LDS ceiling of the two SVD kernels.
 constexpr int kSvdRowsPerGroup = 8192;
 constexpr int kSvdLdsLimit = 160 * 1024 - 1024;
-constexpr int kSvdMaxP = 128;  // two threads per column in a 256-thread workgroup
+constexpr int kSvdMaxP = 256;  // two threads per column in a workgroup of at most 512 threads
 int svd_max_p(const Plan& pl);
 struct SvdSplit {
   int W0, W1;                 // level-1 workgroups for k = 0 and for each k > 0

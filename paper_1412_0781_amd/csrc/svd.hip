@@ -17,7 +17,7 @@ namespace fb {
 
 constexpr int kSvdChunk = 32;          // rows per Householder update
 constexpr int kSvdHalf = kSvdChunk / 2;  // rows per thread: two threads per column
-constexpr int kSvdThreads = 256;       // two threads per matrix column (p_k <= 128)
+constexpr int kSvdThreadsMax = 2 * kSvdMaxP;  // two threads per matrix column; 256 threads when max p_k <= 128
 
 __device__ __forceinline__ long long tri_row(int j, int p) { return (long long)j * p - (long long)j * (j - 1) / 2; }
 
@@ -110,7 +110,7 @@ __host__ __device__ inline long long svd_qr_lds_doubles(int p) {
 
 // Level 1: workgroup (k, w) reduces rows [w rows_per, (w + 1) rows_per) of X^(k) to a
 // packed R at Rout + offset(k, w).  Blocks 0 .. W0-1 take k = 0, then W1 blocks per k > 0.
-__global__ __launch_bounds__(kSvdThreads) void k_svd_tsqr(const float* __restrict__ coeffs, long long n,
+__global__ __launch_bounds__(kSvdThreadsMax) void k_svd_tsqr(const float* __restrict__ coeffs, long long n,
                                                           long long p_half, const double* __restrict__ mean,
                                                           const int* __restrict__ p_arr,
                                                           const int* __restrict__ coef_off,
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_tsqr(const float* __restric
   double* dB = dA + pk;
   double* yb = dB + pk;
   double* ref = yb + 2 * kSvdChunk;
-  for (long long i = tid; i < tp; i += kSvdThreads) R[i] = 0.0;
-  for (int i = tid; i < pk; i += kSvdThreads) dA[i] = dB[i] = 0.0;
+  for (long long i = tid; i < tp; i += (int)blockDim.x) R[i] = 0.0;
+  for (int i = tid; i < pk; i += (int)blockDim.x) dA[i] = dB[i] = 0.0;
   const int c = tid >> 1, h = tid & 1;
   double y[kSvdHalf];
   for (long long q0 = r0; q0 < r1; q0 += kSvdChunk) {
@@ -159,10 +159,10 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_tsqr(const float* __restric
     dB = t;
   }
   __syncthreads();
-  for (int j = tid; j < pk; j += kSvdThreads) R[tri_row(j, pk)] = dA[j];
+  for (int j = tid; j < pk; j += (int)blockDim.x) R[tri_row(j, pk)] = dA[j];
   __syncthreads();
   double* out = Rout + (k == 0 ? 0 : base1 + (long long)W1 * (tri_off[k] - tri_off[1])) + (long long)w * tp;
-  for (long long i = tid; i < tp; i += kSvdThreads) out[i] = R[i];
+  for (long long i = tid; i < tp; i += (int)blockDim.x) out[i] = R[i];
 }
 
 // Level 2 and the small SVD, one workgroup per k: merge the W R's of k (their rows streamed
@@ -171,13 +171,14 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_tsqr(const float* __restric
 // order: the P/2 disjoint pairs of a round go to the waves, one pair per wave), then write
 // lambda_l = ||m_l||^2 / n in descending order and the columns m_l / ||m_l||, the entry of
 // largest magnitude made positive (lowest index on ties), packed like the covariance.
-__global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __restrict__ Rin_all, long long n,
+__global__ __launch_bounds__(kSvdThreadsMax) void k_svd_finish(const double* __restrict__ Rin_all, long long n,
                                                             const int* __restrict__ p_arr,
                                                             const int* __restrict__ coef_off,
                                                             const long long* __restrict__ cov_off,
                                                             const long long* __restrict__ tri_off, int W0, int W1,
                                                             long long base1, double* __restrict__ Mg_all,
-                                                            double* __restrict__ evals, double* __restrict__ evecs) {
+                                                            double* __restrict__ evals, double* __restrict__ evecs,
+                                                            long long lds_doubles) {
   extern __shared__ double sm[];
   __shared__ int s_rot;
   const int k = blockIdx.x, pk = p_arr[k], tid = threadIdx.x;
@@ -190,8 +191,8 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
   double* dB = dA + pk;
   double* yb = dB + pk;
   double* ref = yb + 2 * kSvdChunk;
-  for (long long i = tid; i < tp; i += kSvdThreads) R[i] = 0.0;
-  for (int i = tid; i < pk; i += kSvdThreads) dA[i] = dB[i] = 0.0;
+  for (long long i = tid; i < tp; i += (int)blockDim.x) R[i] = 0.0;
+  for (int i = tid; i < pk; i += (int)blockDim.x) dA[i] = dB[i] = 0.0;
   const long long nrows = (long long)W * pk;
   const int c = tid >> 1, h = tid & 1;
   double y[kSvdHalf];
@@ -214,21 +215,25 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
     dB = t;
   }
   __syncthreads();
-  for (int j = tid; j < pk; j += kSvdThreads) R[tri_row(j, pk)] = dA[j];
+  for (int j = tid; j < pk; j += (int)blockDim.x) R[tri_row(j, pk)] = dA[j];
   __syncthreads();
   double* Mg = Mg_all + cov_off[k];
-  for (int i = tid; i < pk * pk; i += kSvdThreads) {
+  for (int i = tid; i < pk * pk; i += (int)blockDim.x) {
     const int l = i / pk, c = i - l * pk;
     Mg[i] = c >= l ? R[tri_row(l, pk) + (c - l)] : 0.0;
   }
   __syncthreads();
-  double* M = sm;  // the LDS of R is free now
-  for (int i = tid; i < pk * pk; i += kSvdThreads) M[i] = Mg[i];
-  double* sig2 = M + (long long)pk * pk;
+  // the rotations run on M in LDS when it fits (the LDS of R is free now), else on Mg in
+  // global memory (the waves of one workgroup meet at barriers, which order those accesses)
+  const bool in_lds = (long long)pk * pk + pk <= lds_doubles;
+  double* M = in_lds ? sm : Mg;
+  if (in_lds)
+    for (int i = tid; i < pk * pk; i += (int)blockDim.x) M[i] = Mg[i];
+  double* sig2 = in_lds ? M + (long long)pk * pk : sm;
   // ---- one-sided Jacobi
   one_sided_jacobi(M, pk, &s_rot);
   // ---- singular values, order, sign, output
-  for (int l = tid; l < pk; l += kSvdThreads) {
+  for (int l = tid; l < pk; l += (int)blockDim.x) {
     double a = 0.0;
     for (int e = 0; e < pk; ++e) a = fma(M[(long long)l * pk + e], M[(long long)l * pk + e], a);
     sig2[l] = a;
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
   __syncthreads();
   const long long eo = cov_off[k];
   const int co = coef_off[k];
-  for (int l = tid; l < pk; l += kSvdThreads) {
+  for (int l = tid; l < pk; l += (int)blockDim.x) {
     const double s2 = sig2[l];
     int rank = 0;
     for (int m = 0; m < pk; ++m) rank += (sig2[m] > s2 || (sig2[m] == s2 && m < l)) ? 1 : 0;
@@ -258,10 +263,15 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_finish(const double* __rest
 int svd_max_p(const Plan& pl) { return *std::max_element(pl.p.begin(), pl.p.end()); }
 
 size_t svd_finish_lds_bytes(const Plan& pl) {
+  // the merge's LDS, and the p x p block of the rotations with its p norms when that fits
   const int pm = *std::max_element(pl.p.begin(), pl.p.end());
-  const long long need = std::max(svd_qr_lds_doubles(pm), (long long)pm * pm + pm);
+  long long need = std::max(svd_qr_lds_doubles(pm), (long long)pm);
+  const long long block = (long long)pm * pm + pm;
+  if (block * (long long)sizeof(double) <= kSvdLdsLimit) need = std::max(need, block);
   return (size_t)need * sizeof(double);
 }
+
+int svd_threads(const Plan& pl) { return svd_max_p(pl) > kSvdMaxP / 2 ? kSvdThreadsMax : kSvdThreadsMax / 2; }
 
 size_t svd_qr_lds_bytes(const Plan& pl) {
   const int pm = *std::max_element(pl.p.begin(), pl.p.end());
@@ -298,14 +308,16 @@ hipError_t launch_svd(const Plan& pl, const float* coeffs, long long n, double* 
   pl.prof.end(st);
   const long long nblk = (long long)s.W0 + (long long)s.W1 * pl.k_max;
   pl.prof.begin(ST_SVD, st);
-  hipLaunchKernelGGL(k_svd_tsqr, dim3((unsigned)nblk), dim3(kSvdThreads), svd_qr_lds_bytes(pl), st, coeffs, n,
+  const int nthr = svd_threads(pl);
+  hipLaunchKernelGGL(k_svd_tsqr, dim3((unsigned)nblk), dim3(nthr), svd_qr_lds_bytes(pl), st, coeffs, n,
                      (long long)pl.p_half, mean, pl.d_p, pl.d_coef_off, pl.d_tri_off, s.W0, s.W1, s.base1,
                      (long long)kSvdRowsPerGroup, Rws);
   pl.prof.end(st);
   pl.prof.begin(ST_SVD, st);
-  hipLaunchKernelGGL(k_svd_finish, dim3((unsigned)(pl.k_max + 1)), dim3(kSvdThreads), svd_finish_lds_bytes(pl), st,
-                     Rws, n, pl.d_p, pl.d_coef_off, pl.d_cov_off, pl.d_tri_off, s.W0, s.W1, s.base1, Mws, evals,
-                     evecs);
+  const size_t fin_lds = svd_finish_lds_bytes(pl);
+  hipLaunchKernelGGL(k_svd_finish, dim3((unsigned)(pl.k_max + 1)), dim3(nthr), fin_lds, st, Rws, n, pl.d_p,
+                     pl.d_coef_off, pl.d_cov_off, pl.d_tri_off, s.W0, s.W1, s.base1, Mws, evals, evecs,
+                     (long long)(fin_lds / sizeof(double)));
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -7,7 +7,7 @@ Householder QR and Jacobi rotations are backward stable at a few ulps of the lar
 singular value); eigenvectors 1e-8 where the relative gap to their neighbours exceeds
 1e-3; the mean 1e-12.  The ill-conditioned case compares every eigenvalue to its own size,
 which the covariance route cannot do.  Sizes span several level-1 row ranges per k
-(8192 rows each) and a ragged last range."""
+(8192 rows each) and a ragged last range, and blocks of up to 179 coefficients (L = 360)."""
 
 import numpy as np
 import pytest
@@ -95,6 +95,20 @@ def test_svd_full_size():
     po = oracle.plan(L, c, R)
     plan = Plan(L, c, R)
     _compare(po, plan, _coeffs(po, n, seed=7))
+
+
+@pytest.mark.parametrize("L,n", [(276, 1500), (360, 2000)])
+def test_svd_blocks_above_128(L, n):
+    """Blocks of more than 128 coefficients: two threads per column in 512-thread workgroups;
+    at L = 276 (p_0 = 137) the p_k x p_k rotations still run in LDS, at L = 360 (p_0 = 179)
+    the blocks above 141 are rotated in global memory."""
+    torch.cuda.set_device(0)
+    print(f"[svd] L={L} n={n}", flush=True)
+    c, R = 0.5, L / 2
+    po = oracle.plan(L, c, R)
+    plan = Plan(L, c, R)
+    assert max(po.p) > 128
+    _compare(po, plan, _coeffs(po, n, seed=L))
 
 
 def test_svd_arguments():
