@@ -18,4 +18,29 @@ __device__ __forceinline__ int xcd_remap(int lin, int total) {
 // exchanged through it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Store of a value that the kernel does not read again (the output of a streaming pass),
+// with the nontemporal hint: measured 2-3 % faster for the column, gather and angular
+// passes (the row pass, whose output the column pass rereads at once, stores plainly).
+#ifndef FB_NT_STORES
+#define FB_NT_STORES 1
+#endif
+typedef float fb_f2v __attribute__((ext_vector_type(2)));
+typedef float fb_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_out(float2* p, float2 v) {
+  if constexpr (FB_NT_STORES != 0) {
+    const fb_f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (fb_f2v*)p);
+  } else {
+    *p = v;
+  }
+}
+__device__ __forceinline__ void st_out(float4* p, float4 v) {
+  if constexpr (FB_NT_STORES != 0) {
+    const fb_f4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (fb_f4v*)p);
+  } else {
+    *p = v;
+  }
+}
+
 }  // namespace fb

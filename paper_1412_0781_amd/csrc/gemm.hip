@@ -182,8 +182,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_f32(const float* __restrict_
       const int il = i / nrow, q = i - il * nrow;
       const float re = S.Cs[2 * il][q];
       const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
-      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] =
-          make_float2(wk * re, wk * im);
+      st_out((float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)],
+             make_float2(wk * re, wk * im));
     }
   };
   emit(acc0, 0);
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
       const int il = i / nrow, q = i - il * nrow;
       const float re = S.Cs[2 * il][q];
       const float im = (k == 0) ? 0.f : S.Cs[2 * il + 1][q];
-      *(float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)] =
-          make_float2(wk * re, wk * im);
+      st_out((float2*)&coeffs[(size_t)(c0 / 2 + il) * 2 * p_half + 2 * (size_t)(off + m0 + q)],
+             make_float2(wk * re, wk * im));
     }
   };
   emit(acc0, 0);

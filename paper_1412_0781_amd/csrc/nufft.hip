@@ -314,7 +314,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __res
     fft_stream<NC, G>(s_buf, S, fd, s_tw);
     const int c = tid & (G - 1);
     float2* dst = g + ((size_t)m2 * ngrp + grp) * N * G + c;
-    for (int m1 = tid / G; m1 < N; m1 += nthr / G) dst[(size_t)m1 * G] = s_buf[c * S + fpad(m1)];
+    for (int m1 = tid / G; m1 < N; m1 += nthr / G) st_out(&dst[(size_t)m1 * G], s_buf[c * S + fpad(m1)]);
     stage_barrier<true>();
   }
 }
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
       }
     }
     float2* dst = P + (((size_t)nd.j * ngrp + grp) * H + nd.l) * IG + 2 * ip;
-    *(float4*)dst = make_float4(ax0, ay0, ax1, ay1);
+    st_out((float4*)dst, make_float4(ax0, ay0, ax1, ay1));
   }
 }
 
@@ -567,8 +567,8 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __
       float2 d = csub(zk, zc);
       float2 o = make_float2(0.5f * d.y, -0.5f * d.x);
       float2 Sk = cadd(e, cmul(s_angtw[k], o));
-      dst[(size_t)k * G] =
-          (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale);
+      st_out(&dst[(size_t)k * G],
+             (k & 1) ? make_float2(-Sk.y * scale, Sk.x * scale) : make_float2(Sk.x * scale, Sk.y * scale));
     }
     stage_barrier<true>();  // s_buf is rewritten by the next unit
   }
