@@ -48,6 +48,8 @@ from .fb import (  # noqa: F401
     coefficient_rows,
     svd_blocks,
     adjoint,
+    adjoint_polar,
+    adjoint_pixels,
     coeff_inner,
 )
 from . import spca  # noqa: F401,E402

@@ -376,18 +376,11 @@ def coeff_inner(a: np.ndarray, b: np.ndarray, pl: Plan) -> np.ndarray:
     return s0 + 2.0 * s1
 
 
-def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096, ring_filter=None) -> np.ndarray:
-    """(T b)(x) = Re sum_{k=-kmax..kmax} sum_q b_{kq} conj(M_{kq}(x)), with b_{-k} = conj(b_k).
-
-    M_{kq}(x) is the row of T* for coefficient (k, q): Eq.(nufft), Eq.(1DFFT)
-    and Eq.(a) composed.  Folding +-k gives weight 1 for k = 0 and 2 for k > 0.
-    Computed as the transpose of each step in turn: the radial sum, the angular
-    sum, then the direct type-1 sum over the polar nodes.
-
-    ring_filter (optional, [n_xi]) multiplies the spectrum on ring j by H(xi_j) after the
-    radial sum: the image of a radially symmetric Fourier filter H applied to the
-    band-limited synthesis (the convolution of Sec. VI-C's CTF workload).
-    """
+def adjoint_polar(b: np.ndarray, pl: Plan, ring_filter=None) -> np.ndarray:
+    """The transposes of Eq.(a) and Eq.(1DFFT) applied to coefficients b: the values on the
+    polar nodes, complex128 [n, n_xi * n_theta] (rings outer), that the type-1 sum of
+    ``adjoint`` takes to pixels.  Folding +-k gives weight 1 for k = 0 and 2 for k > 0;
+    ring_filter as in ``adjoint``."""
     b = np.asarray(b, dtype=np.complex128)
     n = b.shape[0]
     K = pl.k_max
@@ -402,8 +395,24 @@ def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096, ring_filter=None) -
     kk = np.arange(K + 1)
     phase = (np.outer(l, kk) % pl.n_theta) / pl.n_theta
     Wp = np.exp(+1j * TWO_PI * phase)                                    # [n_theta, K+1]
-    P = (TWO_PI / pl.n_theta) * np.einsum("njk,lk->njl", D, Wp)          # [n, n_xi, n_theta]
-    P = P.reshape(n, -1)
+    P = (TWO_PI / pl.n_theta) * (D @ Wp.T)                               # [n, n_xi, n_theta]: sum over k
+    return P.reshape(n, -1)
+
+
+def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096, ring_filter=None) -> np.ndarray:
+    """(T b)(x) = Re sum_{k=-kmax..kmax} sum_q b_{kq} conj(M_{kq}(x)), with b_{-k} = conj(b_k).
+
+    M_{kq}(x) is the row of T* for coefficient (k, q): Eq.(nufft), Eq.(1DFFT)
+    and Eq.(a) composed.  Folding +-k gives weight 1 for k = 0 and 2 for k > 0.
+    Computed as the transpose of each step in turn: the radial sum, the angular
+    sum, then the direct type-1 sum over the polar nodes.
+
+    ring_filter (optional, [n_xi]) multiplies the spectrum on ring j by H(xi_j) after the
+    radial sum: the image of a radially symmetric Fourier filter H applied to the
+    band-limited synthesis (the convolution of Sec. VI-C's CTF workload).
+    """
+    P = adjoint_polar(b, pl, ring_filter)
+    n = P.shape[0]
     x = pixel_coords(pl.L)
     xi1, xi2 = polar_nodes(pl)
     xi1 = xi1.ravel()
@@ -415,4 +424,20 @@ def adjoint(b: np.ndarray, pl: Plan, node_block: int = 4096, ring_filter=None) -
         for i in range(n):
             # sum over the nodes b of e1[b, i1] P[b] e2[b, i2], as one matrix product
             out[i] += ((e1 * P[i, s:s + node_block, None]).T @ e2).real
+    return out
+
+
+def adjoint_pixels(b: np.ndarray, pl: Plan, rows, cols) -> np.ndarray:
+    """The same (T b)(x) as ``adjoint``, evaluated only at the pixels (rows[t], cols[t])
+    (array indices, axis 0 then axis 1): the type-1 sum over every polar node, term by
+    node, at each listed pixel.  Returns float64 [n, len(rows)]."""
+    P = adjoint_polar(b, pl)
+    x = pixel_coords(pl.L)
+    xi1, xi2 = polar_nodes(pl)
+    xi1 = xi1.ravel()
+    xi2 = xi2.ravel()
+    out = np.empty((P.shape[0], len(rows)), dtype=np.float64)
+    for t, (r, c) in enumerate(zip(rows, cols)):
+        e = np.exp(+1j * TWO_PI * (xi1 * x[r] + xi2 * x[c]))            # [nodes]
+        out[:, t] = (P @ e).real
     return out

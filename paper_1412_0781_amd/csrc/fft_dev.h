@@ -106,6 +106,42 @@ struct Dft<5> {
   }
 };
 
+// Prime-factor (Good-Thomas) DFT of length N1 * N2 with coprime factors: no twiddles between
+// the two passes.  The input x at (N2 n1 + N1 n2) mod N forms N2 DFTs of length N1 over n1;
+// their outputs at k1 form N1 DFTs of length N2 over n2; output (k1, k2) is X at
+// (N2 u k1 + N1 v k2) mod N, with u N2 = 1 mod N1 and v N1 = 1 mod N2 (Chinese remainders).
+constexpr int mod_inverse(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+template <int N1, int N2>
+struct DftPfa {
+  static constexpr int N = N1 * N2, U = mod_inverse(N2 % N1, N1), V = mod_inverse(N1 % N2, N2);
+  __device__ __forceinline__ static void run(float2* v, const float2*, int, int) {
+    float2 a[N2][N1];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2)
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[(N2 * n1 + N1 * n2) % N];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) Dft<N1>::run(a[n2], nullptr, 0, 0);
+    float2 b[N1][N2];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) b[k1][n2] = a[n2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) Dft<N2>::run(b[k1], nullptr, 0, 0);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) v[(N2 * U * k1 + N1 * V * k2) % N] = b[k1][k2];
+  }
+};
+template <>
+struct Dft<12> : DftPfa<4, 3> {};
+
 // Generic odd prime R <= 31: direct O(R^2) DFT with roots taken from the twiddle table of length n.
 template <int RMAX>
 __device__ __forceinline__ void dft_generic(float2* v, int R, const float2* tw, int n) {
@@ -361,17 +397,85 @@ __device__ __forceinline__ void fft_pow2_inplace(float2* buf, const float2* __re
   }
 }
 
+// The same in-place padded stage for a compile-time length that is not a power of two
+// (2, 3, 5-smooth, e.g. 720 = 12 * 12 * 5): radix 12 (a prime-factor 4 x 3 butterfly)
+// while the remaining length allows it, then 8, 4, 5, 3, 2, so that 720 takes three
+// stages instead of the five of its prime-power split.  A thread takes
+// ceil(COUNT * N / R / NT) butterflies per stage.
+constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+constexpr int mixed_stage_radix(int rem) {
+  return rem % 12 == 0 ? 12 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 5 == 0 ? 5 : rem % 3 == 0 ? 3 : 2;
+}
+constexpr bool mixed_supported(int n) {
+  while (n > 1) {
+    const int r = mixed_stage_radix(n);
+    if (n % r != 0) return false;
+    n /= r;
+  }
+  return n == 1;
+}
+
+template <int N, int R, int NS, int COUNT, int STRIDE, int NT>
+__device__ __forceinline__ void fft_stage_mixed(float2* buf, const float2* __restrict__ tw, unsigned tid) {
+  constexpr unsigned NB = N / R, TWS = N / (NS * R), TOTAL = COUNT * NB, BM = (TOTAL + NT - 1) / NT;
+  static_assert(N % R == 0, "the radix divides the remaining length");
+  float2 v[BM][R];
+#pragma unroll
+  for (unsigned b = 0; b < BM; ++b) {
+    const unsigned idx = tid + b * NT;
+    if (idx < TOTAL) {
+      const unsigned t = idx / NB, j = idx % NB;
+      const float2* src = buf + t * STRIDE;
+#pragma unroll
+      for (unsigned r = 0; r < R; ++r) v[b][r] = src[fpad(j + r * NB)];
+    }
+  }
+  stage_barrier<true>();
+#pragma unroll
+  for (unsigned b = 0; b < BM; ++b) {
+    const unsigned idx = tid + b * NT;
+    if (idx < TOTAL) {
+      const unsigned t = idx / NB, j = idx % NB, k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (unsigned r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[k * r * TWS]);
+      }
+      Dft<R>::run(v[b], tw, N, R);
+      float2* dst = buf + t * STRIDE;
+      const unsigned base = (j - k) * R + k;
+#pragma unroll
+      for (unsigned r = 0; r < R; ++r) dst[fpad(base + r * NS)] = v[b][r];
+    }
+  }
+  stage_barrier<true>();
+}
+
+template <int N, int COUNT, int STRIDE, int NT, int NS = 1>
+__device__ __forceinline__ void fft_mixed_inplace(float2* buf, const float2* __restrict__ tw, unsigned tid) {
+  if constexpr (NS < N) {
+    constexpr int R = mixed_stage_radix(N / NS);
+    fft_stage_mixed<N, R, NS, COUNT, STRIDE, NT>(buf, tw, tid);
+    fft_mixed_inplace<N, COUNT, STRIDE, NT, NS * R>(buf, tw, tid);
+  }
+}
+
 // The FFT of the streaming kernels (1024 threads, padded in-place layout, LDS twiddles):
-// the compile-time form for NC > 0 (NC = d.n), the run-time form for NC = 0.  In the
-// compile-time form the thread index passes through an empty asm statement, so that the
-// stages' addresses are formed here rather than held in registers across the caller's
-// loop (they depend on nothing else that changes).
+// the compile-time forms for NC > 0 (NC = d.n; powers of two and the mixed-radix lengths
+// above), the run-time form for NC = 0.  In the compile-time forms the thread index
+// passes through an empty asm statement, so that the stages' addresses are formed here
+// rather than held in registers across the caller's loop (they depend on nothing else
+// that changes).
 template <int NC, int COUNT>
 __device__ __forceinline__ void fft_stream(float2* buf, int stride, const FftDesc& d, const float2* __restrict__ tw) {
   if constexpr (NC > 0) {
     unsigned tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    fft_pow2_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+    if constexpr (is_pow2(NC)) {
+      fft_pow2_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+    } else {
+      static_assert(mixed_supported(NC), "a length of radices 12, 8, 4, 5, 3, 2");
+      fft_mixed_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+    }
   } else {
     fft_lds_inplace_tw<true, true>(buf, COUNT, stride, d, tw);
   }

@@ -168,19 +168,24 @@ __global__ void k_fwd_cols(const float2* __restrict__ g1, float2* __restrict__ g
 // registers before the current unit is transformed and written, the FFT reads its
 // twiddles from LDS and meets at LDS-only barriers, so those loads stay in flight.
 // ---------------------------------------------------------------------------
-constexpr int kGridStreamN = 512;   // largest grid side of the streaming forms
-constexpr int kGridStreamPF = 8;    // input values per thread held for the next unit
+constexpr int kGridStreamN = 512;   // largest power-of-two grid side of the streaming forms
+constexpr int kStreamMixedN = 720;  // the compile-time mixed-radix length (L = 360 grid, R = 180 rings)
+// LDS and prefetch registers of a streaming kernel are sized for the larger of its own
+// compile-time length and the largest power-of-two one; a kernel longer than 512 holds one
+// workgroup per compute unit (its LDS), so it may take twice the registers.
+constexpr int stream_cap(int nc, int base) { return nc > base ? nc : base; }
+constexpr int stream_waves(int nc) { return nc > kGridStreamN ? 4 : 8; }
 
 // rows: unit = (image, 16 row pairs); rows a = 2 p0 .. 2 p0 + 31 of the image
 template <int NC>
-__global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
+__global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
                                                              const float* __restrict__ deconv, FftDesc fd,
                                                              const float2* __restrict__ tw, int L, int M2, int hw,
                                                              int nimg, int U, FastDiv dL4, FastDiv dZ) {
-  constexpr int RP = 16;
-  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
-  __shared__ float2 s_tw[kGridStreamN];
-  __shared__ float s_dec[kGridStreamN / 2];
+  constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
+  __shared__ float2 s_tw[NM];
+  __shared__ float s_dec[NM / 2];
   const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;  // row blocks per image
@@ -191,8 +196,8 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
   for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
   for (int i = tid; i < L; i += nthr) s_dec[i] = deconv[i];
   __syncthreads();
-  // one item = four consecutive pixels of a row (L % 4 == 0); rows past L read as zero
-  constexpr int PF = kGridStreamPF / 4;
+  // one item = four consecutive pixels of a row (L % 4 == 0, L <= N / 2); rows past L read as zero
+  constexpr int PF = (2 * RP * (NM / 2) / 4 + 1023) / 1024;
   const int L4 = L / 4, nval = 2 * RP * L4;
   float4 pre[PF];
   auto load = [&](int u) {
@@ -261,13 +266,13 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_rows_stream(const float* __rest
 
 // columns: unit = (stored row m2, image group); output G [M2][group][N][16]
 template <int NC>
-__global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
+__global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
                                                              FftDesc fd, const float2* __restrict__ tw, int L,
                                                              int M2, int nimg, int ngrp, int U, FastDiv dL,
                                                              FastDiv dZ) {
-  constexpr int G = kImgGroup;
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
-  __shared__ float2 s_tw[kGridStreamN];
+  constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
+  __shared__ float2 s_tw[NM];
   const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = M2 * ngrp;
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(1024, 8) void k_fwd_cols_stream(const float2* __res
   const int x0 = -((L - 1 + 1) / 2);
   for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
   __syncthreads();
-  constexpr int PF = kGridStreamPF / 2;
+  constexpr int PF = (G * (NM / 2) + 1023) / 1024;  // L <= N / 2
   const int nval = G * L;
   float2 pre[PF];
   // unit u = (m2, group): groups vary fastest, so consecutive units write consecutive runs of G
@@ -504,16 +509,16 @@ __global__ void k_fwd_angular(const float2* __restrict__ P, float2* __restrict__
 constexpr int kAngStreamH = 512;  // largest angular half length of the streaming form
 
 template <int NC>
-__global__ __launch_bounds__(1024, 8) void k_fwd_angular_stream(const float2* __restrict__ P, float2* __restrict__ Fh,
+__global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_angular_stream(const float2* __restrict__ P, float2* __restrict__ Fh,
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const float2* __restrict__ angtw,
                                                              const int* __restrict__ kring, int n_xi, int K,
                                                              int ngrp, int U, float scale) {
-  constexpr int G = kImgGroup;
-  constexpr int PF = kAngStreamH * G / 2 / 1024;  // (m, gg) items per thread at H = 512
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];  // packed transforms, padded
-  __shared__ float2 s_tw[kAngStreamH];
-  __shared__ float2 s_angtw[kAngStreamH];
+  constexpr int G = kImgGroup, HM = stream_cap(NC, kAngStreamH);
+  constexpr int PF = (HM * G / 2 + 1023) / 1024;  // (m, gg) items per thread at the largest H
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(HM - 1) + 2)];  // packed transforms, padded
+  __shared__ float2 s_tw[HM];
+  __shared__ float2 s_angtw[HM];
   const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
@@ -642,15 +647,15 @@ __global__ void k_adj_angular(const float2* __restrict__ D, float2* __restrict__
 // loads stay in flight.
 // ---------------------------------------------------------------------------
 template <int NC>
-__global__ __launch_bounds__(1024, 8) void k_adj_angular_stream(const float2* __restrict__ D, float2* __restrict__ Q,
+__global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(const float2* __restrict__ D, float2* __restrict__ Q,
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const float2* __restrict__ angtw, int n_xi, int K,
                                                              int nimg, int ngrp, int U, float scale) {
-  constexpr int G = kImgGroup;
-  constexpr int PF = kAngStreamH * G / 2 / 1024;  // pairs of spectrum values per thread (K + 1 <= H <= 512)
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kAngStreamH - 1) + 2)];
-  __shared__ float2 s_tw[kAngStreamH];
-  __shared__ float2 s_angtw[kAngStreamH];
+  constexpr int G = kImgGroup, HM = stream_cap(NC, kAngStreamH);
+  constexpr int PF = (HM * G / 2 + 1023) / 1024;  // pairs of spectrum values per thread (K + 1 <= H)
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(HM - 1) + 2)];
+  __shared__ float2 s_tw[HM];
+  __shared__ float2 s_angtw[HM];
   const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
@@ -940,10 +945,10 @@ template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __restrict__ Y, float2* __restrict__ Zc,
                                                             FftDesc fd, const float2* __restrict__ tw, int L,
                                                             int nimg, int ngrp, int U, FastDiv dL) {
-  constexpr int G = kImgGroup;
-  constexpr int PF = kGridStreamN * G / 2 / 1024;  // pairs of values per thread
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(kGridStreamN - 1) + 2)];
-  __shared__ float2 s_tw[kGridStreamN];
+  constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
+  constexpr int PF = (NM * G / 2 + 1023) / 1024;  // pairs of values per thread
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
+  __shared__ float2 s_tw[NM];
   const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = Nh * ngrp;
@@ -1003,11 +1008,11 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
                                                             const float* __restrict__ deconv, FftDesc fd,
                                                             const float2* __restrict__ tw, int L, int nimg, int U,
                                                             FastDiv dL) {
-  constexpr int RP = 16;
-  constexpr int PF = ((kGridStreamN / 2 + 1) * RP + 1023) / 1024;  // row-pair values per thread
-  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(kGridStreamN - 1) + 2)];
-  __shared__ float2 s_tw[kGridStreamN];
-  __shared__ float s_dec[kGridStreamN / 2];
+  constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
+  constexpr int PF = ((NM / 2 + 1) * RP + 1023) / 1024;  // row-pair values per thread
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
+  __shared__ float2 s_tw[NM];
+  __shared__ float s_dec[NM / 2];
   const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;
@@ -1221,11 +1226,22 @@ hipError_t configure_kernels() {
   return hipSuccess;
 }
 
-// Launch a streaming kernel compiled for its transform length n (a power of two from 64
-// to 512), or its run-time-length form for any other n.
-#define FB_LAUNCH_POW2(K, n, grid, st, ...)                                                 \
+// Transform lengths the streaming kernels take: powers of two up to nmax whose radices are
+// 8 and 4 (compiled for 64 to 512, run-time form below 64), and the mixed-radix 720.
+static bool stream_length(const FftDesc& d, int nmax) {
+  return d.n == kStreamMixedN || (d.n <= nmax && fft_inplace_capacity(d, kFftThreads) >= kImgGroup * d.n);
+}
+// Resident workgroups per compute unit of a streaming kernel of length n (its LDS).
+static int stream_per_cu(int n) { return n > kGridStreamN ? 1 : 2; }
+
+// Launch a streaming kernel compiled for its transform length n (720, or a power of two
+// from 64 to 512), or its run-time-length form for any other n.
+#define FB_LAUNCH_STREAM(K, n, grid, st, ...)                                               \
   do {                                                                                      \
     switch (n) {                                                                            \
+      case kStreamMixedN:                                                                   \
+        hipLaunchKernelGGL(K<kStreamMixedN>, grid, dim3(1024), 0, st, __VA_ARGS__);         \
+        break;                                                                              \
       case 512: hipLaunchKernelGGL(K<512>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
       case 256: hipLaunchKernelGGL(K<256>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
       case 128: hipLaunchKernelGGL(K<128>, grid, dim3(1024), 0, st, __VA_ARGS__); break;    \
@@ -1238,23 +1254,22 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
                                 hipStream_t st) {
   const int N = pl.N, L = pl.L;
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
-  // streaming forms: 16 transforms of length N <= 512 in place with 1024 threads, and the
-  // inputs of one unit (32 rows or 16 columns of L values) in kGridStreamPF values per thread
-  const bool stream_ok = N <= kGridStreamN && fft_inplace_capacity(pl.fft_grid, 1024) >= 16 * N &&
-                         32 * L <= kGridStreamPF * 1024 && L % 4 == 0;
+  // streaming forms: 16 transforms in place with 1024 threads; the inputs of one unit (32
+  // rows or 16 columns of L <= N / 2 values) are held in registers, the rows as float4
+  const bool stream_ok = stream_length(pl.fft_grid, kGridStreamN) && L % 4 == 0;
   if (stream_ok) {
     const int nrb = ((L + 1) / 2 + 15) / 16;
     const long long ur = (long long)nimg * nrb;
-    const int Ur = fixed_units(pl, ur, 2, kGridUnits);
+    const int Ur = fixed_units(pl, ur, stream_per_cu(N), kGridUnits);
     pl.prof.begin(ST_FWD_ROWS, st);
-    FB_LAUNCH_POW2(k_fwd_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
+    FB_LAUNCH_STREAM(k_fwd_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
                        images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, Ur,
                        make_fastdiv(L / 4), make_fastdiv(N - L));
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
     pl.prof.begin(ST_FWD_COLS, st);
-    const int Uc = stream_units(pl, uc, 2, kGridUnits);
-    FB_LAUNCH_POW2(k_fwd_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
+    const int Uc = stream_units(pl, uc, stream_per_cu(N), kGridUnits);
+    FB_LAUNCH_STREAM(k_fwd_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
                        bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L),
                        make_fastdiv(N - L));
     pl.prof.end(st);
@@ -1286,13 +1301,12 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
 hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, int nimg, hipStream_t st) {
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
   const float scale = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
-  const bool stream_ok = pl.H % 8 == 0 && pl.H <= kAngStreamH && pl.k_max < pl.H &&
-                         fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
+  const bool stream_ok = pl.H % 8 == 0 && stream_length(pl.fft_ang, kAngStreamH) && pl.k_max < pl.H;
   if (stream_ok) {
     const int units = pl.n_xi * ngrp;
-    const int U = fixed_units(pl, units, 2, kAngularUnits);
+    const int U = fixed_units(pl, units, stream_per_cu(pl.H), kAngularUnits);
     pl.prof.begin(ST_FWD_ANGULAR, st);
-    FB_LAUNCH_POW2(k_fwd_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, P,
+    FB_LAUNCH_STREAM(k_fwd_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, P,
                        Fh, pl.fft_ang, pl.d_tw, pl.d_angtw, pl.d_kring, pl.n_xi, pl.k_max, ngrp, U, scale);
     pl.prof.end(st);
     return hipGetLastError();
@@ -1308,14 +1322,13 @@ hipError_t launch_forward_angular(const Plan& pl, const float2* P, float2* Fh, i
 
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st) {
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
-  const bool stream_ok = pl.H % 8 == 0 && pl.H <= kAngStreamH && pl.k_max < pl.H &&
-                         fft_inplace_capacity(pl.fft_ang, 1024) >= kImgGroup * pl.H;
+  const bool stream_ok = pl.H % 8 == 0 && stream_length(pl.fft_ang, kAngStreamH) && pl.k_max < pl.H;
   if (stream_ok) {
     const long long units = (long long)pl.n_xi * ngrp;
-    const int U = fixed_units(pl, units, 2, kAngularUnits);
+    const int U = fixed_units(pl, units, stream_per_cu(pl.H), kAngularUnits);
     const float sc = (float)(2.0 * 3.14159265358979323846 / pl.n_theta);
     pl.prof.begin(ST_ADJ_ANGULAR, st);
-    FB_LAUNCH_POW2(k_adj_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, D, Q,
+    FB_LAUNCH_STREAM(k_adj_angular_stream, pl.H, dim3((unsigned)((units + U - 1) / U)), st, D, Q,
                        pl.fft_ang, pl.d_tw, pl.d_angtw, pl.n_xi, pl.k_max, nimg, ngrp, U, sc);
     pl.prof.end(st);
     return hipGetLastError();
@@ -1342,18 +1355,18 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   hipLaunchKernelGGL((k_adj_spread<NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
                      pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sent, N, Nh, pl.H, ngrp, nsl);
   pl.prof.end(st);
-  const bool stream_ok = N <= kGridStreamN && fft_inplace_capacity(pl.fft_grid, 1024) >= 16 * N && L % 2 == 0;
+  const bool stream_ok = stream_length(pl.fft_grid, kGridStreamN) && L % 2 == 0;
   if (stream_ok) {
     const long long uc = (long long)Nh * ngrp;
     pl.prof.begin(ST_ADJ_COLS, st);
     const int Uc = stream_units(pl, uc, 1, kGridUnits);
-    FB_LAUNCH_POW2(k_adj_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
+    FB_LAUNCH_STREAM(k_adj_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
                        bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, Uc, make_fastdiv(L));
     pl.prof.end(st);
     const long long ur = (long long)nimg * (((L + 1) / 2 + 15) / 16);
     pl.prof.begin(ST_ADJ_ROWS, st);
     const int Ur = stream_units(pl, ur, 1, kGridUnits);
-    FB_LAUNCH_POW2(k_adj_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
+    FB_LAUNCH_STREAM(k_adj_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
                        bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, Ur, make_fastdiv(L));
     pl.prof.end(st);
     return hipGetLastError();

@@ -1,7 +1,9 @@
 """Parity at the full workload sizes, through the C ABI.
 
 * The L = 360, R = 180 shape (oversampled grid 720 = 2^4 3^2 5 and angular half length
-  720: the mixed-radix FFT kernels) on whole images.
+  720: the compile-time mixed-radix streaming FFT kernels) on whole images: the expansion
+  against the oracle, the adjoint against the oracle at sampled pixels, and the two against
+  each other by the dot-product identity.
 * n = 100 000 images at L = 256 (BF16x3) and L = 128 (FP32), expanded in the passes the
   benchmark times (up to 2048 images per pass).  The oracle cannot expand 10^5 images, so
   the outputs are sampled: sparse images (48 nonzero pixels, which the oracle evaluates
@@ -18,13 +20,15 @@ the k = 0 sums within the FP32 partial-sum bound; eigenvalues 1e-9 of the block'
 against LAPACK on the same blocks, 1e-5 against the oracle's.
 """
 
+import functools
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from gpu_util import as_complex, dictionary_images, max_block_rel, rel_l2, sparse_images
-from paper_1412_0781_amd import Plan
+from paper_1412_0781_amd import Plan, synth
 from paper_1412_0781_amd.fb import synth_normals
 
 pytestmark = pytest.mark.gpu
@@ -37,11 +41,18 @@ def _dev():
     yield
 
 
+@functools.lru_cache(maxsize=None)
+def _oracle_plan(L, c, R):
+    """One oracle plan per shape for the module (its radial table at L = 360 takes tens of
+    seconds of scipy Bessel evaluations)."""
+    return oracle.plan(L, c, R)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_l360_shape_matches_oracle(precision):
     L, c, R = 360, 0.5, 180.0
     print(f"[fullsize] L={L} {precision}", flush=True)
-    po = oracle.plan(L, c, R)
+    po = _oracle_plan(L, c, R)
     dense, pix = sparse_images(L, 3, 48, seed=11)
     ref = oracle.expand_sparse(pix, po)
     plan = Plan(L, c, R)
@@ -54,6 +65,49 @@ def test_l360_shape_matches_oracle(precision):
     print(f"  worst k block {blk:.3e}", flush=True)
     assert blk <= TOL
     assert np.all(got[:, :po.p[0]].imag == 0.0)
+
+
+def test_l360_adjoint_matches_oracle():
+    """The adjoint at L = 360 (radial and angular transposes, spread, 720-point inverse
+    column and row transforms) for 3 images of random coefficients, at 96 scattered pixels
+    plus the four corners and the centre, against the oracle's type-1 sum at those pixels."""
+    L, c, R = 360, 0.5, 180.0
+    print(f"[fullsize] adjoint L={L}", flush=True)
+    po = _oracle_plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(21, np.arange(3), k, q)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    got = plan.adjoint(bt).cpu().numpy()
+    rng = np.random.default_rng(12)
+    rows = list(rng.integers(0, L, 96)) + [0, 0, L - 1, L - 1, L // 2]
+    cols = list(rng.integers(0, L, 96)) + [0, L - 1, 0, L - 1, L // 2]
+    ref = oracle.adjoint_pixels(b, po, rows, cols)
+    for i in range(len(b)):
+        e = rel_l2(got[i, rows, cols], ref[i])
+        print(f"  image {i}: rel-L2 at {len(rows)} pixels {e:.3e}", flush=True)
+        assert e <= TOL
+
+
+def test_l360_dot_product_identity():
+    """<T* I, b> = <I, T b> at L = 360 with I = T b, so that both sides are close to
+    ||T b||^2 and cannot cancel; 1e-6 relative in FP32."""
+    L, c, R = 360, 0.5, 180.0
+    print(f"[fullsize] dot test L={L}", flush=True)
+    po = _oracle_plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(22, np.arange(4), k, q)
+    bc = b.astype(np.complex64).astype(np.complex128)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    img = plan.adjoint(bt)
+    a = as_complex(plan.expand(img))
+    I = img.cpu().numpy().astype(np.float64)
+    lhs = oracle.coeff_inner(a, bc, po)
+    rhs = np.sum(I * I, axis=(1, 2))
+    rel = np.abs(lhs - rhs) / np.abs(rhs)
+    print(f"  dot test {np.max(rel):.3e}", flush=True)
+    assert np.max(rel) <= 1e-6
 
 
 @pytest.mark.parametrize("L,R,precision", [(256, 128.0, "bf16x3"), (128, 64.0, "fp32")])

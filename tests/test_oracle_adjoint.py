@@ -105,3 +105,28 @@ def test_adjoint_is_synthesis_left_inverse_on_basis():
         e[0, pl.coef_off[k] + q - 1] = 1.0
         back = oracle.expand(oracle.adjoint(e, pl), pl)[0]
         assert np.max(np.abs(back - e[0])) < 1e-2
+
+
+@pytest.mark.parametrize("k,q", [(0, 4), (3, 2), (12, 1)])
+def test_adjoint_pixels_matches_closed_form(k, q):
+    """The pixel-sampled adjoint at scattered pixels inside the disk against the closed form
+    of Eq.(IFT_FB), and against the whole-image adjoint for random coefficients."""
+    L, c, R = 32, 0.5, 16
+    pl = oracle.plan(L, c, R)
+    x = oracle.pixel_coords(L)
+    rng = np.random.default_rng(7)
+    rows, cols = [], []
+    while len(rows) < 24:
+        r, cc = rng.integers(0, L, 2)
+        if math.hypot(x[r], x[cc]) < R:
+            rows.append(int(r))
+            cols.append(int(cc))
+    e = np.zeros((1, pl.p_half), dtype=complex)
+    e[0, pl.coef_off[k] + q - 1] = 1.0
+    got = oracle.adjoint_pixels(e, pl, rows, cols)[0]
+    f = _ift_fb(pl, k, q, x[rows], x[cols])
+    ref = f.real if k == 0 else 2.0 * f.real
+    assert np.max(np.abs(got - ref)) <= 1e-7 * np.max(np.abs(ref))
+    b = _random_coeffs(pl, 2, 9)
+    full = oracle.adjoint(b, pl)
+    assert np.max(np.abs(oracle.adjoint_pixels(b, pl, rows, cols) - full[:, rows, cols])) <= 1e-12 * np.max(np.abs(full))
