@@ -264,12 +264,13 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
   }
 }
 
-// columns: unit = (stored row m2, image group); output G [M2][group][N][16]
+// columns: unit = (stored row m2, image group); output G [M2][group][N][16], of each row
+// only the centred m1 range gcols[m2] that the gather's boxes read
 template <int NC>
 __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
-                                                             FftDesc fd, const float2* __restrict__ tw, int L,
-                                                             int M2, int nimg, int ngrp, int U, FastDiv dL,
-                                                             FastDiv dZ) {
+                                                             FftDesc fd, const float2* __restrict__ tw,
+                                                             const int2* __restrict__ gcols, int L, int M2,
+                                                             int nimg, int ngrp, int U, FastDiv dL, FastDiv dZ) {
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
   __shared__ float2 s_tw[NM];
@@ -319,7 +320,11 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(cons
     fft_stream<NC, G>(s_buf, S, fd, s_tw);
     const int c = tid & (G - 1);
     float2* dst = g + ((size_t)m2 * ngrp + grp) * N * G + c;
-    for (int m1 = tid / G; m1 < N; m1 += nthr / G) st_out(&dst[(size_t)m1 * G], s_buf[c * S + fpad(m1)]);
+    const int2 rg = gcols[m2];
+    for (int ic = rg.x + tid / G; ic <= rg.y; ic += nthr / G) {
+      const int m1 = ic < 0 ? ic + N : ic;
+      st_out(&dst[(size_t)m1 * G], s_buf[c * S + fpad(m1)]);
+    }
     stage_barrier<true>();
   }
 }
@@ -1270,8 +1275,8 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     pl.prof.begin(ST_FWD_COLS, st);
     const int Uc = stream_units(pl, uc, stream_per_cu(N), kGridUnits);
     FB_LAUNCH_STREAM(k_fwd_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
-                       bufA, bufB, pl.fft_grid, pl.d_tw, L, pl.M2, nimg, ngrp, Uc, make_fastdiv(L),
-                       make_fastdiv(N - L));
+                       bufA, bufB, pl.fft_grid, pl.d_tw, (const int2*)pl.d_gcols, L, pl.M2, nimg, ngrp, Uc,
+                       make_fastdiv(L), make_fastdiv(N - L));
     pl.prof.end(st);
   } else {
     FftLaunch fr = fft_launch(pl.fft_grid, N + 1);

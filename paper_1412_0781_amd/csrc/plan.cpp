@@ -215,6 +215,20 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
           pl.gitems.push_back(it);
         }
       }
+    // the centred hull of the box columns read in each row (a box of a cell near m1 = N/2
+    // wraps, and its row's hull is then the whole row)
+    pl.gcols.assign(2 * (size_t)pl.M2, 0);
+    for (int r = 0; r < pl.M2; ++r) {
+      pl.gcols[2 * r] = pl.N;
+      pl.gcols[2 * r + 1] = -pl.N - 1;
+    }
+    for (const GatherItem& it : pl.gitems)
+      for (int r = it.c2; r < std::min(it.c2 + BW, pl.M2); ++r)
+        for (int cc = 0; cc < BW; ++cc) {
+          const int col = (it.c1 + cc) % pl.N, ic = col < pl.N / 2 ? col : col - pl.N;
+          pl.gcols[2 * r] = std::min(pl.gcols[2 * r], ic);
+          pl.gcols[2 * r + 1] = std::max(pl.gcols[2 * r + 1], ic);
+        }
   }
 
   // FFTs: grid side N and the angular half length H
@@ -500,6 +514,7 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_items_spca, pl.items_spca.data(), pl.items_spca.size()));
   FB_HIP_TRY(upload(&pl.d_jmin, pl.jmin.data(), pl.jmin.size()));
   FB_HIP_TRY(upload(&pl.d_kring, pl.kring.data(), pl.kring.size()));
+  FB_HIP_TRY(upload(&pl.d_gcols, pl.gcols.data(), pl.gcols.size()));
   pl.has_device = true;
   return FB_OK;
 }
@@ -510,7 +525,7 @@ void free_device(Plan& pl) {
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
                   pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca,
-                  pl.d_jmin,      pl.d_kring};
+                  pl.d_jmin,      pl.d_kring,     pl.d_gcols};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   pl.d_radial = nullptr;
@@ -534,7 +549,7 @@ void free_device(Plan& pl) {
   pl.d_sseg = nullptr;
   pl.d_sent = nullptr;
   pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = pl.d_items_spca = nullptr;
-  pl.d_jmin = pl.d_kring = nullptr;
+  pl.d_jmin = pl.d_kring = pl.d_gcols = nullptr;
   pl.has_device = false;
 }
 

@@ -213,6 +213,10 @@ struct Plan {
   std::vector<NodeTap> nodes;      // n_xi * H, node n = j * H + l
   std::vector<GatherNode> gnodes;  // nodes sorted by gather cell
   std::vector<GatherItem> gitems;  // (cell, node chunk) work items
+  // per stored grid row m2 (M2 rows): the centred m1 range [lo, hi] (m1 - N for m1 >= N/2)
+  // that holds every point some gather box reads (lo > hi if none); the streaming column
+  // pass stores only these points of G
+  std::vector<int> gcols;          // 2 * M2: lo, hi
   FftDesc fft_grid{}, fft_ang{};
   std::vector<float> tw;           // interleaved (re, im) twiddles of both FFT lengths
   std::vector<float> angtw;        // exp(-2 pi i k / n_theta), k = 0..H, interleaved
@@ -267,6 +271,7 @@ struct Plan {
   GemmItem* d_items_spca = nullptr;   // (k, 64-wide column tile) of the steerable-PCA products
   int* d_jmin = nullptr;              // k_max + 1
   int* d_kring = nullptr;             // n_xi
+  int* d_gcols = nullptr;             // 2 * M2
 };
 
 // Build host tables; returns FB_OK or an FB_ERR_* code.

@@ -51,6 +51,19 @@ int main() {
       bool ok = true;
       for (int k = 0; k <= pl.k_max; ++k) ok = ok && pl.jmin[k] >= 0 && pl.jmin[k] < pl.n_xi;
       check(ok, "every block reads at least one ring");
+      // the column pass's stored ranges: one centred interval per grid row, inside the row
+      ok = pl.gcols.size() == 2 * (size_t)pl.M2;
+      long long stored = 0;
+      for (int r = 0; ok && r < pl.M2; ++r) {
+        const int lo = pl.gcols[2 * r], hi = pl.gcols[2 * r + 1];
+        if (lo <= hi) {
+          ok = lo >= -pl.N / 2 && hi < pl.N - pl.N / 2;
+          stored += hi - lo + 1;
+        }
+      }
+      check(ok, "grid column ranges");
+      std::printf("  grid points stored by the column pass: %.3f of %d x %d\n", (double)stored / ((double)pl.M2 * pl.N),
+                  pl.M2, pl.N);
     } else {
       std::printf("\n");
     }
