@@ -375,60 +375,68 @@ __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // covariance accumulation (Eqs.(ck),(ck_0)), split over image slices.
-// grid: work items (k, 64-row tile m0, 64-column tile n0 >= m0) x S image slices.
-// The K dimension is (image, re/im): X[q][2i + r] = (Re, Im) a^i_{kq}, so
-// Re(A A^*) = X X^T.  A K chunk is 16 images = 32 columns; the next chunk is held in
-// registers while the current one is multiplied (the workgroup barriers wait for LDS
-// operations only, so those loads stay in flight across them).  In the BF16x3 form each
-// thread stores the hi and lo parts of four consecutive images of its row as two 16-byte
-// runs, which keeps the 64 rows' stores free of LDS bank conflicts.  FP32 tile sums are moved to FP64
-// registers every COV_FLUSH_COLS columns; each block writes its FP64 tile (and the
-// mirrored tile) into its slice's partial copy of G, which k_cov_reduce then adds
-// into G in slice order, so the result does not depend on scheduling.
-// The k = 0 imaginary parts are masked; the k = 0 diagonal tiles also sum S0.  With a
-// shift s (FP32 [p_0]) the k = 0 rows enter as a_{0q} - s_q, before the BF16 split, so
-// the sums stay of the order of the spread of the data rather than of its mean.
+// grid: work items x S image slices; a work item stages up to kCovSegs segments of 32
+// coefficients (rows) for every chunk of images and each of its kCovWaves waves forms one
+// 32 x 32 tile: the product of two segments of the same block k (eight waves of at most 128
+// registers: two workgroups per compute unit; the Hermitian form takes more registers and
+// runs one).  The K dimension is
+// (image, re/im): X[q][2i + r] = (Re, Im) a^i_{kq}, so Re(A A^*) = X X^T.  A K chunk is
+// 16 images = 32 columns; the next chunk is held in registers while the current one is
+// multiplied (the workgroup barriers wait for LDS operations only, so those loads stay in
+// flight across them).  In the BF16x3 form each thread stores the hi and lo parts of four
+// consecutive images of its row as two 16-byte runs, which keeps the stores free of LDS
+// bank conflicts.  FP32 tile sums are moved to FP64 registers every COV_FLUSH_COLS
+// columns; each wave writes its FP64 tile (and the mirrored tile) into its slice's partial
+// copy of G, which k_cov_reduce then adds into G in slice order, so the result does not
+// depend on scheduling.
+// The k = 0 imaginary parts are masked and the k = 0 rows also sum S0 (in the item that
+// owns the segment's sums).  With a shift s (FP32 [p_0]) the k = 0 rows enter as
+// a_{0q} - s_q, before the BF16 split, so the sums stay of the order of the spread of the
+// data rather than of its mean.
 // HERM also forms the imaginary part of A A^* for k > 0 (the Hermitian covariance
 // under rotations only): Im(A A^*) = Ai Ar^T - Ar Ai^T = X Y^T with the second operand
 // taken as Y[q][2i] = -Im a^i_{kq}, Y[q][2i + 1] = Re a^i_{kq}: one more product per
-// chunk from the same staged tiles.
+// chunk from the same staged rows.
 // ---------------------------------------------------------------------------
 constexpr int COV_FLUSH_COLS = 512;
 constexpr int COV_IMG = 16;                 // images per K chunk
 constexpr int COV_K = 2 * COV_IMG;          // columns per K chunk
+constexpr int COV_ROWS = kCovSegs * kCovSeg;  // staged rows per item
+constexpr int COV_THREADS = 64 * kCovWaves;
 static_assert(COV_K == BKH, "BF16 tiles hold one K chunk");
+static_assert(kCovSeg == 32, "one 32 x 32 MFMA tile per wave");
+static_assert(COV_THREADS == 4 * COV_ROWS, "four loader threads (four images each) per staged row");
 
 template <int PREC>
 struct CovSmem;
 template <>
 struct CovSmem<0> {
-  float As[COV_K][BM + 4];
-  float Bs[COV_K][BN + 4];
+  float As[COV_K][COV_ROWS + 4];
 };
 template <>
 struct CovSmem<1> {
-  unsigned short Ah[BM][LDH], Al[BM][LDH];
-  unsigned short Bh[BN][LDH], Bl[BN][LDH];
+  unsigned short Ah[COV_ROWS][LDH], Al[COV_ROWS][LDH];
 };
 
-__device__ __forceinline__ void mma_f32_k32(const float (*As)[BM + 4], const float (*Bs)[BN + 4], f32x16& acc,
-                                            int wm, int wn, int lane) {
+// rows ra0.. and rb0.. of the staged chunk (32 each): acc += X_a X_b^T
+__device__ __forceinline__ void mma_f32_k32(const float (*As)[COV_ROWS + 4], f32x16& acc, int ra0, int rb0,
+                                            int lane) {
 #pragma unroll
   for (int kk = 0; kk < COV_K; kk += 2) {
-    float a = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
-    float b = Bs[kk + (lane >> 5)][wn * 32 + (lane & 31)];
+    float a = As[kk + (lane >> 5)][ra0 + (lane & 31)];
+    float b = As[kk + (lane >> 5)][rb0 + (lane & 31)];
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
   }
 }
 
-// X Y^T with Y[2i] = -X[2i + 1], Y[2i + 1] = X[2i] on the second operand (FP32 form)
-__device__ __forceinline__ void mma_f32_k32_im(const float (*As)[BM + 4], const float (*Bs)[BN + 4], f32x16& acc,
-                                               int wm, int wn, int lane) {
+// X_a Y_b^T with Y[2i] = -X[2i + 1], Y[2i + 1] = X[2i] on the second operand (FP32 form)
+__device__ __forceinline__ void mma_f32_k32_im(const float (*As)[COV_ROWS + 4], f32x16& acc, int ra0, int rb0,
+                                               int lane) {
   const int h = lane >> 5;
 #pragma unroll
   for (int kk = 0; kk < COV_K; kk += 2) {
-    float a = As[kk + h][wm * 32 + (lane & 31)];
-    float b = Bs[kk + 1 - h][wn * 32 + (lane & 31)];
+    float a = As[kk + h][ra0 + (lane & 31)];
+    float b = As[kk + 1 - h][rb0 + (lane & 31)];
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, h ? b : -b, acc, 0, 0, 0);
   }
 }
@@ -446,14 +454,13 @@ __device__ __forceinline__ bf16x8 swap_neg_pairs(bf16x8 x) {
 // BF16x3 products of the real part (acc) and, when im, of the imaginary part (acc_im)
 template <bool IM>
 __device__ __forceinline__ void mma_bf16x3_cov(const unsigned short (*Ah)[LDH], const unsigned short (*Al)[LDH],
-                                               const unsigned short (*Bh)[LDH], const unsigned short (*Bl)[LDH],
-                                               f32x16& acc, f32x16& acc_im, bool im, int wm, int wn, int lane) {
-  const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31);
+                                               f32x16& acc, f32x16& acc_im, bool im, int ra0, int rb0, int lane) {
+  const int ra = ra0 + (lane & 31), rb = rb0 + (lane & 31);
 #pragma unroll
   for (int kb = 0; kb < BKH; kb += 16) {
     const int c = kb + 8 * (lane >> 5);
     bf16x8 ah = ld8(&Ah[ra][c]), al = ld8(&Al[ra][c]);
-    bf16x8 bh = ld8(&Bh[rb][c]), bl = ld8(&Bl[rb][c]);
+    bf16x8 bh = ld8(&Ah[rb][c]), bl = ld8(&Al[rb][c]);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
@@ -467,91 +474,71 @@ __device__ __forceinline__ void mma_bf16x3_cov(const unsigned short (*Ah)[LDH], 
 }
 
 template <int PREC, bool HERM>
-__global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ coeffs, double* __restrict__ partG,
-                                                    double* __restrict__ partS0, double* __restrict__ partGi,
-                                                    const float* __restrict__ shift,
-                                                    const GemmItem* __restrict__ items,
-                                                    const int* __restrict__ coef_off, const int* __restrict__ p,
-                                                    const long long* __restrict__ cov_off, long long n,
-                                                    long long p_half, int nitems, long long per, long long cov_size,
-                                                    int p0) {
+__global__ __launch_bounds__(COV_THREADS, HERM ? 1 : 4) void k_covariance(const float* __restrict__ coeffs,
+                                                            double* __restrict__ partG, double* __restrict__ partS0,
+                                                            double* __restrict__ partGi,
+                                                            const float* __restrict__ shift,
+                                                            const CovItem* __restrict__ items,
+                                                            const int* __restrict__ p,
+                                                            const long long* __restrict__ cov_off, long long n,
+                                                            long long p_half, int nitems, long long per,
+                                                            long long cov_size, int p0) {
   __shared__ __attribute__((aligned(16))) CovSmem<PREC> S;
-  __shared__ double dred[4][BM];
+  __shared__ double dred[4][COV_ROWS];
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int itx = lin % nitems, slice = lin / nitems;  // tiles of one k are neighbours on one XCD
-  const GemmItem it = items[itx];
-  const int k = it.k, m0 = it.t0, n0 = it.t1, pk = p[k], off = coef_off[k];
-  const bool diag = (m0 == n0);
-  const bool do_sum = (k == 0 && diag);
+  const int itx = lin % nitems, slice = lin / nitems;  // items of neighbouring k are neighbours on one XCD
+  const CovItem& it = items[itx];
   const long long i0 = (long long)slice * per, i1 = min(n, i0 + per);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  // loader: thread owns row q = tid & 63 of the tile for the four consecutive images
-  // 4 (tid >> 6) + u, u < 4, of each chunk (one 16-byte LDS store per operand in the BF16x3 form)
-  const int q = tid & 63, ib = tid >> 6;
-  const bool rowa = m0 + q < pk, rowb = n0 + q < pk;
-  const float2* srcA = (const float2*)coeffs + off + m0 + q;
-  const float2* srcB = (const float2*)coeffs + off + n0 + q;
-  const bool k0 = (k == 0);
-  const bool im = HERM && !k0;  // the imaginary part of a k = 0 block is zero
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // loader: thread owns staged row `row` (segment sg, row r of it) for the four consecutive
+  // images 4 ib + u, u < 4, of each chunk (one 16-byte LDS store per part in the BF16x3 form)
+  const int row = tid % COV_ROWS, ib = tid / COV_ROWS, sg = row / kCovSeg, r = row % kCovSeg;
+  const int kr = it.k[sg];
+  const bool valid = kr >= 0 && it.q0[sg] + r < p[max(kr, 0)];
+  const bool k0r = (kr == 0);
+  const bool do_sum = k0r && it.sum0[sg] && valid;
+  const float2* src = (const float2*)coeffs + it.row[sg] + r;
   // k = 0 rows enter shifted (rows past p_0 and images past the run stay exactly zero)
-  const float sha = (k0 && shift && rowa) ? shift[m0 + q] : 0.f;
-  const float shb = (k0 && shift && rowb) ? shift[n0 + q] : 0.f;
-  struct Regs {
-    float2 a[4], b[4];
-  };
-  auto gload = [&](long long c0, Regs& R) {
-    float2* ra = R.a;
-    float2* rb = R.b;
+  const float sh = (k0r && shift && valid) ? shift[it.q0[sg] + r] : 0.f;
+  // this wave's tile: segments ta <= tb of block kt
+  const int ta = it.ta[wave], tb = it.tb[wave];
+  const bool has = ta != 255;
+  const int kt = has ? it.k[ta] : 0;
+  const bool im = HERM && has && kt != 0;  // the imaginary part of a k = 0 block is zero
+  auto gload = [&](long long c0, float2 (&R)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       long long img = c0 + 4 * ib + u;
-      bool ok = img < i1;
-      ra[u] = (ok && rowa) ? srcA[img * p_half] : make_float2(0.f, 0.f);
-      if (!diag) rb[u] = (ok && rowb) ? srcB[img * p_half] : make_float2(0.f, 0.f);
-      if (k0) {
-        if (ok && rowa) ra[u].x -= sha;
-        if (!diag && ok && rowb) rb[u].x -= shb;
-        ra[u].y = 0.f;
-        rb[u].y = 0.f;
+      bool ok = img < i1 && valid;
+      R[u] = ok ? src[img * p_half] : make_float2(0.f, 0.f);
+      if (k0r) {
+        if (ok) R[u].x -= sh;
+        R[u].y = 0.f;
       }
     }
   };
   float ssum = 0.f;
-  auto lstore = [&](const Regs& R) {
-    const float2* ra = R.a;
-    const float2* rb = R.b;
+  auto lstore = [&](const float2 (&R)[4]) {
     if constexpr (PREC == 0) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int col = 2 * (4 * ib + u);
-        if (do_sum) ssum += ra[u].x;
-        S.As[col][q] = ra[u].x;
-        S.As[col + 1][q] = ra[u].y;
-        if (!diag) {
-          S.Bs[col][q] = rb[u].x;
-          S.Bs[col + 1][q] = rb[u].y;
-        }
+        if (do_sum) ssum += R[u].x;
+        S.As[col][row] = R[u].x;
+        S.As[col + 1][row] = R[u].y;
       }
     } else {
-      // columns 8 ib .. 8 ib + 7 of row q: four (re, im) pairs, hi and lo, 16 bytes each
-      uint4 h4, l4, hb, lb;
+      // columns 8 ib .. 8 ib + 7 of the row: four (re, im) pairs, hi and lo, 16 bytes each
+      uint4 h4, l4;
       unsigned* h = (unsigned*)&h4;
       unsigned* l = (unsigned*)&l4;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (do_sum) ssum += ra[u].x;
-        split_bf16_pair(ra[u].x, ra[u].y, h[u], l[u]);
+        if (do_sum) ssum += R[u].x;
+        split_bf16_pair(R[u].x, R[u].y, h[u], l[u]);
       }
-      *(uint4*)&S.Ah[q][8 * ib] = h4;
-      *(uint4*)&S.Al[q][8 * ib] = l4;
-      if (!diag) {
-        unsigned* h2 = (unsigned*)&hb;
-        unsigned* l2 = (unsigned*)&lb;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) split_bf16_pair(rb[u].x, rb[u].y, h2[u], l2[u]);
-        *(uint4*)&S.Bh[q][8 * ib] = hb;
-        *(uint4*)&S.Bl[q][8 * ib] = lb;
-      }
+      *(uint4*)&S.Ah[row][8 * ib] = h4;
+      *(uint4*)&S.Al[row][8 * ib] = l4;
     }
   };
   f32x16 acc = {}, acc_im = {};
@@ -564,20 +551,20 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
   }
   double dsum = 0.0;
   int since_flush = 0;
+  const int ra0 = ta * kCovSeg, rb0 = tb * kCovSeg;
   // chunk c0 is staged from R, then the loads of the next chunk go into R and stay in flight
   // through the products (the barriers wait for LDS operations only)
-  auto step = [&](long long c0, Regs& R) {
+  auto step = [&](long long c0, float2 (&R)[4]) {
     lstore(R);
     lds_barrier();
     if (c0 + COV_IMG < i1) gload(c0 + COV_IMG, R);
-    if constexpr (PREC == 0) {
-      mma_f32_k32(S.As, diag ? S.As : S.Bs, acc, wm, wn, lane);
-      if (HERM && im) mma_f32_k32_im(S.As, diag ? S.As : S.Bs, acc_im, wm, wn, lane);
-    } else {
-      if (diag)
-        mma_bf16x3_cov<HERM>(S.Ah, S.Al, S.Ah, S.Al, acc, acc_im, im, wm, wn, lane);
-      else
-        mma_bf16x3_cov<HERM>(S.Ah, S.Al, S.Bh, S.Bl, acc, acc_im, im, wm, wn, lane);
+    if (has) {
+      if constexpr (PREC == 0) {
+        mma_f32_k32(S.As, acc, ra0, rb0, lane);
+        if (HERM && im) mma_f32_k32_im(S.As, acc_im, ra0, rb0, lane);
+      } else {
+        mma_bf16x3_cov<HERM>(S.Ah, S.Al, acc, acc_im, im, ra0, rb0, lane);
+      }
     }
     lds_barrier();
     since_flush += COV_K;
@@ -599,7 +586,7 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
       since_flush = 0;
     }
   };
-  Regs R0;
+  float2 R0[4];
   gload(i0, R0);
   for (long long c0 = i0; c0 < i1; c0 += COV_IMG) step(c0, R0);
 #pragma unroll
@@ -609,35 +596,40 @@ __global__ __launch_bounds__(256) void k_covariance(const float* __restrict__ co
     for (int i = 0; i < 16; ++i) dacc_im[i] += (double)acc_im[i];
   }
   dsum += (double)ssum;
-  double* gk = partG + (size_t)slice * cov_size + cov_off[k];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int r = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-    if (r < pk && c < pk) {
-      gk[(size_t)r * pk + c] = dacc[i];
-      if (!diag) gk[(size_t)c * pk + r] = dacc[i];
-    }
-  }
-  if constexpr (HERM) {
-    // the imaginary part is antisymmetric: every value is written at (r, c) with r < c and
-    // negated at (c, r), the diagonal as zero (a diagonal tile keeps its upper triangle)
-    double* gi = partGi + (size_t)slice * cov_size + cov_off[k];
+  if (has) {
+    const int pk = p[kt], ma = it.q0[ta], nb = it.q0[tb];
+    const bool diag = (ta == tb);
+    double* gk = partG + (size_t)slice * cov_size + cov_off[kt];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      int r = m0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-      if (r < pk && c < pk && r <= c) {
-        const double v = (r == c) ? 0.0 : dacc_im[i];
-        gi[(size_t)r * pk + c] = v;
-        gi[(size_t)c * pk + r] = -v;
+      int rr = ma + acc_row(i, lane), cc = nb + (lane & 31);
+      if (rr < pk && cc < pk) {
+        gk[(size_t)rr * pk + cc] = dacc[i];
+        if (!diag) gk[(size_t)cc * pk + rr] = dacc[i];
+      }
+    }
+    if constexpr (HERM) {
+      // the imaginary part is antisymmetric: every value is written at (r, c) with r < c and
+      // negated at (c, r), the diagonal as zero (a diagonal tile keeps its upper triangle)
+      double* gi = partGi + (size_t)slice * cov_size + cov_off[kt];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        int rr = ma + acc_row(i, lane), cc = nb + (lane & 31);
+        if (rr < pk && cc < pk && rr <= cc) {
+          const double v = (rr == cc) ? 0.0 : dacc_im[i];
+          gi[(size_t)rr * pk + cc] = v;
+          gi[(size_t)cc * pk + rr] = -v;
+        }
       }
     }
   }
-  if (do_sum) {
-    // the four loader threads of row q hold FP64 sums of disjoint images
-    dred[ib][q] = dsum;
-    __syncthreads();
-    if (tid < BM && m0 + tid < pk)
-      partS0[(size_t)slice * p0 + m0 + tid] = ((dred[0][tid] + dred[1][tid]) + dred[2][tid]) + dred[3][tid];
+  // the four loader threads of a k = 0 row hold FP64 sums of disjoint images
+  dred[ib][row] = dsum;
+  __syncthreads();
+  if (tid < COV_ROWS) {
+    const int s2 = tid / kCovSeg, r2 = tid % kCovSeg;
+    if (it.k[s2] == 0 && it.sum0[s2] && it.q0[s2] + r2 < p0)
+      partS0[(size_t)slice * p0 + it.q0[s2] + r2] = ((dred[0][tid] + dred[1][tid]) + dred[2][tid]) + dred[3][tid];
   }
 }
 
@@ -747,8 +739,8 @@ hipError_t launch_covariance(const Plan& pl, const float* coeffs, long long n, d
   dim3 g((unsigned)(nitems * sp.slices));
   pl.prof.begin(ST_COVARIANCE, st);
 #define FB_COV(P, H)                                                                                              \
-  hipLaunchKernelGGL((k_covariance<P, H>), g, dim3(256), 0, st, coeffs, partG, partS0, partGi, shift,             \
-                     pl.d_items_cov, pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per, \
+  hipLaunchKernelGGL((k_covariance<P, H>), g, dim3(COV_THREADS), 0, st, coeffs, partG, partS0, partGi, shift,     \
+                     pl.d_items_cov, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half, nitems, sp.per,                \
                      (long long)pl.cov_size, pl.p0)
   if (precision == FB_BF16X3) {
     if (herm) FB_COV(1, true);

@@ -418,8 +418,54 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     for (int n0 = 0; n0 < pl.p[k]; n0 += 64) pl.items_spca.push_back(GemmItem{k, n0, 0, 0});
     for (int m0 = 0; m0 < pl.p[k]; m0 += kRadialRows) pl.items_fwd.push_back(GemmItem{k, m0, 0, 0});
     for (int j0 = 0; j0 < pl.n_xi; j0 += pl.bm) pl.items_adj.push_back(GemmItem{k, j0, 0, 0});
-    for (int m0 = 0; m0 < pl.p[k]; m0 += pl.bm)
-      for (int n0 = m0; n0 < pl.p[k]; n0 += pl.bn) pl.items_cov.push_back(GemmItem{k, m0, n0, 0});
+  }
+  // covariance items: blocks whose segments and tiles fit one item go whole, packed in k
+  // order while an item's segments and tiles allow; larger blocks tile by tile (column by
+  // column of the upper triangle), a segment loaded again by each item that needs it (its
+  // S0 sums by the first)
+  {
+    CovItem cur{};
+    int nseg = 0, ntile = 0;
+    auto reset = [&]() {
+      cur = CovItem{};
+      for (int s = 0; s < kCovSegs; ++s) cur.k[s] = -1;
+      for (int w = 0; w < kCovWaves; ++w) cur.ta[w] = cur.tb[w] = 255;
+      nseg = ntile = 0;
+    };
+    auto flush = [&]() {
+      if (nseg > 0) pl.items_cov.push_back(cur);
+      reset();
+    };
+    std::vector<char> summed;
+    auto seg_slot = [&](int k, int i) {  // slot of segment i of block k, added if absent
+      for (int s = 0; s < nseg; ++s)
+        if (cur.k[s] == k && cur.q0[s] == i * kCovSeg) return s;
+      cur.k[nseg] = (short)k;
+      cur.q0[nseg] = (unsigned char)(i * kCovSeg);
+      cur.row[nseg] = (int)pl.coef_off[k] + i * kCovSeg;
+      cur.sum0[nseg] = (k == 0 && !summed[i]) ? 1 : 0;
+      if (k == 0) summed[i] = 1;
+      return nseg++;
+    };
+    reset();
+    for (int k = 0; k <= pl.k_max; ++k) {
+      const int nb = (pl.p[k] + kCovSeg - 1) / kCovSeg, nt = nb * (nb + 1) / 2;
+      if (k == 0) summed.assign(nb, 0);
+      const bool whole = nb <= kCovSegs && nt <= kCovWaves;
+      if (whole && (nseg + nb > kCovSegs || ntile + nt > kCovWaves)) flush();
+      for (int j = 0; j < nb; ++j)
+        for (int i = 0; i <= j; ++i) {
+          const int need = (i == j) ? 1 : 2;
+          int have = 0;
+          for (int s = 0; s < nseg; ++s) have += cur.k[s] == k && (cur.q0[s] == i * kCovSeg || cur.q0[s] == j * kCovSeg);
+          if (nseg + need - have > kCovSegs || ntile + 1 > kCovWaves) flush();
+          const int a = seg_slot(k, i), b = seg_slot(k, j);
+          cur.ta[ntile] = (unsigned char)a;
+          cur.tb[ntile] = (unsigned char)b;
+          ++ntile;
+        }
+    }
+    flush();
   }
   return FB_OK;
 }
@@ -548,7 +594,8 @@ void free_device(Plan& pl) {
   pl.d_snodes = nullptr;
   pl.d_sseg = nullptr;
   pl.d_sent = nullptr;
-  pl.d_items_fwd = pl.d_items_adj = pl.d_items_cov = pl.d_items_spca = nullptr;
+  pl.d_items_fwd = pl.d_items_adj = pl.d_items_spca = nullptr;
+  pl.d_items_cov = nullptr;
   pl.d_jmin = pl.d_kring = pl.d_gcols = nullptr;
   pl.has_device = false;
 }

@@ -183,9 +183,26 @@ constexpr double kRadialNegligible = 1.0 / (1u << 30);
 struct GemmItem {  // one (k, tile) work item of a grouped GEMM
   int k;
   int t0;  // first row (or first row tile) of the tile
-  int t1;  // second tile coordinate (covariance only)
+  int t1;  // second tile coordinate (unused)
   int pad;
 };
+
+// Covariance work item: up to kCovSegs segments of kCovSeg consecutive coefficients, each
+// inside one block k (starting at a multiple of kCovSeg in the block), staged together for
+// every chunk of images, and up to kCovWaves tiles (one per wave): the kCovSeg x kCovSeg
+// products of two segments of the same block.  A block of at most 3 kCovSeg coefficients
+// sits in one item (all its tiles, every coefficient read once); small blocks share items.
+constexpr int kCovSeg = 32;
+constexpr int kCovSegs = 4;
+constexpr int kCovWaves = 8;
+struct CovItem {
+  int row[kCovSegs];                // first coefficient of the segment (index < p_half)
+  short k[kCovSegs];                // its block, -1 for an unused slot
+  unsigned char q0[kCovSegs];       // its first row inside the block (blocks hold <= 256 rows)
+  unsigned char sum0[kCovSegs];     // 1: this item adds the segment's k = 0 sums (S0)
+  unsigned char ta[kCovWaves], tb[kCovWaves];  // segments of wave w's tile (ta <= tb), 255: none
+};
+static_assert(sizeof(CovItem) == 48, "a covariance item is three 16-byte words");
 
 struct Plan {
   // problem
@@ -228,7 +245,8 @@ struct Plan {
   std::vector<int> snodes;         // j << 16 | l
   std::vector<int> sseg;
   std::vector<SpreadLocal> sent;
-  std::vector<GemmItem> items_fwd, items_adj, items_cov, items_spca;
+  std::vector<GemmItem> items_fwd, items_adj, items_spca;
+  std::vector<CovItem> items_cov;
   // rings the radial sum of block k reads: j >= jmin[k] (the first ring where some row of
   // block k reaches kRadialNegligible of its largest entry); kring[j] = the largest k with
   // jmin[k] <= j (-1 if none): the angular step writes F-hat(j, k) for k <= kring[j] only
@@ -267,7 +285,7 @@ struct Plan {
   SpreadLocal* d_sent = nullptr;
   GemmItem* d_items_fwd = nullptr;
   GemmItem* d_items_adj = nullptr;
-  GemmItem* d_items_cov = nullptr;
+  CovItem* d_items_cov = nullptr;
   GemmItem* d_items_spca = nullptr;   // (k, 64-wide column tile) of the steerable-PCA products
   int* d_jmin = nullptr;              // k_max + 1
   int* d_kring = nullptr;             // n_xi

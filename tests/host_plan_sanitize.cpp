@@ -62,6 +62,44 @@ int main() {
         }
       }
       check(ok, "grid column ranges");
+      // covariance items: every 32 x 32 tile of the upper triangle of every block once, from
+      // two segments of that block; every k = 0 segment's S0 sums once
+      {
+        std::vector<std::vector<int>> cover(pl.k_max + 1);
+        for (int k = 0; k <= pl.k_max; ++k) {
+          const int nb = (pl.p[k] + fb::kCovSeg - 1) / fb::kCovSeg;
+          cover[k].assign(nb * nb, 0);
+        }
+        std::vector<int> s0((pl.p[0] + fb::kCovSeg - 1) / fb::kCovSeg, 0);
+        bool cov_ok = true;
+        for (const fb::CovItem& it : pl.items_cov) {
+          for (int s = 0; s < fb::kCovSegs; ++s) {
+            if (it.k[s] < 0) continue;
+            const int k = it.k[s];
+            cov_ok = cov_ok && k <= pl.k_max && it.q0[s] % fb::kCovSeg == 0 && it.q0[s] < pl.p[k] &&
+                     it.row[s] == pl.coef_off[k] + it.q0[s];
+            if (k == 0 && it.sum0[s]) s0[it.q0[s] / fb::kCovSeg]++;
+            cov_ok = cov_ok && (k == 0 || !it.sum0[s]);
+          }
+          for (int w = 0; w < fb::kCovWaves; ++w) {
+            if (it.ta[w] == 255) continue;
+            const int a = it.ta[w], b = it.tb[w];
+            cov_ok = cov_ok && a < fb::kCovSegs && b < fb::kCovSegs && it.k[a] >= 0 && it.k[a] == it.k[b] &&
+                     it.q0[a] <= it.q0[b];
+            if (!cov_ok) break;
+            const int k = it.k[a], nb = (pl.p[k] + fb::kCovSeg - 1) / fb::kCovSeg;
+            cover[k][(it.q0[a] / fb::kCovSeg) * nb + it.q0[b] / fb::kCovSeg]++;
+          }
+        }
+        for (int k = 0; cov_ok && k <= pl.k_max; ++k) {
+          const int nb = (pl.p[k] + fb::kCovSeg - 1) / fb::kCovSeg;
+          for (int i = 0; i < nb; ++i)
+            for (int j = 0; j < nb; ++j) cov_ok = cov_ok && cover[k][i * nb + j] == (i <= j ? 1 : 0);
+        }
+        for (int v : s0) cov_ok = cov_ok && v == 1;
+        check(cov_ok, "covariance items cover every tile once");
+        std::printf("  covariance: %zu items\n", pl.items_cov.size());
+      }
       std::printf("  grid points stored by the column pass: %.3f of %d x %d\n", (double)stored / ((double)pl.M2 * pl.N),
                   pl.M2, pl.N);
     } else {
