@@ -167,6 +167,15 @@ int fb_adjoint(fb_plan_t plan, const float* coeffs, int64_t n, float* images, in
  * Eq.(CTFenv), with H evaluated at the plan's xi_j by the caller).  Same errors. */
 int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* images, int weight_mode,
                         const float* ring_filter, void* ws, size_t ws_bytes, void* stream);
+/* The CTF envelope of Sec. VI-C, Eq.(CTFenv), on the plan's rings:
+ *   filter[j] = min(pi lambda z f^2 + a, 1) exp(-B f^2),  f = xi_j / pixel_size,
+ * in FP64, stored as FP32 (device [n_xi], caller-owned), for fb_adjoint_filtered.
+ * lambda: electron wavelength, z: defocus (both in the units of pixel_size, e.g. Angstrom),
+ * a: amplitude contrast phase (rad), B: B-factor (pixel_size units squared).  Asynchronous
+ * on `stream`; allocates nothing.  Errors: FB_ERR_INVALID_ARG (NULL filter, pixel_size
+ * <= 0, a non-finite parameter), FB_ERR_NO_DEVICE, FB_ERR_HIP. */
+int fb_ctf_filter(fb_plan_t plan, double pixel_size, double lambda, double defocus, double phase, double bfactor,
+                  float* filter, void* stream);
 
 /* Accumulate the steerable covariance of n coefficient vectors (Eqs.(ck),(ck_0)):
  *   G[cov_off[k] + q p_k + q'] += sum_i Re(b^i_{kq} conj(b^i_{kq'}))  (FP64, full p_k x p_k blocks)

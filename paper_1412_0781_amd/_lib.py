@@ -62,6 +62,7 @@ SIGNATURES = [
     ("fb_eigenimages", c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
     ("fb_adjoint_filtered", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int, c_void_p, c_void_p, c_size_t,
                                     c_void_p]),
+    ("fb_ctf_filter", c_int, [c_void_p, c_double, c_double, c_double, c_double, c_double, c_void_p, c_void_p]),
     ("fb_moments_workspace_bytes", c_size_t, [c_void_p]),
     ("fb_pixel_moments", c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("fb_polar_power_workspace_bytes", c_size_t, [c_void_p, c_int64]),

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "../../include/ffbspca.h"
@@ -332,6 +333,17 @@ int fb_estimate_support(fb_plan_t plan, const double* sum, const double* sumsq, 
   fb::Plan& pl = plan->pl;
   if (!pl.has_device) return FB_ERR_NO_DEVICE;
   return hip_rc(pl, fb::launch_estimate_support(pl, sum, sumsq, n, power, noise_var, frac, out, (hipStream_t)stream));
+}
+
+int fb_ctf_filter(fb_plan_t plan, double pixel_size, double lambda, double defocus, double phase, double bfactor,
+                  float* filter, void* stream) {
+  if (!plan || !filter || !(pixel_size > 0.0) || !std::isfinite(pixel_size) || !std::isfinite(lambda) ||
+      !std::isfinite(defocus) || !std::isfinite(phase) || !std::isfinite(bfactor))
+    return FB_ERR_INVALID_ARG;
+  fb::Plan& pl = plan->pl;
+  if (!pl.has_device) return FB_ERR_NO_DEVICE;
+  return hip_rc(pl, fb::launch_ctf_filter(pl, pixel_size, lambda, defocus, phase, bfactor, filter,
+                                          (hipStream_t)stream));
 }
 
 size_t fb_svd_workspace_bytes(fb_plan_t plan, int64_t n) {

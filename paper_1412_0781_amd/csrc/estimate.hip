@@ -189,6 +189,24 @@ hipError_t launch_polar_power(const Plan& pl, const float2* P, const float2* Pme
   return hipGetLastError();
 }
 
+// Eq.(CTFenv) at f = xi_j / pixel_size, one ring per thread, in FP64
+__global__ void k_ctf_filter(const double* __restrict__ xi, int n_xi, double pixel_size, double lambda,
+                             double defocus, double phase, double bfactor, float* __restrict__ filter) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n_xi) {
+    const double f = xi[j] / pixel_size, f2 = f * f;
+    const double env = fmin(3.14159265358979323846 * lambda * defocus * f2 + phase, 1.0);
+    filter[j] = (float)(env * exp(-bfactor * f2));
+  }
+}
+
+hipError_t launch_ctf_filter(const Plan& pl, double pixel_size, double lambda, double defocus, double phase,
+                             double bfactor, float* filter, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctf_filter, dim3((unsigned)((pl.n_xi + 255) / 256)), dim3(256), 0, st, pl.d_xi, pl.n_xi,
+                     pixel_size, lambda, defocus, phase, bfactor, filter);
+  return hipGetLastError();
+}
+
 hipError_t launch_estimate_support(const Plan& pl, const double* sum, const double* sumsq, long long n,
                                    const double* power, double noise_var, double frac, double* out, hipStream_t st) {
   if (pl.L / 2 + 1 > kMaxRadialBins) return hipErrorInvalidValue;

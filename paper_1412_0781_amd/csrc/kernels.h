@@ -92,6 +92,8 @@ hipError_t launch_polar_power(const Plan& pl, const float2* P, const float2* Pme
 hipError_t launch_copy_polar(const Plan& pl, const float2* P, float2* dst, hipStream_t st);
 hipError_t launch_estimate_support(const Plan& pl, const double* sum, const double* sumsq, long long n,
                                    const double* power, double noise_var, double frac, double* out, hipStream_t st);
+hipError_t launch_ctf_filter(const Plan& pl, double pixel_size, double lambda, double defocus, double phase,
+                             double bfactor, float* filter, hipStream_t st);
 hipError_t launch_eigenimages(const Plan& pl, const double* evecs, int k, int l0, int nl, double* out,
                               hipStream_t st);
 

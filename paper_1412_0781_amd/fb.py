@@ -210,6 +210,16 @@ class Plan:
                                    power.data_ptr(), ws.data_ptr(), wsb, _stream_ptr(dev)), self._h)
         return power
 
+    def ctf_filter(self, pixel_size: float, lam: float, defocus: float, phase: float, bfactor: float,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+        """Eq.(CTFenv) on the plan's rings (float32 [n_xi] on the device), for adjoint(ring_filter=...)."""
+        if out is None:
+            out = torch.empty(self.n_xi, dtype=torch.float32, device=self.device)
+        _need(out, torch.float32, (self.n_xi,), "out")
+        check(lib().fb_ctf_filter(self._h, float(pixel_size), float(lam), float(defocus), float(phase),
+                                  float(bfactor), out.data_ptr(), _stream_ptr(out.device)), self._h)
+        return out
+
     def estimate_support(self, sum: torch.Tensor, sumsq: torch.Tensor, n: int, power: torch.Tensor,
                          noise_var: float, frac: float = 0.999):
         """(R, c) from the accumulated moments and ring power (the cumulative-fraction rule)."""

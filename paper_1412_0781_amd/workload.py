@@ -42,11 +42,8 @@ CTF_LAMBDA, CTF_DEFOCUS, CTF_PHASE, CTF_B = 0.0197, 2.5e4, 0.1, 100.0
 def ctf_ring_filter(plan, pixel_size: float = 1.0, lam: float = CTF_LAMBDA, z: float = CTF_DEFOCUS,
                     a: float = CTF_PHASE, B: float = CTF_B) -> torch.Tensor:
     """Eq.(CTFenv), min(pi lambda z f^2 + a, 1) exp(-B f^2) at f = xi_j / pixel_size, on the plan's
-    rings: float32 [n_xi] on the device, for fb_adjoint_filtered."""
-    xi = plan.host_tables()[2]
-    f2 = (xi / pixel_size) ** 2
-    h = np.minimum(math.pi * lam * z * f2 + a, 1.0) * np.exp(-B * f2)
-    return torch.tensor(h.astype(np.float32), device=plan.device)
+    rings: float32 [n_xi] on the device (fb_ctf_filter), for fb_adjoint_filtered."""
+    return plan.ctf_filter(pixel_size, lam, z, a, B)
 
 
 def synthetic_images(plan, first: int, m: int, seed: int, snr: float, out: torch.Tensor | None = None,

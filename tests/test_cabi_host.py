@@ -58,6 +58,11 @@ def test_host_plan_rejects_compute_without_device():
     assert lib.fb_expand_weighted(p._h, 1, 1, 1, 0, 0, 1, 1 << 20, None) == -5
     cnt = ctypes.c_int64(0)
     assert lib.fb_covariance(p._h, 1, 1, 1, 1, None, None, ctypes.byref(cnt), 0, 8, 1 << 20, None) == -5
+    # the CTF envelope: argument checks, then the host-only plan
+    assert lib.fb_ctf_filter(p._h, 1.0, 0.0197, 2.5e4, 0.1, 100.0, None, None) == -1        # no output
+    assert lib.fb_ctf_filter(p._h, 0.0, 0.0197, 2.5e4, 0.1, 100.0, 1, None) == -1           # pixel size
+    assert lib.fb_ctf_filter(p._h, 1.0, float("nan"), 2.5e4, 0.1, 100.0, 1, None) == -1     # non-finite
+    assert lib.fb_ctf_filter(p._h, 1.0, 0.0197, 2.5e4, 0.1, 100.0, 1, None) == -5
     cnt.value = -1
     assert lib.fb_covariance(p._h, 1, 1, 1, 1, None, None, ctypes.byref(cnt), 0, 8, 1 << 20, None) == -1
     # the imaginary parts need a second set of per-run partial sums

@@ -49,6 +49,21 @@ def test_filtered_synthesis_matches_oracle(L, c, R):
     assert rel_l2(got, ref) <= 1e-5
 
 
+def test_ctf_filter_parameters():
+    """Eq.(CTFenv) through fb_ctf_filter with every parameter away from its default (so a
+    swapped argument shows), against the oracle's envelope on the same rings."""
+    torch.cuda.set_device(0)
+    L, c, R = 128, 0.5, 64.0
+    po = oracle.plan(L, c, R)
+    plan = Plan(L, c, R)
+    args = dict(pixel_size=1.7, lam=0.025, z=1.8e4, a=0.07, B=60.0)
+    got = plan.ctf_filter(args["pixel_size"], args["lam"], args["z"], args["a"], args["B"]).cpu().numpy()
+    ref = estimate.ctf_envelope(po.xi, **args)
+    assert np.max(np.abs(got - ref)) <= 1e-7 * np.max(np.abs(ref))
+    # the envelope reaches its cap of 1 on some rings and decays on the outer ones
+    assert np.any(ref >= 0.99 * np.exp(-args["B"] * (po.xi / args["pixel_size"]) ** 2)) and ref[-1] < ref.max()
+
+
 def test_pixel_moments():
     torch.cuda.set_device(0)
     plan = Plan(32, 0.5, 16.0)
