@@ -110,6 +110,45 @@ def test_l360_dot_product_identity():
     assert np.max(rel) <= 1e-6
 
 
+def test_l356_grid720_with_padding():
+    """L = 356, R = 176: the grid side is again 720 (712 is not 2,3,5-smooth), so the 720-point
+    streaming row and column kernels run with 364 zero-padded columns per row (wider than
+    the image), while the half ring of 704 points takes the run-time-length angular form.
+    Expansion of sparse images against the oracle, the adjoint at sampled pixels against the
+    oracle, and the dot-product identity."""
+    L, c, R = 356, 0.5, 176.0
+    print(f"[fullsize] L={L} R={R}", flush=True)
+    po = _oracle_plan(L, c, R)
+    plan = Plan(L, c, R)
+    assert plan.grid_n == 720
+    dense, pix = sparse_images(L, 2, 48, seed=13)
+    ref = oracle.expand_sparse(pix, po)
+    got = as_complex(plan.expand(torch.tensor(dense, device="cuda"), precision="fp32"))
+    for i in range(len(pix)):
+        e = rel_l2(got[i], ref[i])
+        print(f"  expand image {i}: rel-L2 {e:.3e}", flush=True)
+        assert e <= TOL
+    assert max_block_rel(got, ref, po.coef_off) <= TOL
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(23, np.arange(2), k, q)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    img = plan.adjoint(bt)
+    rng = np.random.default_rng(14)
+    rows = list(rng.integers(0, L, 64)) + [0, L - 1, L // 2]
+    cols = list(rng.integers(0, L, 64)) + [L - 1, 0, L // 2]
+    aref = oracle.adjoint_pixels(b, po, rows, cols)
+    I = img.cpu().numpy().astype(np.float64)
+    for i in range(len(b)):
+        e = rel_l2(I[i, rows, cols], aref[i])
+        print(f"  adjoint image {i}: rel-L2 at {len(rows)} pixels {e:.3e}", flush=True)
+        assert e <= TOL
+    a = as_complex(plan.expand(img))
+    bc = b.astype(np.complex64).astype(np.complex128)
+    lhs = oracle.coeff_inner(a, bc, po)
+    rhs = np.sum(I * I, axis=(1, 2))
+    assert np.max(np.abs(lhs - rhs) / np.abs(rhs)) <= 1e-6
+
+
 @pytest.mark.parametrize("L,R,precision", [(256, 128.0, "bf16x3"), (128, 64.0, "fp32")])
 def test_full_n_sampled(L, R, precision):
     n, c, seed = 100000, 0.5, 5
