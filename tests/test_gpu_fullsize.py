@@ -249,6 +249,35 @@ def test_c3_covariance_and_eigenvalues_against_oracle(c3_dictionary, precision):
     assert e_C <= TOL and e_lam <= TOL and e_m <= TOL
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_l360_covariance_against_oracle(precision):
+    """Covariance and mean at L = 360 from host-generated coefficients (600 images, a k = 0
+    mean ten times the spread, in two accumulating calls): blocks of up to 179 coefficients
+    are spread over several work items, some segments loaded by more than one item with
+    the k = 0 sums taken once.  Every C^(k) (relative Frobenius) and the mean against the
+    oracle on the same FP32-rounded coefficients."""
+    L, c, R, n = 360, 0.5, 180.0, 600
+    print(f"[fullsize] covariance L={L} n={n} {precision}", flush=True)
+    po = _oracle_plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(31, np.arange(n), k, q)
+    b[:, :po.p[0]] += 10.0 * np.sqrt(synth.coef_variance(k[:po.p[0]], q[:po.p[0]]))[None, :]
+    b = b.astype(np.complex64)
+    mean_ref, C_ref = oracle.mean_and_covariance(b.astype(np.complex128), po)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1), device="cuda")
+    st = plan.new_covariance()
+    plan.covariance(bt[:350], st, precision=precision)
+    plan.covariance(bt[350:], st, precision=precision)
+    _, _, C, mean = plan.eig(st)
+    torch.cuda.synchronize()
+    Cb = plan.blocks(C.cpu().numpy())
+    worst = max(rel_l2(Cb[kk], C_ref[kk]) for kk in range(po.k_max + 1))
+    e_m = rel_l2(mean.cpu().numpy(), mean_ref)
+    print(f"  C^(k) max over k {worst:.3e}; mean {e_m:.3e}", flush=True)
+    assert worst <= TOL and e_m <= TOL
+
+
 def test_l360_eig_two_sided_form():
     """At L = 360 the largest blocks (p_0 = 179) exceed LDS, so the eigendecomposition takes
     the two-sided form in global memory: eigenvalues descending and equal to LAPACK's on the
