@@ -265,13 +265,16 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
 }
 
 // columns: unit = (stored row m2, image group); output G [M2][group][N][16], of each row
-// only the centred m1 range gcols[m2] that the gather's boxes read
+// only the centred m1 range gcols[m2] that the gather's boxes read.  Thread t stages image
+// slot t / 64 of the group at the columns t % 64 + 64 q, so its positions in LDS (and in the
+// zero padding) are the same for every unit and its loads are one run per image.
 template <int NC>
 __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const int2* __restrict__ gcols, int L, int M2,
-                                                             int nimg, int ngrp, int U, FastDiv dL, FastDiv dZ) {
+                                                             int nimg, int ngrp, int U) {
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
+  static_assert(G * 64 == 1024, "64 threads per image slot");
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
   __shared__ float2 s_tw[NM];
   const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
@@ -282,38 +285,34 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(cons
   const int x0 = -((L - 1 + 1) / 2);
   for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
   __syncthreads();
-  constexpr int PF = (G * (NM / 2) + 1023) / 1024;  // L <= N / 2
-  const int nval = G * L;
+  constexpr int PF = (NM / 2 + 63) / 64;  // L <= N / 2
+  const int ci = tid >> 6, ai = tid & 63;
+  float2* row = s_buf + ci * S;
   float2 pre[PF];
   // unit u = (m2, group): groups vary fastest, so consecutive units write consecutive runs of G
   auto load = [&](int u) {
     const int m2 = u / ngrp, i0 = (u - m2 * ngrp) * G;
+    const bool live = i0 + ci < nimg;
+    const float2* src = g1 + ((size_t)(i0 + ci) * M2 + m2) * L + ai;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int e = tid + q * nthr;
-      const int c = dL.div(e), a = e - c * L;
-      pre[q] = (e < nval && i0 + c < nimg) ? g1[((size_t)(i0 + c) * M2 + m2) * L + a] : make_float2(0.f, 0.f);
-    }
+    for (int q = 0; q < PF; ++q) pre[q] = (live && ai + 64 * q < L) ? src[64 * q] : make_float2(0.f, 0.f);
   };
   if (u0 < u1) load(u0);
   for (int u = u0; u < u1; ++u) {
     const int m2 = u / ngrp, grp = u - m2 * ngrp;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-      const int e = tid + q * nthr;
-      if (e < nval) {
-        const int c = dL.div(e), a = e - c * L;
+      const int a = ai + 64 * q;
+      if (a < L) {
         int pos = x0 + a;
         pos += (pos < 0) ? N : 0;
-        s_buf[c * S + fpad(pos)] = pre[q];
+        row[fpad(pos)] = pre[q];
       }
     }
-    for (int e = tid; e < G * (N - L); e += nthr) {
-      const int t = dZ.div(e), z = e - t * (N - L);  // dZ: division by N - L
+    for (int z = ai; z < N - L; z += 64) {  // the columns past the image, wrapped
       int pos = x0 + L + z;
       pos -= (pos >= N) ? N : 0;
-      pos += (pos < 0) ? N : 0;
-      s_buf[t * S + fpad(pos)] = make_float2(0.f, 0.f);
+      row[fpad(pos)] = make_float2(0.f, 0.f);
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
@@ -1275,8 +1274,7 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     pl.prof.begin(ST_FWD_COLS, st);
     const int Uc = stream_units(pl, uc, stream_per_cu(N), kGridUnits);
     FB_LAUNCH_STREAM(k_fwd_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
-                       bufA, bufB, pl.fft_grid, pl.d_tw, (const int2*)pl.d_gcols, L, pl.M2, nimg, ngrp, Uc,
-                       make_fastdiv(L), make_fastdiv(N - L));
+                       bufA, bufB, pl.fft_grid, pl.d_tw, (const int2*)pl.d_gcols, L, pl.M2, nimg, ngrp, Uc);
     pl.prof.end(st);
   } else {
     FftLaunch fr = fft_launch(pl.fft_grid, N + 1);
