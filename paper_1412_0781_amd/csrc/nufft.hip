@@ -176,12 +176,14 @@ constexpr int kStreamMixedN = 720;  // the compile-time mixed-radix length (L = 
 constexpr int stream_cap(int nc, int base) { return nc > base ? nc : base; }
 constexpr int stream_waves(int nc) { return nc > kGridStreamN ? 4 : 8; }
 
-// rows: unit = (image, 16 row pairs); rows a = 2 p0 .. 2 p0 + 31 of the image
+// rows: unit = (image, 16 row pairs); rows a = 2 p0 .. 2 p0 + 31 of the image.  Thread t
+// stages row t / 32 of the unit at the pixel quads t % 32 + 32 q, and zero-pads transform
+// t / 64 at the columns t % 64 + 64 q, so its LDS positions are the same for every unit.
 template <int NC>
 __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(const float* __restrict__ img, float2* __restrict__ g1,
                                                              const float* __restrict__ deconv, FftDesc fd,
                                                              const float2* __restrict__ tw, int L, int M2, int hw,
-                                                             int nimg, int U, FastDiv dL4, FastDiv dZ) {
+                                                             int nimg, int U) {
   constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
   __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
   __shared__ float2 s_tw[NM];
@@ -197,54 +199,55 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
   for (int i = tid; i < L; i += nthr) s_dec[i] = deconv[i];
   __syncthreads();
   // one item = four consecutive pixels of a row (L % 4 == 0, L <= N / 2); rows past L read as zero
-  constexpr int PF = (2 * RP * (NM / 2) / 4 + 1023) / 1024;
-  const int L4 = L / 4, nval = 2 * RP * L4;
+  static_assert(2 * RP * 32 == 1024, "32 threads per row of the unit");
+  constexpr int PF = (NM / 2 / 4 + 31) / 32;
+  const int L4 = L / 4;
+  const int r = tid >> 5, bq = tid & 31;  // this thread's row of the unit, first pixel quad
+  float2* zrow = s_buf + (tid >> 6) * S;  // the transform this thread zero-pads
   float4 pre[PF];
   auto load = [&](int u) {
-    const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
-    const float4* src = (const float4*)(img + (size_t)im * L * L);
+    const int im = u / nrb, a = 2 * RP * (u - im * nrb) + r;
+    const float4* src = (const float4*)(img + ((size_t)im * L + min(a, L - 1)) * L) + bq;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int e = tid + q * nthr;
-      const int r = dL4.div(e), a = a0 + r;
-      pre[q] = (e < nval && a < L) ? src[(size_t)a * L4 + (e - r * L4)] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int q = 0; q < PF; ++q)
+      pre[q] = (a < L && bq + 32 * q < L4) ? src[32 * q] : make_float4(0.f, 0.f, 0.f, 0.f);
   };
   if (u0 < u1) load(u0);
   for (int u = u0; u < u1; ++u) {
     const int im = u / nrb, a0 = 2 * RP * (u - im * nrb);
     // row a0 + r goes to transform r / 2, real part (r even) or imaginary part (r odd),
     // deconvolved and centred; the N - L padded columns of every transform are zero
+    {
+      const int a = a0 + r;
+      const float da = (a < L) ? s_dec[a] : 0.f;
+      float* row = (float*)(s_buf + (r >> 1) * S) + (r & 1);
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      const int e = tid + q * nthr;
-      if (e < nval) {
-        const int r = dL4.div(e), b0 = 4 * (e - r * L4), a = a0 + r;
-        const float da = (a < L) ? s_dec[a] : 0.f;
-        const float vv[4] = {pre[q].x, pre[q].y, pre[q].z, pre[q].w};
+      for (int q = 0; q < PF; ++q) {
+        const int b0 = 4 * (bq + 32 * q);
+        if (b0 < L) {
+          const float vv[4] = {pre[q].x, pre[q].y, pre[q].z, pre[q].w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          int pos = x0 + b0 + i;
-          pos += (pos < 0) ? N : 0;
-          ((float*)&s_buf[(r >> 1) * S + fpad(pos)])[r & 1] = vv[i] * da * s_dec[b0 + i];
+          for (int i = 0; i < 4; ++i) {
+            int pos = x0 + b0 + i;
+            pos += (pos < 0) ? N : 0;
+            row[2 * fpad(pos)] = vv[i] * da * s_dec[b0 + i];
+          }
         }
       }
     }
-    for (int e = tid; e < RP * (N - L); e += nthr) {
-      const int t = dZ.div(e), z = e - t * (N - L);  // dZ: division by N - L
-      int pos = x0 + L + z;  // columns past the image, wrapped
+    for (int z = tid & 63; z < N - L; z += 64) {  // columns past the image, wrapped
+      int pos = x0 + L + z;
       pos -= (pos >= N) ? N : 0;
-      pos += (pos < 0) ? N : 0;
-      s_buf[t * S + fpad(pos)] = make_float2(0.f, 0.f);
+      zrow[fpad(pos)] = make_float2(0.f, 0.f);
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
     fft_stream<NC, RP>(s_buf, S, fd, s_tw);
     // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i); lanes over the rows
     float2* out = g1 + (size_t)im * M2 * L;
-    const int r = tid & 31, a = a0 + r;
-    if (a < L) {
-      const int pp = r >> 1, which = r & 1;
+    const int ru = tid & 31, au = a0 + ru;  // the unpacking lanes run over the unit's rows
+    if (au < L) {
+      const int pp = ru >> 1, which = ru & 1;
       for (int mi = tid >> 5; mi < M2; mi += nthr >> 5) {
         int m2 = mi - hw;
         int mp = m2 < 0 ? m2 + N : m2;
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
           float2 dd = csub(z1, z2);
           v = make_float2(0.5f * dd.y, -0.5f * dd.x);
         }
-        out[(size_t)mi * L + a] = v;
+        out[(size_t)mi * L + au] = v;
       }
     }
     stage_barrier<true>();
@@ -948,7 +951,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
 template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __restrict__ Y, float2* __restrict__ Zc,
                                                             FftDesc fd, const float2* __restrict__ tw, int L,
-                                                            int nimg, int ngrp, int U, FastDiv dL) {
+                                                            int nimg, int ngrp, int U) {
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
   constexpr int PF = (NM * G / 2 + 1023) / 1024;  // pairs of values per thread
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
@@ -988,12 +991,15 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
     fft_stream<NC, G>(s_buf, S, fd, s_tw);
-    for (int e = tid; e < G * L; e += nthr) {
-      const int c = dL.div(e), a = e - c * L, i = grp * G + c;
+    {
+      const int c = tid >> 6, i = grp * G + c;  // thread t writes image slot t / 64 at x1 = t % 64 + 64 q
       if (i < nimg) {
-        int pos = x0 + a;
-        pos += (pos < 0) ? N : 0;
-        Zc[((size_t)i * Nh + m2) * L + a] = cconj(s_buf[c * S + fpad(pos)]);
+        float2* dst = Zc + ((size_t)i * Nh + m2) * L;
+        for (int a = tid & 63; a < L; a += 64) {
+          int pos = x0 + a;
+          pos += (pos < 0) ? N : 0;
+          dst[a] = cconj(s_buf[c * S + fpad(pos)]);
+        }
       }
     }
     stage_barrier<true>();
@@ -1010,8 +1016,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
 template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __restrict__ Zc, float* __restrict__ img,
                                                             const float* __restrict__ deconv, FftDesc fd,
-                                                            const float2* __restrict__ tw, int L, int nimg, int U,
-                                                            FastDiv dL) {
+                                                            const float2* __restrict__ tw, int L, int nimg, int U) {
   constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
   constexpr int PF = ((NM / 2 + 1) * RP + 1023) / 1024;  // row-pair values per thread
   __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
@@ -1058,14 +1063,18 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
     fft_stream<NC, RP>(s_buf, S, fd, s_tw);
-    float* dst = img + (size_t)im * L * L;
-    for (int e = tid; e < 2 * RP * L; e += nthr) {
-      const int r = dL.div(e), b = e - r * L, a = a0 + r;
+    {
+      const int r = tid >> 5, a = a0 + r;  // thread t writes row t / 32 at x2 = t % 32 + 32 q
       if (a < L) {
-        int pos = x0 + b;
-        pos += (pos < 0) ? N : 0;
-        const float2 z = s_buf[(r >> 1) * S + fpad(pos)];  // conj of the inverse transform
-        dst[(size_t)a * L + b] = ((r & 1) ? -z.y : z.x) * s_dec[a] * s_dec[b];
+        float* dst = img + ((size_t)im * L + a) * L;
+        const float2* row = s_buf + (r >> 1) * S;
+        const float da = s_dec[a];
+        for (int b = tid & 31; b < L; b += 32) {
+          int pos = x0 + b;
+          pos += (pos < 0) ? N : 0;
+          const float2 z = row[fpad(pos)];  // conj of the inverse transform
+          dst[b] = ((r & 1) ? -z.y : z.x) * da * s_dec[b];
+        }
       }
     }
     stage_barrier<true>();
@@ -1267,8 +1276,7 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
     const int Ur = fixed_units(pl, ur, stream_per_cu(N), kGridUnits);
     pl.prof.begin(ST_FWD_ROWS, st);
     FB_LAUNCH_STREAM(k_fwd_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
-                       images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, Ur,
-                       make_fastdiv(L / 4), make_fastdiv(N - L));
+                       images, bufA, pl.d_deconv, pl.fft_grid, pl.d_tw, L, pl.M2, pl.hw, nimg, Ur);
     pl.prof.end(st);
     const long long uc = (long long)pl.M2 * ngrp;
     pl.prof.begin(ST_FWD_COLS, st);
@@ -1364,13 +1372,13 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
     pl.prof.begin(ST_ADJ_COLS, st);
     const int Uc = stream_units(pl, uc, 1, kGridUnits);
     FB_LAUNCH_STREAM(k_adj_cols_stream, N, dim3((unsigned)((uc + Uc - 1) / Uc)), st,
-                       bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, Uc, make_fastdiv(L));
+                       bufB, bufA, pl.fft_grid, pl.d_tw, L, nimg, ngrp, Uc);
     pl.prof.end(st);
     const long long ur = (long long)nimg * (((L + 1) / 2 + 15) / 16);
     pl.prof.begin(ST_ADJ_ROWS, st);
     const int Ur = stream_units(pl, ur, 1, kGridUnits);
     FB_LAUNCH_STREAM(k_adj_rows_stream, N, dim3((unsigned)((ur + Ur - 1) / Ur)), st,
-                       bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, Ur, make_fastdiv(L));
+                       bufA, images, pl.d_deconv, pl.fft_grid, pl.d_tw, L, nimg, Ur);
     pl.prof.end(st);
     return hipGetLastError();
   }
