@@ -347,8 +347,6 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   static_assert(IG == kImgGroup, "a gather workgroup takes one image group");
   constexpr int BW = CS + W - 1;
   constexpr int NPT = BW * BW;            // grid points in the box
-  constexpr int NV4 = NPT * IG / 2;       // float4 = two images of one point
-  constexpr int PER = (NV4 + NT - 1) / NT;  // float4 loads per thread
   extern __shared__ float4 lds4[];
   float2* box = (float2*)lds4;                               // [NPT][IG]
   const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -360,26 +358,31 @@ __global__ __launch_bounds__(NT) void k_fwd_gather(const float2* __restrict__ g,
   const int nn = it.s1 - it.s0;
   {
     // every group is whole (padded): issue every load of this thread before the LDS stores;
-    // a box row of one group is one contiguous run of BW * IG values in G
-    const float2* gg = g + (size_t)grp * N * IG;
+    // a box row of one group is one contiguous run of BW * IG values in G.  Thread t < BR * RW
+    // takes box rows t / RW + BR u and, in each, column and image pair t % RW, so successive
+    // loads step by BR rows in G and by a constant in LDS.
+    constexpr int RW = BW * (IG / 2);  // float4 per box row
+    constexpr int BR = NT / RW;        // box rows per pass of the threads
+    constexpr int PR = (BW + BR - 1) / BR;
+    static_assert(BR >= 1 && PR * BR >= BW, "the passes cover the box rows");
+    const int t = threadIdx.x, rr = t / RW, w = t - rr * RW;
+    const int cc = w / (IG / 2), h = w - cc * (IG / 2);
+    int col = it.c1 + cc;
+    col = col >= N ? col - N : col;
     const size_t row_stride = (size_t)ngrp * N * IG;
-    float4 v[PER];
+    const float4* src = (const float4*)(g + (size_t)grp * N * IG + (size_t)(it.c2 + (rr < BR ? rr : 0)) * row_stride +
+                                        (size_t)col * IG + 2 * h);
+    float4 v[PR];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      int i = threadIdx.x + u * NT;
-      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (i < NV4) {
-        int pt = i / (IG / 2), h = i - pt * (IG / 2);
-        int r = pt / BW, cc = pt - r * BW;
-        int row = it.c2 + r, col = it.c1 + cc;
-        col = col >= N ? col - N : col;
-        if (row < M2) v[u] = *(const float4*)(gg + row * row_stride + (size_t)col * IG + 2 * h);
-      }
+    for (int u = 0; u < PR; ++u) {
+      const int r = rr + BR * u;
+      v[u] = (rr < BR && r < BW && it.c2 + r < M2) ? src[(size_t)(BR * u) * (row_stride / 2)]
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      int i = threadIdx.x + u * NT;
-      if (i < NV4) lds4[i] = v[u];
+    for (int u = 0; u < PR; ++u) {
+      const int r = rr + BR * u;
+      if (rr < BR && r < BW) lds4[r * RW + w] = v[u];
     }
   }
   __syncthreads();
