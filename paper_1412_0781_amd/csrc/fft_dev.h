@@ -353,7 +353,52 @@ __device__ inline void fft_lds_inplace_tw(float2* buf, int count, int stride, co
 // twiddles are skipped: multiplying by exactly 1 changes nothing).
 constexpr int pow2_stage_radix(int rem) { return (rem % 8 == 0 && rem != 16) ? 8 : 4; }
 
-template <int N, int R, int NS, int COUNT, int STRIDE, int NT>
+// LDS layout of one transform in the compile-time streaming forms: element i of a length-N
+// transform sits at lds_pos<N, SW>(i), and transforms follow each other every
+// lds_span<N, SW>(N) elements.  SW = false: the padded layout fpad.  SW = true: powers of two
+// swizzle each aligned run of 16 elements by i / 16, 720 swizzles runs of 32 by i / 64; both
+// stay inside their runs (no padding), and a span of N + 2 puts the same element of 16
+// side-by-side transforms on distinct banks.  Measured, the swizzle pays at 720 in every
+// streaming kernel and at 512 in the four grid kernels, where the stride-8 and stride-64
+// butterfly writes meet fewer bank conflicts; elsewhere the padded layout is as fast or
+// faster (the swizzled addresses take more registers).  The run-time-length form (N = 0)
+// is always padded.
+constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+template <int N, bool SW>
+__host__ __device__ constexpr int lds_pos(int i) {
+  if constexpr (N == 0 || !SW)
+    return fpad(i);
+  else if constexpr (is_pow2(N))
+    return i ^ ((i >> 4) & 15);
+  else
+    return i ^ ((i >> 6) & 31);
+}
+template <int N, bool SW>
+__host__ __device__ constexpr int lds_span(int n) {
+  if constexpr (N == 0 || !SW)
+    return fpad(n - 1) + 2;
+  else
+    return n + 2;
+}
+// the layouts chosen per kernel family: grid (rows, columns and their transposes), angular
+constexpr bool grid_swizzle(int nc) { return nc == 720 || nc == 512; }
+constexpr bool angular_swizzle(int nc) { return nc == 720; }
+// the layout of length N maps [0, N) one to one into [0, lds_span - 1)
+template <int N, bool SW>
+constexpr bool lds_layout_ok() {
+  bool seen[lds_span<N, SW>(N)] = {};
+  for (int i = 0; i < N; ++i) {
+    const int p = lds_pos<N, SW>(i);
+    if (p < 0 || p > lds_span<N, SW>(N) - 2 || seen[p]) return false;
+    seen[p] = true;
+  }
+  return true;
+}
+static_assert(lds_layout_ok<64, true>() && lds_layout_ok<256, true>() && lds_layout_ok<512, true>() &&
+                  lds_layout_ok<720, true>() && lds_layout_ok<512, false>() && lds_layout_ok<720, false>(),
+              "each streaming layout is one to one within its span");
+
+template <int N, int R, int NS, int COUNT, int STRIDE, int NT, bool SW>
 __device__ __forceinline__ void fft_stage_pow2(float2* buf, const float2* __restrict__ tw, unsigned tid) {
   constexpr unsigned NB = N / R, TWS = N / (NS * R), BM = kFftVmax / R, TOTAL = COUNT * NB;
   static_assert((N & (N - 1)) == 0 && TOTAL <= BM * NT, "one pass of the threads covers every butterfly");
@@ -365,7 +410,7 @@ __device__ __forceinline__ void fft_stage_pow2(float2* buf, const float2* __rest
       const unsigned t = idx / NB, j = idx % NB;
       const float2* src = buf + t * STRIDE;
 #pragma unroll
-      for (unsigned r = 0; r < R; ++r) v[b][r] = src[fpad(j + r * NB)];
+      for (unsigned r = 0; r < R; ++r) v[b][r] = src[lds_pos<N, SW>(j + r * NB)];
     }
   }
   stage_barrier<true>();
@@ -382,18 +427,18 @@ __device__ __forceinline__ void fft_stage_pow2(float2* buf, const float2* __rest
       float2* dst = buf + t * STRIDE;
       const unsigned base = (j - k) * R + k;
 #pragma unroll
-      for (unsigned r = 0; r < R; ++r) dst[fpad(base + r * NS)] = v[b][r];
+      for (unsigned r = 0; r < R; ++r) dst[lds_pos<N, SW>(base + r * NS)] = v[b][r];
     }
   }
   stage_barrier<true>();
 }
 
-template <int N, int COUNT, int STRIDE, int NT, int NS = 1>
+template <int N, int COUNT, int STRIDE, int NT, bool SW, int NS = 1>
 __device__ __forceinline__ void fft_pow2_inplace(float2* buf, const float2* __restrict__ tw, unsigned tid) {
   if constexpr (NS < N) {
     constexpr int R = pow2_stage_radix(N / NS);
-    fft_stage_pow2<N, R, NS, COUNT, STRIDE, NT>(buf, tw, tid);
-    fft_pow2_inplace<N, COUNT, STRIDE, NT, NS * R>(buf, tw, tid);
+    fft_stage_pow2<N, R, NS, COUNT, STRIDE, NT, SW>(buf, tw, tid);
+    fft_pow2_inplace<N, COUNT, STRIDE, NT, SW, NS * R>(buf, tw, tid);
   }
 }
 
@@ -402,7 +447,6 @@ __device__ __forceinline__ void fft_pow2_inplace(float2* buf, const float2* __re
 // while the remaining length allows it, then 8, 4, 5, 3, 2, so that 720 takes three
 // stages instead of the five of its prime-power split.  A thread takes
 // ceil(COUNT * N / R / NT) butterflies per stage.
-constexpr bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 constexpr int mixed_stage_radix(int rem) {
   return rem % 12 == 0 ? 12 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 5 == 0 ? 5 : rem % 3 == 0 ? 3 : 2;
 }
@@ -415,7 +459,7 @@ constexpr bool mixed_supported(int n) {
   return n == 1;
 }
 
-template <int N, int R, int NS, int COUNT, int STRIDE, int NT>
+template <int N, int R, int NS, int COUNT, int STRIDE, int NT, bool SW>
 __device__ __forceinline__ void fft_stage_mixed(float2* buf, const float2* __restrict__ tw, unsigned tid) {
   constexpr unsigned NB = N / R, TWS = N / (NS * R), TOTAL = COUNT * NB, BM = (TOTAL + NT - 1) / NT;
   static_assert(N % R == 0, "the radix divides the remaining length");
@@ -427,7 +471,7 @@ __device__ __forceinline__ void fft_stage_mixed(float2* buf, const float2* __res
       const unsigned t = idx / NB, j = idx % NB;
       const float2* src = buf + t * STRIDE;
 #pragma unroll
-      for (unsigned r = 0; r < R; ++r) v[b][r] = src[fpad(j + r * NB)];
+      for (unsigned r = 0; r < R; ++r) v[b][r] = src[lds_pos<N, SW>(j + r * NB)];
     }
   }
   stage_barrier<true>();
@@ -444,37 +488,37 @@ __device__ __forceinline__ void fft_stage_mixed(float2* buf, const float2* __res
       float2* dst = buf + t * STRIDE;
       const unsigned base = (j - k) * R + k;
 #pragma unroll
-      for (unsigned r = 0; r < R; ++r) dst[fpad(base + r * NS)] = v[b][r];
+      for (unsigned r = 0; r < R; ++r) dst[lds_pos<N, SW>(base + r * NS)] = v[b][r];
     }
   }
   stage_barrier<true>();
 }
 
-template <int N, int COUNT, int STRIDE, int NT, int NS = 1>
+template <int N, int COUNT, int STRIDE, int NT, bool SW, int NS = 1>
 __device__ __forceinline__ void fft_mixed_inplace(float2* buf, const float2* __restrict__ tw, unsigned tid) {
   if constexpr (NS < N) {
     constexpr int R = mixed_stage_radix(N / NS);
-    fft_stage_mixed<N, R, NS, COUNT, STRIDE, NT>(buf, tw, tid);
-    fft_mixed_inplace<N, COUNT, STRIDE, NT, NS * R>(buf, tw, tid);
+    fft_stage_mixed<N, R, NS, COUNT, STRIDE, NT, SW>(buf, tw, tid);
+    fft_mixed_inplace<N, COUNT, STRIDE, NT, SW, NS * R>(buf, tw, tid);
   }
 }
 
-// The FFT of the streaming kernels (1024 threads, padded in-place layout, LDS twiddles):
+// The FFT of the streaming kernels (1024 threads, in-place layout lds_pos, LDS twiddles):
 // the compile-time forms for NC > 0 (NC = d.n; powers of two and the mixed-radix lengths
 // above), the run-time form for NC = 0.  In the compile-time forms the thread index
 // passes through an empty asm statement, so that the stages' addresses are formed here
 // rather than held in registers across the caller's loop (they depend on nothing else
 // that changes).
-template <int NC, int COUNT>
+template <int NC, int COUNT, bool SW>
 __device__ __forceinline__ void fft_stream(float2* buf, int stride, const FftDesc& d, const float2* __restrict__ tw) {
   if constexpr (NC > 0) {
     unsigned tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     if constexpr (is_pow2(NC)) {
-      fft_pow2_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+      fft_pow2_inplace<NC, COUNT, lds_span<NC, SW>(NC), 1024, SW>(buf, tw, tid);
     } else {
       static_assert(mixed_supported(NC), "a length of radices 12, 8, 4, 5, 3, 2");
-      fft_mixed_inplace<NC, COUNT, fpad(NC - 1) + 2, 1024>(buf, tw, tid);
+      fft_mixed_inplace<NC, COUNT, lds_span<NC, SW>(NC), 1024, SW>(buf, tw, tid);
     }
   } else {
     fft_lds_inplace_tw<true, true>(buf, COUNT, stride, d, tw);

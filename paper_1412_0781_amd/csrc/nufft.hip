@@ -184,11 +184,12 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
                                                              const float* __restrict__ deconv, FftDesc fd,
                                                              const float2* __restrict__ tw, int L, int M2, int hw,
                                                              int nimg, int U) {
+  constexpr bool SW = grid_swizzle(NC);  // LDS layout of the transforms
   constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
-  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * lds_span<NC, SW>(NM)];
   __shared__ float2 s_tw[NM];
   __shared__ float s_dec[NM / 2];
-  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
+  const int N = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(N);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;  // row blocks per image
   const int total = nimg * nrb;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
           for (int i = 0; i < 4; ++i) {
             int pos = x0 + b0 + i;
             pos += (pos < 0) ? N : 0;
-            row[2 * fpad(pos)] = vv[i] * da * s_dec[b0 + i];
+            row[2 * lds_pos<NC, SW>(pos)] = vv[i] * da * s_dec[b0 + i];
           }
         }
       }
@@ -238,11 +239,11 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
     for (int z = tid & 63; z < N - L; z += 64) {  // columns past the image, wrapped
       int pos = x0 + L + z;
       pos -= (pos >= N) ? N : 0;
-      zrow[fpad(pos)] = make_float2(0.f, 0.f);
+      zrow[lds_pos<NC, SW>(pos)] = make_float2(0.f, 0.f);
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_stream<NC, RP>(s_buf, S, fd, s_tw);
+    fft_stream<NC, RP, SW>(s_buf, S, fd, s_tw);
     // unpack: row a: (Z(m) + conj Z(-m)) / 2, row a+1: (Z(m) - conj Z(-m)) / (2i); lanes over the rows
     float2* out = g1 + (size_t)im * M2 * L;
     const int ru = tid & 31, au = a0 + ru;  // the unpacking lanes run over the unit's rows
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
         int m2 = mi - hw;
         int mp = m2 < 0 ? m2 + N : m2;
         int mn = m2 > 0 ? N - m2 : -m2;
-        float2 z1 = s_buf[pp * S + fpad(mp)], z2 = cconj(s_buf[pp * S + fpad(mn)]);
+        float2 z1 = s_buf[pp * S + lds_pos<NC, SW>(mp)], z2 = cconj(s_buf[pp * S + lds_pos<NC, SW>(mn)]);
         float2 v;
         if (which == 0) {
           v = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y + z2.y));
@@ -276,11 +277,12 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(cons
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const int2* __restrict__ gcols, int L, int M2,
                                                              int nimg, int ngrp, int U) {
+  constexpr bool SW = grid_swizzle(NC);  // LDS layout of the transforms
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
   static_assert(G * 64 == 1024, "64 threads per image slot");
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * lds_span<NC, SW>(NM)];
   __shared__ float2 s_tw[NM];
-  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2;
+  const int N = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(N);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = M2 * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -309,23 +311,23 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(cons
       if (a < L) {
         int pos = x0 + a;
         pos += (pos < 0) ? N : 0;
-        row[fpad(pos)] = pre[q];
+        row[lds_pos<NC, SW>(pos)] = pre[q];
       }
     }
     for (int z = ai; z < N - L; z += 64) {  // the columns past the image, wrapped
       int pos = x0 + L + z;
       pos -= (pos >= N) ? N : 0;
-      row[fpad(pos)] = make_float2(0.f, 0.f);
+      row[lds_pos<NC, SW>(pos)] = make_float2(0.f, 0.f);
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_stream<NC, G>(s_buf, S, fd, s_tw);
+    fft_stream<NC, G, SW>(s_buf, S, fd, s_tw);
     const int c = tid & (G - 1);
     float2* dst = g + ((size_t)m2 * ngrp + grp) * N * G + c;
     const int2 rg = gcols[m2];
     for (int ic = rg.x + tid / G; ic <= rg.y; ic += nthr / G) {
       const int m1 = ic < 0 ? ic + N : ic;
-      st_out(&dst[(size_t)m1 * G], s_buf[c * S + fpad(m1)]);
+      st_out(&dst[(size_t)m1 * G], s_buf[c * S + lds_pos<NC, SW>(m1)]);
     }
     stage_barrier<true>();
   }
@@ -524,12 +526,13 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_angular_stream(c
                                                              const float2* __restrict__ angtw,
                                                              const int* __restrict__ kring, int n_xi, int K,
                                                              int ngrp, int U, float scale) {
+  constexpr bool SW = angular_swizzle(NC);  // LDS layout of the transforms
   constexpr int G = kImgGroup, HM = stream_cap(NC, kAngStreamH);
   constexpr int PF = (HM * G / 2 + 1023) / 1024;  // (m, gg) items per thread at the largest H
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(HM - 1) + 2)];  // packed transforms, padded
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * lds_span<NC, SW>(HM)];  // packed transforms, padded
   __shared__ float2 s_tw[HM];
   __shared__ float2 s_angtw[HM];
-  const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
+  const int H = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(H), Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -562,21 +565,21 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_angular_stream(c
       if (e < nitem) {
         const int gg = e & (G - 1), m = e / G;
         const float4 f = pre[p];
-        s_buf[gg * S + fpad(m)] = make_float2(f.x + f.y, f.z + f.w);
-        s_buf[gg * S + fpad(m + Hh)] = make_float2(f.x - f.y, f.z - f.w);
+        s_buf[gg * S + lds_pos<NC, SW>(m)] = make_float2(f.x + f.y, f.z + f.w);
+        s_buf[gg * S + lds_pos<NC, SW>(m + Hh)] = make_float2(f.x - f.y, f.z - f.w);
       }
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
-    fft_stream<NC, G>(s_buf, S, fd, s_tw);
+    fft_stream<NC, G, SW>(s_buf, S, fd, s_tw);
     const int j = u / ngrp, grp = u - j * ngrp;
     const int gg = tid & (G - 1);
     float2* dst = Fh + (((size_t)grp * n_xi + j) * (K + 1)) * G + gg;
     // only the k whose radial sums read ring j (the table of every larger k is negligible there)
     const int Kj = kring[j];
     for (int k = tid / G; k <= Kj; k += nthr / G) {
-      float2 zk = s_buf[gg * S + fpad(k)];
-      float2 zc = cconj(s_buf[gg * S + fpad(k == 0 ? 0 : H - k)]);
+      float2 zk = s_buf[gg * S + lds_pos<NC, SW>(k)];
+      float2 zc = cconj(s_buf[gg * S + lds_pos<NC, SW>(k == 0 ? 0 : H - k)]);
       // S(k) = (Z(k) + conj Z(H-k))/2 + e^{-2 pi i k / n_theta} (Z(k) - conj Z(H-k)) / (2i)
       float2 e = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
       float2 d = csub(zk, zc);
@@ -661,12 +664,13 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(c
                                                              FftDesc fd, const float2* __restrict__ tw,
                                                              const float2* __restrict__ angtw, int n_xi, int K,
                                                              int nimg, int ngrp, int U, float scale) {
+  constexpr bool SW = angular_swizzle(NC);  // LDS layout of the transforms
   constexpr int G = kImgGroup, HM = stream_cap(NC, kAngStreamH);
   constexpr int PF = (HM * G / 2 + 1023) / 1024;  // pairs of spectrum values per thread (K + 1 <= H)
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(HM - 1) + 2)];
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * lds_span<NC, SW>(HM)];
   __shared__ float2 s_tw[HM];
   __shared__ float2 s_angtw[HM];
-  const int H = NC > 0 ? NC : fd.n, S = fpad(H - 1) + 2, Hh = H / 2;
+  const int H = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(H), Hh = H / 2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = n_xi * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -706,12 +710,12 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(c
         const int k = (2 * e) / G, gg = (2 * e) & (G - 1);
         const float4 d = pre[p];
         const float sr = (k & 1) ? -scale : scale;  // odd k: -i c D_k
-        s_buf[gg * S + fpad(k)] = (k & 1) ? make_float2(d.y * scale, d.x * sr) : make_float2(d.x * scale, d.y * scale);
-        s_buf[(gg + 1) * S + fpad(k)] =
+        s_buf[gg * S + lds_pos<NC, SW>(k)] = (k & 1) ? make_float2(d.y * scale, d.x * sr) : make_float2(d.x * scale, d.y * scale);
+        s_buf[(gg + 1) * S + lds_pos<NC, SW>(k)] =
             (k & 1) ? make_float2(d.w * scale, d.z * sr) : make_float2(d.z * scale, d.w * scale);
       }
     }
-    for (int e = nval + tid; e < H * G; e += nthr) s_buf[(e & (G - 1)) * S + fpad(e / G)] = make_float2(0.f, 0.f);
+    for (int e = nval + tid; e < H * G; e += nthr) s_buf[(e & (G - 1)) * S + lds_pos<NC, SW>(e / G)] = make_float2(0.f, 0.f);
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);  // in flight through the transform and the writes below
     // Zin(k') = (Y_k' + Y_{k'+H}) + i e^{+i pi k'/H} (Y_k' - Y_{k'+H}), Y_k' = E_k'/2 (Re E_0 at 0),
@@ -719,8 +723,8 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(c
     for (int e = tid; e < (Hh + 1) * G; e += nthr) {
       const int kp = e / G, gg = e & (G - 1), km = H - kp;
       float2* row = s_buf + gg * S;
-      const float2 a = row[fpad(kp)];
-      const float2 b = kp == 0 ? make_float2(0.f, 0.f) : row[fpad(km)];
+      const float2 a = row[lds_pos<NC, SW>(kp)];
+      const float2 b = kp == 0 ? make_float2(0.f, 0.f) : row[lds_pos<NC, SW>(km)];
       auto zin = [&](int k, float2 ek, float2 eo) {  // ek = E_k, eo = E_{H-k}
         const float2 y0 = k == 0 ? make_float2(ek.x, 0.f) : make_float2(0.5f * ek.x, 0.5f * ek.y);
         const float2 y1 = k == 0 ? make_float2(0.f, 0.f) : make_float2(0.5f * eo.x, -0.5f * eo.y);
@@ -728,18 +732,18 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(c
         const float2 zo = cmul(cconj(s_angtw[k]), csub(y0, y1));
         return cconj(make_float2(ze.x - zo.y, ze.y + zo.x));
       };
-      row[fpad(kp)] = zin(kp, a, b);
-      if (kp != 0 && kp != Hh) row[fpad(km)] = zin(km, b, a);
+      row[lds_pos<NC, SW>(kp)] = zin(kp, a, b);
+      if (kp != 0 && kp != Hh) row[lds_pos<NC, SW>(km)] = zin(km, b, a);
     }
     stage_barrier<true>();
-    fft_stream<NC, G>(s_buf, S, fd, s_tw);
+    fft_stream<NC, G, SW>(s_buf, S, fd, s_tw);
     // z_m = conj(res_m) = s'_{2m} + i s'_{2m+1};  Q_l = (s'_l + s'_{l+H}) + i (s'_l - s'_{l+H})
     float2* dst = Q + (size_t)u * H * G;
     for (int e = tid; e < H * G; e += nthr) {
       const int l = e / G, gg = e & (G - 1);
       const float2* row = s_buf + gg * S;
       auto sp = [&](int t) -> float {
-        const float2 z = row[fpad(t >> 1)];
+        const float2 z = row[lds_pos<NC, SW>(t >> 1)];
         return (t & 1) ? -z.y : z.x;
       };
       const float a = sp(l), b = sp(l + H);
@@ -955,11 +959,12 @@ template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __restrict__ Y, float2* __restrict__ Zc,
                                                             FftDesc fd, const float2* __restrict__ tw, int L,
                                                             int nimg, int ngrp, int U) {
+  constexpr bool SW = grid_swizzle(NC);  // LDS layout of the transforms
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
   constexpr int PF = (NM * G / 2 + 1023) / 1024;  // pairs of values per thread
-  __shared__ __attribute__((aligned(16))) float2 s_buf[G * (fpad(NM - 1) + 2)];
+  __shared__ __attribute__((aligned(16))) float2 s_buf[G * lds_span<NC, SW>(NM)];
   __shared__ float2 s_tw[NM];
-  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int N = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(N), Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int total = Nh * ngrp;
   const int u0 = xcd_remap(blockIdx.x, gridDim.x) * U;
@@ -987,13 +992,13 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
       if (e < nval) {
         const int m1 = (2 * e) / G, c = (2 * e) & (G - 1);
         const float4 v = pre[q];
-        s_buf[c * S + fpad(m1)] = make_float2(v.x, -v.y);
-        s_buf[(c + 1) * S + fpad(m1)] = make_float2(v.z, -v.w);
+        s_buf[c * S + lds_pos<NC, SW>(m1)] = make_float2(v.x, -v.y);
+        s_buf[(c + 1) * S + lds_pos<NC, SW>(m1)] = make_float2(v.z, -v.w);
       }
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_stream<NC, G>(s_buf, S, fd, s_tw);
+    fft_stream<NC, G, SW>(s_buf, S, fd, s_tw);
     {
       const int c = tid >> 6, i = grp * G + c;  // thread t writes image slot t / 64 at x1 = t % 64 + 64 q
       if (i < nimg) {
@@ -1001,7 +1006,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
         for (int a = tid & 63; a < L; a += 64) {
           int pos = x0 + a;
           pos += (pos < 0) ? N : 0;
-          dst[a] = cconj(s_buf[c * S + fpad(pos)]);
+          dst[a] = cconj(s_buf[c * S + lds_pos<NC, SW>(pos)]);
         }
       }
     }
@@ -1020,12 +1025,13 @@ template <int NC>
 __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __restrict__ Zc, float* __restrict__ img,
                                                             const float* __restrict__ deconv, FftDesc fd,
                                                             const float2* __restrict__ tw, int L, int nimg, int U) {
+  constexpr bool SW = grid_swizzle(NC);  // LDS layout of the transforms
   constexpr int RP = 16, NM = stream_cap(NC, kGridStreamN);
   constexpr int PF = ((NM / 2 + 1) * RP + 1023) / 1024;  // row-pair values per thread
-  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * (fpad(NM - 1) + 2)];
+  __shared__ __attribute__((aligned(16))) float2 s_buf[RP * lds_span<NC, SW>(NM)];
   __shared__ float2 s_tw[NM];
   __shared__ float s_dec[NM / 2];
-  const int N = NC > 0 ? NC : fd.n, S = fpad(N - 1) + 2, Nh = N / 2 + 1;
+  const int N = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(N), Nh = N / 2 + 1;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nrb = ((L + 1) / 2 + RP - 1) / RP;
   const int total = nimg * nrb;
@@ -1059,13 +1065,13 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
         float4 v = pre[q];  // (r_a(ms), r_{a+1}(ms))
         if (ms == 0 || 2 * ms == N) v.y = v.w = 0.f;
         float2* row = s_buf + p * S;
-        row[fpad(ms)] = make_float2(v.x - v.w, -(v.y + v.z));
-        if (ms > 0 && 2 * ms < N) row[fpad(N - ms)] = make_float2(v.x + v.w, v.y - v.z);
+        row[lds_pos<NC, SW>(ms)] = make_float2(v.x - v.w, -(v.y + v.z));
+        if (ms > 0 && 2 * ms < N) row[lds_pos<NC, SW>(N - ms)] = make_float2(v.x + v.w, v.y - v.z);
       }
     }
     stage_barrier<true>();
     if (u + 1 < u1) load(u + 1);
-    fft_stream<NC, RP>(s_buf, S, fd, s_tw);
+    fft_stream<NC, RP, SW>(s_buf, S, fd, s_tw);
     {
       const int r = tid >> 5, a = a0 + r;  // thread t writes row t / 32 at x2 = t % 32 + 32 q
       if (a < L) {
@@ -1075,7 +1081,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_rows_stream(const float2* __res
         for (int b = tid & 31; b < L; b += 32) {
           int pos = x0 + b;
           pos += (pos < 0) ? N : 0;
-          const float2 z = row[fpad(pos)];  // conj of the inverse transform
+          const float2 z = row[lds_pos<NC, SW>(pos)];  // conj of the inverse transform
           dst[b] = ((r & 1) ? -z.y : z.x) * da * s_dec[b];
         }
       }
