@@ -140,12 +140,15 @@ def stage_peak_tflops(stage: str, precision: str) -> float:
     return FP32_PEAK_TFLOPS
 
 
-def step_roofline(plan, precision: str, stages: dict, images: int, step_ms: float, n: int) -> dict:
+def step_roofline(plan, precision: str, stages: dict, images: int, step_ms: float, n: int,
+                  passes: int = 1) -> dict:
     """Whole-step roofline: sum over the step's stages of max(bytes / HBM peak, flops / peak)
     per image, divided by the measured time per image; also each stage's own fraction (its
     bound over its measured average time per image) and the bound of a fully fused path,
     which moves only the image and its coefficients through HBM.  `images` = images over all
-    timed steps (the stage totals' span), n = images per step."""
+    timed steps, n = images per step, `passes` = times each image runs through every stage in
+    one step (2 for forward + backward of the differentiation workload, whose backward pass
+    applies the adjoint of each transform: T for T* and T* for T)."""
     bpi = algorithmic_bytes_per_image(plan)
     fpi = algorithmic_flops_per_image(plan)
     bound = 0.0
@@ -153,17 +156,19 @@ def step_roofline(plan, precision: str, stages: dict, images: int, step_ms: floa
     present = [st for st in bpi if st in stages and stages[st]["launches"]]
     for st in present:
         t = max(bpi[st] / (HBM_PEAK_GBS * 1e9), fpi[st] / (stage_peak_tflops(st, precision) * 1e12))
-        bound += t
-        per_stage[st] = round(t / (stages[st]["total_ms"] * 1e-3 / images), 4)
+        bound += passes * t
+        per_stage[st] = round(t / (stages[st]["total_ms"] * 1e-3 / (images * passes)), 4)
     measured = step_ms * 1e-3 / n
-    irreducible = 4 * plan.L * plan.L + 8 * plan.p_half
+    # image in, coefficients out (expansion) and back (synthesis), per pass
+    directions = sum(1 for pre in ("fwd_", "adj_") if any(st.startswith(pre) for st in present))
+    irreducible = passes * directions * (4 * plan.L * plan.L + 8 * plan.p_half)
     fused = max(irreducible / (HBM_PEAK_GBS * 1e9),
-                sum(fpi[st] / (stage_peak_tflops(st, precision) * 1e12) for st in present))
+                passes * sum(fpi[st] / (stage_peak_tflops(st, precision) * 1e12) for st in present))
     return {"bound_us_per_image": round(bound * 1e6, 4), "measured_us_per_image": round(measured * 1e6, 4),
             "frac": round(bound / measured, 4), "fused_bound_us_per_image": round(fused * 1e6, 4),
             "fused_frac": round(fused / measured, 4), "stage_frac": per_stage,
-            "mflop_per_image": round(sum(fpi[st] for st in present) / 1e6, 2),
-            "unfused_MB_per_image": round(sum(bpi[st] for st in present) / 1e6, 3),
+            "mflop_per_image": round(passes * sum(fpi[st] for st in present) / 1e6, 2),
+            "unfused_MB_per_image": round(passes * sum(bpi[st] for st in present) / 1e6, 3),
             "irreducible_MB_per_image": round(irreducible / 1e6, 3)}
 
 
@@ -171,7 +176,8 @@ def kernel_roofline(plan, stages: dict, images: int, precision: str) -> dict:
     """The dominant kernel (largest total time among the stages with known algorithmic bytes)
     against its roofline: HBM when its arithmetic intensity is below the ridge point of its
     unit, else that unit's peak.  achieved = algorithmic bytes (or flops) of one launch over
-    the average launch duration measured with HIP events on the launch stream."""
+    the average launch duration measured with HIP events on the launch stream.  `images` =
+    images the timed region ran through each stage (all of its launches together)."""
     bpi = algorithmic_bytes_per_image(plan)
     fpi = algorithmic_flops_per_image(plan)
     dom = max((s for s in stages if s in bpi), key=lambda s: stages[s]["total_ms"])
@@ -640,6 +646,7 @@ def main():
 
     forms, profs = {}, {}
     images = coeffs = st = None
+    passes = 1
     steps_done = args.steps
     from paper_1412_0781_amd.workload import noise_sigma
     sigma = noise_sigma(plan, args.snr)
@@ -672,6 +679,7 @@ def main():
         profs["fp32"] = prof
         timed_images = args.n * args.steps
         n_step = args.n
+        passes = 2  # the backward pass runs the expansion and the synthesis once more
     head = wk["head"] if wk["head"] in forms else next(iter(forms))
 
     eig_ms = None
@@ -688,9 +696,9 @@ def main():
     del images, coeffs
 
     stages = _stage_totals(profs[head])
-    roofline = kernel_roofline(plan, stages, timed_images, head)
+    roofline = kernel_roofline(plan, stages, timed_images * passes, head)
     step = {prec: step_roofline(plan, prec, _stage_totals(profs[prec]), timed_images, forms[prec]["ms_per_step"],
-                                n_step)
+                                n_step, passes)
             for prec in forms}
     log(f"roofline: {roofline}")
     log(f"step roofline: {step}")
