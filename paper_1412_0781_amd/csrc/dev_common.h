@@ -26,6 +26,7 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 #endif
 typedef float fb_f2v __attribute__((ext_vector_type(2)));
 typedef float fb_f4v __attribute__((ext_vector_type(4)));
+typedef unsigned fb_u4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void st_out(float2* p, float2 v) {
   if constexpr (FB_NT_STORES != 0) {
     const fb_f2v w = {v.x, v.y};

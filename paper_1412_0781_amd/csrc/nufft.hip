@@ -272,6 +272,9 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_rows_stream(cons
 // only the centred m1 range gcols[m2] that the gather's boxes read.  Thread t stages image
 // slot t / 64 of the group at the columns t % 64 + 64 q, so its positions in LDS (and in the
 // zero padding) are the same for every unit and its loads are one run per image.
+// blocks of 64 columns in which the columns form reads an image row of at most n / 2 values
+constexpr int cols_stream_blocks(int n) { return (n / 2 + 63) / 64; }
+
 template <int NC>
 __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(const float2* __restrict__ g1, float2* __restrict__ g,
                                                              FftDesc fd, const float2* __restrict__ tw,
@@ -290,28 +293,33 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_fwd_cols_stream(cons
   const int x0 = -((L - 1 + 1) / 2);
   for (int i = tid; i < N; i += nthr) s_tw[i] = tw[fd.tw_off + i];
   __syncthreads();
-  constexpr int PF = (NM / 2 + 63) / 64;  // L <= N / 2
+  // column blocks per row: L <= N / 2; for a compiled length L > 64 (PF - 1) (checked at launch)
+  constexpr int PF = cols_stream_blocks(NC > 0 ? NC : NM);
   const int ci = tid >> 6, ai = tid & 63;
   float2* row = s_buf + ci * S;
   float2 pre[PF];
   // unit u = (m2, group): groups vary fastest, so consecutive units write consecutive runs of G
+  // the loads are unconditional (a conditional load is waited for where it is issued, which
+  // would undo the prefetch): a slot past the last image reads the last image and a column
+  // past L reads column L - 1, and the LDS stores put zeros in their place
   auto load = [&](int u) {
     const int m2 = u / ngrp, i0 = (u - m2 * ngrp) * G;
-    const bool live = i0 + ci < nimg;
-    const float2* src = g1 + ((size_t)(i0 + ci) * M2 + m2) * L + ai;
+    const float2* src = g1 + ((size_t)min(i0 + ci, nimg - 1) * M2 + m2) * L;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) pre[q] = (live && ai + 64 * q < L) ? src[64 * q] : make_float2(0.f, 0.f);
+    for (int q = 0; q < PF; ++q)  // (the run-time-length form sizes PF for its largest N: clamps all)
+      pre[q] = src[q + 1 < PF && NC > 0 ? ai + 64 * q : min(ai + 64 * q, L - 1)];
   };
   if (u0 < u1) load(u0);
   for (int u = u0; u < u1; ++u) {
     const int m2 = u / ngrp, grp = u - m2 * ngrp;
+    const bool live = grp * G + ci < nimg;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int a = ai + 64 * q;
       if (a < L) {
         int pos = x0 + a;
         pos += (pos < 0) ? N : 0;
-        row[lds_pos<NC, SW>(pos)] = pre[q];
+        row[lds_pos<NC, SW>(pos)] = live ? pre[q] : make_float2(0.f, 0.f);
       }
     }
     for (int z = ai; z < N - L; z += 64) {  // the columns past the image, wrapped
@@ -755,16 +763,17 @@ __global__ __launch_bounds__(1024, stream_waves(NC)) void k_adj_angular_stream(c
 
 // ---------------------------------------------------------------------------
 // adjoint spread (gather form, tiled): Q [n_xi][group][H][16] -> Y [N/2+1][group][N][16]
-// workgroup = (cell of kSpreadRows x kSpreadCols output points, one of its nsub
-// workgroups, slice of kSpreadSlice image groups); it walks its (chunk, image group) steps,
-// chunks outer, with the next step's node values (one 128-byte line per node: 16 images)
-// and, when the chunk changes, entries on their way into registers.  A cell of several
-// chunks keeps the partial sums of its (at most kSpreadHeavyGroups) image groups in
+// workgroup = (tile: pairs of a cell of kSpreadRows x kSpreadCols output points, one of its
+// nsub workgroups, slice of kSpreadSlice image groups); it walks its (chunk, image group)
+// steps, chunks outer, with the next step's node values (one 128-byte line per node: 16
+// images) and, when the chunk changes, entries on their way into registers.  A tile of
+// several chunks keeps the partial sums of its (at most kSpreadHeavyGroups) image groups in
 // registers, added in chunk order.  Per step the values and entries sit in LDS and lane
-// (point pair, image pair) sums the pair's entries in their fixed order, one 16-byte LDS
-// read of node values for eight FMAs, so the result is the same on every run.  Entries
-// come in aligned batches of kSpreadBatch; spreading weights are non-negative, so each
-// weight carries its point's conjugate flag as its sign.
+// (slot, image pair) sums the slot's entries in their fixed order, one 16-byte LDS read of
+// node values for eight FMAs; the slots of a pair then add their sums in a fixed pattern,
+// so the result is the same on every run.  Entries come in aligned batches of
+// kSpreadBatch; spreading weights are non-negative, so each weight carries its point's
+// conjugate flag as its sign.
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__ Q, float2* __restrict__ Y,
@@ -772,6 +781,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
                                                       const SpreadBlock* __restrict__ blocks,
                                                       const SpreadChunk* __restrict__ chunks,
                                                       const int* __restrict__ snodes, const int* __restrict__ sseg,
+                                                      const uint16_t* __restrict__ sslot,
                                                       const SpreadLocal* __restrict__ sent, int N, int Nh, int H,
                                                       int ngrp, int nsl) {
   constexpr int G = kImgGroup, IP = G / 2, NP = kSpreadPairs, CC = kSpreadCols;
@@ -781,21 +791,42 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   static_assert(KQ * NT == kSpreadNodes * IP && KE * NT == EV, "staging slots per lane");
   static_assert(sizeof(SpreadLocal) == 12 && kSpreadBatch == 4, "a batch is three 16-byte vectors");
   static_assert(kSpreadHeavyGroups == 4, "four partial-sum sets");
-  __shared__ __attribute__((aligned(16))) float4 s_q[kSpreadNodes * IP];
-  __shared__ __attribute__((aligned(16))) uint4 s_e[EV];
+  // staging in native vector types, so that the register copies below stay in registers
+  __shared__ __attribute__((aligned(16))) fb_f4v s_q[kSpreadNodes * IP];
+  __shared__ __attribute__((aligned(16))) fb_u4v s_e[EV];
   const int tid = threadIdx.x, ip = tid & (IP - 1), pp = tid / IP;
   const int slice = (int)(blockIdx.x % (unsigned)nsl);
   const SpreadBlock bk = blocks[blockIdx.x / (unsigned)nsl];
   const SpreadTile t = tiles[bk.tile];
   const int nch = t.c1 - t.c0;
   const int gb = slice * kSpreadSlice + bk.sub, ge = min(ngrp, (slice + 1) * kSpreadSlice);
-  const int m2 = t.m2 + 2 * (pp / CC), m1 = t.m1 + pp % CC;
-  const bool outA = m2 < Nh && m1 < N, outB = m2 + 1 < Nh && m1 < N;
+  // slot pp sums part of the entries of pair pr; the first of the pair's 2^lg2s slots (an
+  // aligned run of lane groups in this wavefront) writes the pair's two points
+  const unsigned sl = sslot[t.slots + pp];
+  const int pr = sl & 63, lg2s = (sl >> 8) & 3;
+  const bool lead = !(sl & kSpreadIdleSlot) && (pp & ((1 << lg2s) - 1)) == 0;
+  const int m2 = t.m2 + 2 * (pr / CC), m1 = t.m1 + pr % CC;
+  const bool outA = lead && m2 < Nh && m1 < N, outB = lead && m2 + 1 < Nh && m1 < N;
   float4* Y4 = (float4*)Y;
   auto yidx = [&](int r, int g) { return (((size_t)r * ngrp + g) * N + m1) * IP + ip; };
   auto put = [&](int g, float4 a, float4 b) {
     if (outA) Y4[yidx(m2, g)] = a;
     if (outB) Y4[yidx(m2 + 1, g)] = b;
+  };
+  // the slots of one pair add their sums, slots 1, 2, 4 apart in turn (every lane of the
+  // wavefront takes part; x + y = y + x, so all slots of a pair end with the same bits)
+  auto gather_slots = [&](float4& a, float4& b) {
+    for (int k = 1; k < t.maxs; k <<= 1) {
+      const int lanes = k * IP;
+      const float4 oa = make_float4(__shfl_xor(a.x, lanes), __shfl_xor(a.y, lanes), __shfl_xor(a.z, lanes),
+                                    __shfl_xor(a.w, lanes));
+      const float4 ob = make_float4(__shfl_xor(b.x, lanes), __shfl_xor(b.y, lanes), __shfl_xor(b.z, lanes),
+                                    __shfl_xor(b.w, lanes));
+      if (k < (1 << lg2s)) {
+        a = make_float4(a.x + oa.x, a.y + oa.y, a.z + oa.z, a.w + oa.w);
+        b = make_float4(b.x + ob.x, b.y + ob.y, b.z + ob.z, b.w + ob.w);
+      }
+    }
   };
   if (nch == 0) {  // no node reaches this cell
     for (int g = gb; g < ge; g += t.nsub) put(g, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f));
@@ -804,46 +835,42 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   // image groups of this workgroup; a cell of several chunks has nsub >= 4, so ng <= 4
   const int ng = gb < ge ? (ge - gb + t.nsub - 1) / t.nsub : 0;
   const int nsteps = ng * nch;
-  const float4* Q4 = (const float4*)Q;
-  const uint4* E4 = (const uint4*)sent;
+  const fb_f4v* Q4 = (const fb_f4v*)Q;
+  const fb_u4v* E4 = (const fb_u4v*)sent;
   const size_t gstride = (size_t)H * IP;  // float4s between image groups of one node
   // next step's chunk data, held in registers
   int nl_n = 0, ne_n = 0, e0_n = 0, e1_n = 0;
   size_t qoff[KQ];
-  uint4 er[KE];
-  float4 qr[KQ];
+  fb_u4v er[KE];
+  fb_f4v qr[KQ];
   auto load_meta_rec = [&](const SpreadChunk ch) {
     nl_n = ch.n1 - ch.n0;
     const int base = sseg[ch.seg];
     ne_n = (sseg[ch.seg + NP] - base) / 4 * 3;  // 16-byte vectors
     e0_n = (sseg[ch.seg + pp] - base) / 4 * 3;
     e1_n = (sseg[ch.seg + pp + 1] - base) / 4 * 3;
+    // every chunk has at least one node and one batch of entries; slots past them load the
+    // last ones again (and are not stored), so that no load is conditional: a conditional
+    // load into a register that lives on is waited for where it is issued
 #pragma unroll
-    for (int k = 0; k < KE; ++k) {
-      const int i = tid + k * NT;
-      if (i < ne_n) er[k] = E4[base / 4 * 3 + i];
-    }
+    for (int k = 0; k < KE; ++k) er[k] = E4[base / 4 * 3 + min(tid + k * NT, ne_n - 1)];
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
-      const int i = tid + k * NT;
-      qoff[k] = 0;
-      if (i < nl_n * IP) {
-        const int jl = snodes[ch.n0 + i / IP];
-        qoff[k] = ((size_t)(jl >> 16) * ngrp * H + (jl & 0xffff)) * IP + (i & (IP - 1));
-      }
+      const int i = min(tid + k * NT, nl_n * IP - 1);
+      const int jl = snodes[ch.n0 + i / IP];
+      qoff[k] = ((size_t)(jl >> 16) * ngrp * H + (jl & 0xffff)) * IP + (i & (IP - 1));
     }
   };
-  auto load_q_into = [&](float4 (&dst)[KQ], int g) {
+  auto load_q_into = [&](fb_f4v (&dst)[KQ], int g) {
 #pragma unroll
-    for (int k = 0; k < KQ; ++k)
-      if (tid + k * NT < nl_n * IP) dst[k] = Q4[qoff[k] + (size_t)g * gstride];
+    for (int k = 0; k < KQ; ++k) dst[k] = Q4[qoff[k] + (size_t)g * gstride];
   };
   auto load_q = [&](int g) { load_q_into(qr, g); };
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
   // entry: byte offset of the node row in s_q, the two points' weights signed by their conjugate flags
-  const char* s_lane = (const char*)s_q + ip * sizeof(float4);
+  const char* s_lane = (const char*)s_q + ip * sizeof(fb_f4v);
   auto acc = [&](unsigned off, unsigned wa_bits, unsigned wb_bits) {
-    const float4 q = *(const float4*)(s_lane + off);
+    const fb_f4v q = *(const fb_f4v*)(s_lane + off);
     const float wsa = __uint_as_float(wa_bits), wa = fabsf(wsa);
     const float wsb = __uint_as_float(wb_bits), wb = fabsf(wsb);
     a0 = fmaf(wa, q.x, a0);
@@ -858,7 +885,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   auto sum_entries = [&](int e0, int e1) {
     a0 = a1 = a2 = a3 = b0 = b1 = b2 = b3 = 0.f;
     for (int e = e0; e < e1; e += 3) {
-      const uint4 v0 = s_e[e], v1 = s_e[e + 1], v2 = s_e[e + 2];
+      const fb_u4v v0 = s_e[e], v1 = s_e[e + 1], v2 = s_e[e + 2];
       acc(v0.x, v0.y, v0.z);
       acc(v0.w, v1.x, v1.y);
       acc(v1.z, v1.w, v2.x);
@@ -870,11 +897,11 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     // groups ahead in two register sets
     if (ng == 0) return;
     load_meta_rec(chunks[t.c0]);
-    float4 qb[KQ];
+    fb_f4v qb[KQ];
     load_q_into(qr, gb);
     if (ng > 1) load_q_into(qb, gb + t.nsub);
     const int e0 = e0_n, e1 = e1_n;
-    auto step = [&](float4 (&cur)[KQ], int gi) {
+    auto step = [&](fb_f4v (&cur)[KQ], int gi) {
       __syncthreads();  // the previous step's readers are done with LDS
 #pragma unroll
       for (int k = 0; k < KQ; ++k)
@@ -887,7 +914,9 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
       __syncthreads();
       if (gi + 2 < ng) load_q_into(cur, gb + (gi + 2) * t.nsub);
       sum_entries(e0, e1);
-      put(gb + gi * t.nsub, make_float4(a0, a1, a2, a3), make_float4(b0, b1, b2, b3));
+      float4 ra = make_float4(a0, a1, a2, a3), rb = make_float4(b0, b1, b2, b3);
+      gather_slots(ra, rb);
+      put(gb + gi * t.nsub, ra, rb);
     };
     for (int gi = 0; gi < ng; gi += 2) {
       step(qr, gi);
@@ -943,7 +972,10 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
       else if (gi == 2) upd(PA2, PB2);
       else upd(PA3, PB3);
     }
-    if (ci == nch - 1) put(g, ra, rb);
+    if (ci == nch - 1) {
+      gather_slots(ra, rb);
+      put(g, ra, rb);
+    }
   }
 }
 
@@ -961,7 +993,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
                                                             int nimg, int ngrp, int U) {
   constexpr bool SW = grid_swizzle(NC);  // LDS layout of the transforms
   constexpr int G = kImgGroup, NM = stream_cap(NC, kGridStreamN);
-  constexpr int PF = (NM * G / 2 + 1023) / 1024;  // pairs of values per thread
+  constexpr int PF = ((NC > 0 ? NC : NM) * G / 2 + 1023) / 1024;  // pairs of values per thread
   __shared__ __attribute__((aligned(16))) float2 s_buf[G * lds_span<NC, SW>(NM)];
   __shared__ float2 s_tw[NM];
   const int N = NC > 0 ? NC : fd.n, S = lds_span<NC, SW>(N), Nh = N / 2 + 1;
@@ -980,7 +1012,7 @@ __global__ __launch_bounds__(1024, 4) void k_adj_cols_stream(const float2* __res
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int e = tid + q * nthr;
-      if (e < nval) pre[q] = src[e];
+      pre[q] = src[min(e, nval - 1)];  // unconditional: stays in flight (items past nval unused)
     }
   };
   if (u0 < u1) load(u0);
@@ -1278,7 +1310,11 @@ hipError_t launch_forward_nufft(const Plan& pl, const float* images, int nimg, f
   const int ngrp = (nimg + kImgGroup - 1) / kImgGroup;
   // streaming forms: 16 transforms in place with 1024 threads; the inputs of one unit (32
   // rows or 16 columns of L <= N / 2 values) are held in registers, the rows as float4
-  const bool stream_ok = stream_length(pl.fft_grid, kGridStreamN) && L % 4 == 0;
+  // (the columns form reads each image row in blocks of 64 and clamps only the last block,
+  // so L must reach into that block: true whenever N is the smallest 2,3,5-smooth even number
+  // >= 2L, as the plan takes it)
+  const bool stream_ok =
+      stream_length(pl.fft_grid, kGridStreamN) && L % 4 == 0 && L > 64 * (cols_stream_blocks(N) - 1);
   if (stream_ok) {
     const int nrb = ((L + 1) / 2 + 15) / 16;
     const long long ur = (long long)nimg * nrb;
@@ -1373,7 +1409,8 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   if (nblk > 0x7fffffffu) return hipErrorInvalidValue;
   pl.prof.begin(ST_ADJ_SPREAD, st);
   hipLaunchKernelGGL((k_adj_spread<NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
-                     pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sent, N, Nh, pl.H, ngrp, nsl);
+                     pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sslot, pl.d_sent, N, Nh, pl.H, ngrp,
+                     nsl);
   pl.prof.end(st);
   const bool stream_ok = stream_length(pl.fft_grid, kGridStreamN) && L % 2 == 0;
   if (stream_ok) {

@@ -293,6 +293,7 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     pl.schunks.clear();
     pl.snodes.clear();
     pl.sseg.clear();
+    pl.sslot.clear();
     pl.sent.clear();
     pl.sent.reserve(pl.csr.size());
     struct PairTmp {
@@ -302,8 +303,7 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
     std::vector<int> where(pl.nodes.size(), -1);  // node -> index in the cell's node list
     std::vector<int> cell_nodes;
     std::vector<std::vector<PairTmp>> plist(NP);
-    std::vector<std::vector<uint8_t>> node_pairs;  // pairs reached by each listed node (per key)
-    std::vector<int> pcnt(NP);
+    std::vector<int> chunk_cnt;  // entries per (chunk, pair) of a trial chunk count
     std::vector<std::pair<uint32_t, float>> la, lb;
     auto point_list = [&](int m2, int m1, std::vector<std::pair<uint32_t, float>>& out) {
       out.clear();
@@ -316,9 +316,38 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
       std::stable_sort(out.begin(), out.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
     };
     auto padded = [](int n) { return (n + kSpreadBatch - 1) / kSpreadBatch * kSpreadBatch; };
+    // lane groups (slots) of a pair: the pairs of a cell are taken by 1, 2, 4 or 8 tiles of
+    // kSpreadPairs slots each; in a tile every pair starts with one slot and the pair with
+    // the most entries per slot has its slots doubled while slots remain (at most 8: one
+    // wavefront); a pair's slots form an aligned run inside one wavefront, so the kernel adds
+    // their partial sums with a butterfly over lanes.  Returns the most entries of one slot.
+    std::vector<int> slot_of(NP), split_of(NP);
+    auto allocate = [&](int p0, int np) {
+      int left = NP - np;
+      for (int p = p0; p < p0 + np; ++p) split_of[p] = 1;
+      for (;;) {
+        int best = -1;
+        double bv = 0.0;
+        for (int p = p0; p < p0 + np; ++p) {
+          const double v = (double)plist[p].size() / split_of[p];
+          if (split_of[p] < 8 && split_of[p] <= left && !plist[p].empty() && v > bv) {
+            bv = v;
+            best = p;
+          }
+        }
+        if (best < 0) break;
+        left -= split_of[best];
+        split_of[best] *= 2;
+      }
+      size_t most = 0;
+      for (int p = p0; p < p0 + np; ++p)
+        most = std::max(most, (plist[p].size() + split_of[p] - 1) / split_of[p]);
+      return most;
+    };
+    std::vector<int> order_p(NP);
+    std::vector<uint16_t> tile_slots(NP);
     for (int cy = 0; cy < ncy; ++cy)
       for (int cx = 0; cx < ncx; ++cx) {
-        cell_nodes.clear();
         for (int pp = 0; pp < NP; ++pp) {
           const int m2 = cy * CR + 2 * (pp / CC), m1 = cx * CC + pp % CC;
           point_list(m2, m1, la);
@@ -339,62 +368,113 @@ int build_host_plan(int L, double c, double R, Plan& pl) {
               ++k;
             }
           }
-          for (const PairTmp& t : L2) {
-            const int nd = (int)(t.key >> 1);
-            if (where[nd] < 0) {
-              where[nd] = (int)cell_nodes.size();
-              cell_nodes.push_back(nd);
-              if (node_pairs.size() < cell_nodes.size()) node_pairs.resize(cell_nodes.size());
-              node_pairs[where[nd]].clear();
-            }
-            node_pairs[where[nd]].push_back((uint8_t)pp);
+        }
+        // tiles per cell: the smallest count that is at least 15 % cheaper than the previous
+        // choice (the per-step time of a tile is set by its fullest slot; a tile stages the
+        // node values of all its pairs, so splitting a cell is not free)
+        int T = 1;
+        size_t cost = allocate(0, NP);
+        for (int tt = 2; tt <= 8; tt *= 2) {
+          size_t c = 0;
+          for (int k = 0; k < tt; ++k) c += allocate(k * (NP / tt), NP / tt);
+          if ((double)c < 0.85 * (double)cost) {
+            cost = c;
+            T = tt;
           }
         }
-        SpreadTile t{cy * CR, cx * CC, (int)pl.schunks.size(), 0, 1, {0, 0, 0}};
-        const int nn = (int)cell_nodes.size();
-        for (int a0 = 0; a0 < nn;) {
-          // greedy chunk: as many nodes as fit kSpreadNodes and, padded, kSpreadEntries
-          std::fill(pcnt.begin(), pcnt.end(), 0);
-          int a1 = a0, total = 0;
-          while (a1 < nn && a1 - a0 < kSpreadNodes) {
-            int grow = 0;
-            for (uint8_t q : node_pairs[a1]) {
-              grow += padded(pcnt[q] + 1) - padded(pcnt[q]);
-              pcnt[q]++;
-            }
-            if (total + grow > kSpreadEntries) {
-              for (uint8_t q : node_pairs[a1]) pcnt[q]--;
-              break;
-            }
-            total += grow;
-            ++a1;
+        for (int tk = 0; tk < T; ++tk) {
+          const int p0 = tk * (NP / T), np = NP / T;
+          allocate(p0, np);
+          // slot layout: larger runs first, each at the first free aligned position
+          for (int i = 0; i < np; ++i) order_p[i] = p0 + i;
+          std::stable_sort(order_p.begin(), order_p.begin() + np,
+                           [&](int x, int y) { return split_of[x] > split_of[y]; });
+          std::fill(tile_slots.begin(), tile_slots.end(), (uint16_t)kSpreadIdleSlot);
+          int next = 0;
+          for (int i = 0; i < np; ++i) {
+            const int p = order_p[i], sp = split_of[p];
+            next = (next + sp - 1) / sp * sp;
+            slot_of[p] = next;
+            int lg = 0;
+            while ((1 << lg) < sp) ++lg;
+            for (int j = 0; j < sp; ++j) tile_slots[next + j] = (uint16_t)(p | (lg << 8));
+            next += sp;
           }
-          SpreadChunk ch{(int)pl.snodes.size(), 0, (int)pl.sseg.size(), 0};
-          for (int a = a0; a < a1; ++a) {
-            const int nd = cell_nodes[a];
-            pl.snodes.push_back(((nd / pl.H) << 16) | (nd % pl.H));
+          // nodes of this tile, in the order in which they first reach one of its pairs
+          cell_nodes.clear();
+          for (int p = p0; p < p0 + np; ++p)
+            for (const PairTmp& t : plist[p]) {
+              const int nd = (int)(t.key >> 1);
+              if (where[nd] < 0) {
+                where[nd] = (int)cell_nodes.size();
+                cell_nodes.push_back(nd);
+              }
+            }
+          SpreadTile t{cy * CR, cx * CC, (int)pl.schunks.size(), 0, 1, (int)pl.sslot.size(), 1, 0};
+          for (int p = p0; p < p0 + np; ++p) t.maxs = std::max(t.maxs, split_of[p]);
+          pl.sslot.insert(pl.sslot.end(), tile_slots.begin(), tile_slots.end());
+          const int nn = (int)cell_nodes.size();
+          // chunks: the tile's nodes dealt round-robin (node li to chunk li % nch), so that
+          // every chunk takes about the same share of each pair's entries and the slots of
+          // one step stay balanced; a pair's entries of a chunk are cut into its slots in
+          // order; nch is the smallest count whose chunks hold at most kSpreadNodes nodes and,
+          // padded per slot, kSpreadEntries entries
+          auto part = [](int n, int sp, int j) { return (int)((long long)n * j / sp); };
+          int nch = 0;
+          if (nn > 0) {
+            long long tot = 0;
+            for (int p = p0; p < p0 + np; ++p) tot += (long long)plist[p].size();
+            nch = std::max((nn + kSpreadNodes - 1) / kSpreadNodes, (int)((tot + kSpreadEntries - 1) / kSpreadEntries));
+            for (;; ++nch) {
+              chunk_cnt.assign((size_t)nch * NP, 0);
+              for (int p = p0; p < p0 + np; ++p)
+                for (const PairTmp& e : plist[p]) chunk_cnt[(size_t)(where[(int)(e.key >> 1)] % nch) * NP + p]++;
+              bool fits = true;
+              for (int c = 0; c < nch && fits; ++c) {
+                int used = 0;
+                for (int p = p0; p < p0 + np; ++p) {
+                  const int n = chunk_cnt[(size_t)c * NP + p];
+                  for (int j = 0; j < split_of[p]; ++j)
+                    used += padded(part(n, split_of[p], j + 1) - part(n, split_of[p], j));
+                }
+                fits = used <= kSpreadEntries;
+              }
+              if (fits) break;
+            }
           }
-          ch.n1 = (int)pl.snodes.size();
-          for (int pp = 0; pp < NP; ++pp) {
+          std::vector<PairTmp> mine;
+          for (int c = 0; c < nch; ++c) {
+            SpreadChunk ch{(int)pl.snodes.size(), 0, (int)pl.sseg.size(), 0};
+            for (int li = c; li < nn; li += nch) {
+              const int nd = cell_nodes[li];
+              pl.snodes.push_back(((nd / pl.H) << 16) | (nd % pl.H));
+            }
+            ch.n1 = (int)pl.snodes.size();
+            for (int sl = 0; sl < NP; ++sl) {
+              pl.sseg.push_back((int)pl.sent.size());
+              if (tile_slots[sl] == kSpreadIdleSlot) continue;
+              const int p = tile_slots[sl] & 63, sp = split_of[p], j = sl - slot_of[p];
+              mine.clear();
+              for (const PairTmp& e : plist[p])
+                if (where[(int)(e.key >> 1)] % nch == c) mine.push_back(e);
+              const int n = (int)mine.size();
+              for (int i = part(n, sp, j); i < part(n, sp, j + 1); ++i) {
+                const PairTmp& e = mine[i];
+                const int li = where[(int)(e.key >> 1)];
+                const bool cj = e.key & 1u;
+                pl.sent.push_back(SpreadLocal{(uint32_t)(li / nch) * kImgGroup * 8u, cj ? -e.wa : e.wa,
+                                              cj ? -e.wb : e.wb});
+              }
+              while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0u, 0.f, 0.f});
+            }
             pl.sseg.push_back((int)pl.sent.size());
-            for (const PairTmp& e : plist[pp]) {
-              const int li = where[(int)(e.key >> 1)];
-              if (li < a0 || li >= a1) continue;
-              const bool cj = e.key & 1u;
-              pl.sent.push_back(SpreadLocal{(uint32_t)(li - a0) * kImgGroup * 8u, cj ? -e.wa : e.wa,
-                                            cj ? -e.wb : e.wb});
-            }
-            while (pl.sent.size() % kSpreadBatch) pl.sent.push_back(SpreadLocal{0u, 0.f, 0.f});
+            pl.schunks.push_back(ch);
           }
-          pl.sseg.push_back((int)pl.sent.size());
-          pl.schunks.push_back(ch);
-          a0 = a1;
+          t.c1 = (int)pl.schunks.size();
+          t.nsub = nch <= 1 ? 1 : std::min(kSpreadSlice, std::max(kSpreadSlice / kSpreadHeavyGroups, nch));
+          pl.stiles.push_back(t);
+          for (int nd : cell_nodes) where[nd] = -1;
         }
-        t.c1 = (int)pl.schunks.size();
-        const int nch = t.c1 - t.c0;
-        t.nsub = nch <= 1 ? 1 : std::min(kSpreadSlice, std::max(kSpreadSlice / kSpreadHeavyGroups, nch));
-        pl.stiles.push_back(t);
-        for (int nd : cell_nodes) where[nd] = -1;
       }
     // workgroups of one slice: cells with the most chunks first, then in grid order
     std::vector<int> order(pl.stiles.size());
@@ -553,6 +633,7 @@ int upload_plan(Plan& pl) {
   FB_HIP_TRY(upload(&pl.d_schunks, pl.schunks.data(), pl.schunks.size()));
   FB_HIP_TRY(upload(&pl.d_snodes, pl.snodes.data(), pl.snodes.size()));
   FB_HIP_TRY(upload(&pl.d_sseg, pl.sseg.data(), pl.sseg.size()));
+  FB_HIP_TRY(upload(&pl.d_sslot, pl.sslot.data(), pl.sslot.size()));
   FB_HIP_TRY(upload(&pl.d_sent, pl.sent.data(), pl.sent.size()));
   FB_HIP_TRY(upload(&pl.d_items_fwd, pl.items_fwd.data(), pl.items_fwd.size()));
   FB_HIP_TRY(upload(&pl.d_items_adj, pl.items_adj.data(), pl.items_adj.size()));
@@ -569,7 +650,7 @@ void free_device(Plan& pl) {
   if (pl.has_device) pl.prof.release();
   void* ptrs[] = {pl.d_radial,    pl.d_radial_bf, pl.d_radial_pad, pl.d_xw,        pl.d_xi,        pl.d_wq,        pl.d_roots,     pl.d_coef_off,  pl.d_p,         pl.d_cov_off,   pl.d_tri_off,
                   pl.d_deconv,    pl.d_gnodes,    pl.d_gitems,    pl.d_tw,        pl.d_angtw,
-                  pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sent,
+                  pl.d_stiles,    pl.d_sblocks,   pl.d_schunks,   pl.d_snodes,    pl.d_sseg,      pl.d_sslot,     pl.d_sent,
                   pl.d_items_fwd, pl.d_items_adj, pl.d_items_cov, pl.d_items_spca,
                   pl.d_jmin,      pl.d_kring,     pl.d_gcols};
   for (void* p : ptrs)
@@ -593,6 +674,7 @@ void free_device(Plan& pl) {
   pl.d_schunks = nullptr;
   pl.d_snodes = nullptr;
   pl.d_sseg = nullptr;
+  pl.d_sslot = nullptr;
   pl.d_sent = nullptr;
   pl.d_items_fwd = pl.d_items_adj = pl.d_items_spca = nullptr;
   pl.d_items_cov = nullptr;

@@ -101,7 +101,10 @@ struct SpreadEntry {
 // split over nsub >= kSpreadSlice / kSpreadHeavyGroups workgroups per slice of
 // kSpreadSlice image groups (workgroup r of the cell takes groups r, r + nsub, ...), each
 // walking the chunks in order with the next image group's values prefetched and
-// per-group partial sums in registers.
+// per-group partial sums in registers.  The pairs of a cell whose entry counts differ
+// widely (near the origin, where the rings crowd) are shared out over up to 8 tiles, and in
+// a tile a pair may take 1, 2, 4 or 8 of the kSpreadPairs lane groups (slots), each summing
+// a contiguous part of the pair's entries; the slot table of a tile maps slot -> pair.
 constexpr int kSpreadRows = 16;
 constexpr int kSpreadCols = 8;
 constexpr int kSpreadPairs = kSpreadRows / 2 * kSpreadCols;
@@ -110,11 +113,16 @@ constexpr int kSpreadEntries = 4096;
 constexpr int kSpreadBatch = 4;
 constexpr int kSpreadSlice = 16;
 constexpr int kSpreadHeavyGroups = 4;
+// slot table entry: pair index in the cell (bits 0-5) | log2 of the pair's slot count << 8,
+// or kSpreadIdleSlot for a slot without a pair
+constexpr uint16_t kSpreadIdleSlot = 0x8000;
 struct SpreadTile {
   int m2, m1;    // cell origin (row m2 of the half plane, column m1)
   int c0, c1;    // chunk range
   int nsub;      // workgroups per slice of image groups
-  int pad[3];
+  int slots;     // first of its kSpreadPairs slot table entries
+  int maxs;      // most slots of one pair (1: slot = pair)
+  int pad;
 };
 struct SpreadBlock {
   int tile;      // index into the cell list
@@ -244,6 +252,7 @@ struct Plan {
   std::vector<SpreadChunk> schunks;
   std::vector<int> snodes;         // j << 16 | l
   std::vector<int> sseg;
+  std::vector<uint16_t> sslot;     // kSpreadPairs slot table entries per tile
   std::vector<SpreadLocal> sent;
   std::vector<GemmItem> items_fwd, items_adj, items_spca;
   std::vector<CovItem> items_cov;
@@ -282,6 +291,7 @@ struct Plan {
   SpreadChunk* d_schunks = nullptr;
   int* d_snodes = nullptr;
   int* d_sseg = nullptr;
+  uint16_t* d_sslot = nullptr;
   SpreadLocal* d_sent = nullptr;
   GemmItem* d_items_fwd = nullptr;
   GemmItem* d_items_adj = nullptr;

@@ -7,6 +7,7 @@
 // run; a wrong value makes it exit non-zero.
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <vector>
 
 #include "hostmath.h"
@@ -99,6 +100,54 @@ int main() {
         for (int v : s0) cov_ok = cov_ok && v == 1;
         check(cov_ok, "covariance items cover every tile once");
         std::printf("  covariance: %zu items\n", pl.items_cov.size());
+      }
+      // spread chunks: the kernel's unconditional staging loads rely on every chunk holding
+      // 1..kSpreadNodes nodes and at least one batch of entries, at most kSpreadEntries, each
+      // pointing at one of its chunk's nodes
+      {
+        bool sp_ok = !pl.stiles.empty();
+        long long nsent = 0;
+        for (const fb::SpreadTile& t : pl.stiles) {
+          sp_ok = sp_ok && t.c0 <= t.c1 && t.c1 <= (int)pl.schunks.size() && t.nsub >= 1 && t.nsub <= fb::kSpreadSlice;
+          sp_ok = sp_ok && (t.c1 - t.c0 <= 1 || t.nsub * fb::kSpreadHeavyGroups >= fb::kSpreadSlice);
+        }
+        for (size_t c = 0; sp_ok && c < pl.schunks.size(); ++c) {
+          const fb::SpreadChunk& ch = pl.schunks[c];
+          const int nl = ch.n1 - ch.n0;
+          sp_ok = nl >= 1 && nl <= fb::kSpreadNodes && ch.n1 <= (int)pl.snodes.size() &&
+                  ch.seg + fb::kSpreadPairs < (int)pl.sseg.size();
+          if (!sp_ok) break;
+          const int e0 = pl.sseg[ch.seg], e1 = pl.sseg[ch.seg + fb::kSpreadPairs];
+          sp_ok = e1 > e0 && e1 - e0 <= fb::kSpreadEntries && e1 <= (int)pl.sent.size();
+          for (int p = 0; sp_ok && p < fb::kSpreadPairs; ++p)
+            sp_ok = pl.sseg[ch.seg + p] <= pl.sseg[ch.seg + p + 1] && pl.sseg[ch.seg + p] % fb::kSpreadBatch == 0;
+          for (int e = e0; sp_ok && e < e1; ++e)
+            sp_ok = pl.sent[e].off % (fb::kImgGroup * 8u) == 0 && pl.sent[e].off / (fb::kImgGroup * 8u) < (unsigned)nl;
+          nsent += e1 - e0;
+        }
+        check(sp_ok, "spread chunks within their limits");
+        // slot tables: each pair of each cell has exactly one leading slot over the cell's
+        // tiles; a pair's slots are an aligned run of 1, 2, 4 or 8 inside one wavefront of 8
+        bool sl_ok = pl.sslot.size() == pl.stiles.size() * (size_t)fb::kSpreadPairs;
+        std::map<std::pair<int, int>, std::vector<int>> leads;
+        for (size_t ti = 0; sl_ok && ti < pl.stiles.size(); ++ti) {
+          const fb::SpreadTile& t = pl.stiles[ti];
+          auto& cov = leads[{t.m2, t.m1}];
+          cov.resize(fb::kSpreadPairs, 0);
+          sl_ok = t.slots == (int)ti * fb::kSpreadPairs && t.maxs >= 1 && t.maxs <= 8;
+          for (int sl = 0; sl_ok && sl < fb::kSpreadPairs; ++sl) {
+            const unsigned v = pl.sslot[t.slots + sl];
+            if (v & fb::kSpreadIdleSlot) continue;
+            const int pr = v & 63, sp = 1 << ((v >> 8) & 3), lead = sl & ~(sp - 1);
+            sl_ok = sp <= t.maxs && lead / 8 == (lead + sp - 1) / 8;
+            for (int j = lead; sl_ok && j < lead + sp; ++j) sl_ok = pl.sslot[t.slots + j] == v;
+            if (sl == lead) cov[pr]++;
+          }
+        }
+        for (auto& kv : leads)
+          for (int v : kv.second) sl_ok = sl_ok && v == 1;
+        check(sl_ok, "spread slot tables cover every pair once");
+        std::printf("  spread: %zu cells, %zu chunks, %lld entries\n", pl.stiles.size(), pl.schunks.size(), nsent);
       }
       std::printf("  grid points stored by the column pass: %.3f of %d x %d\n", (double)stored / ((double)pl.M2 * pl.N),
                   pl.M2, pl.N);
