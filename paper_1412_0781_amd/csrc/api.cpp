@@ -175,6 +175,7 @@ int fb_adjoint_filtered(fb_plan_t plan, const float* coeffs, int64_t n, float* i
   float2 *bufA = nullptr, *bufB = nullptr;
   int64_t nb = split_workspace(lay, ws, ws_bytes, n, &bufA, &bufB);
   if (nb < 1) return FB_ERR_WORKSPACE;
+  nb = std::min(nb, fb::spread_max_images(pl));
   hipStream_t st = (hipStream_t)stream;
   const size_t img_stride = (size_t)pl.L * pl.L;
   const size_t coef_stride = 2 * (size_t)pl.p_half;

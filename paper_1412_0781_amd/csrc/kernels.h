@@ -28,6 +28,8 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
 hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
                                  const float* ring_filter, hipStream_t st);
 hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, int nimg, hipStream_t st);
+// largest pass the adjoint spread takes (its node value offsets are 32-bit)
+int64_t spread_max_images(const Plan& pl);
 hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
                                 float* images, hipStream_t st);
 

@@ -790,7 +790,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   static_assert(NT == NP * IP, "one lane per (point pair, image pair)");
   static_assert(KQ * NT == kSpreadNodes * IP && KE * NT == EV, "staging slots per lane");
   static_assert(sizeof(SpreadLocal) == 12 && kSpreadBatch == 4, "a batch is three 16-byte vectors");
-  static_assert(kSpreadHeavyGroups == 4, "four partial-sum sets");
+  static_assert(kSpreadHeavyGroups == 2, "two partial-sum sets");
   // staging in native vector types, so that the register copies below stay in registers
   __shared__ __attribute__((aligned(16))) fb_f4v s_q[kSpreadNodes * IP];
   __shared__ __attribute__((aligned(16))) fb_u4v s_e[EV];
@@ -832,7 +832,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     for (int g = gb; g < ge; g += t.nsub) put(g, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f));
     return;
   }
-  // image groups of this workgroup; a cell of several chunks has nsub >= 4, so ng <= 4
+  // image groups of this workgroup; a tile of several chunks has nsub >= 8, so ng <= 2
   const int ng = gb < ge ? (ge - gb + t.nsub - 1) / t.nsub : 0;
   const int nsteps = ng * nch;
   const fb_f4v* Q4 = (const fb_f4v*)Q;
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
   const size_t gstride = (size_t)H * IP;  // float4s between image groups of one node
   // next step's chunk data, held in registers
   int nl_n = 0, ne_n = 0, e0_n = 0, e1_n = 0;
-  size_t qoff[KQ];
+  unsigned qoff[KQ];  // node value offsets inside one image group's view (fit 32 bits: spread_max_images)
   fb_u4v er[KE];
   fb_f4v qr[KQ];
   auto load_meta_rec = [&](const SpreadChunk ch) {
@@ -858,12 +858,13 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     for (int k = 0; k < KQ; ++k) {
       const int i = min(tid + k * NT, nl_n * IP - 1);
       const int jl = snodes[ch.n0 + i / IP];
-      qoff[k] = ((size_t)(jl >> 16) * ngrp * H + (jl & 0xffff)) * IP + (i & (IP - 1));
+      qoff[k] = ((unsigned)(jl >> 16) * ngrp * H + (jl & 0xffff)) * IP + (i & (IP - 1));
     }
   };
   auto load_q_into = [&](fb_f4v (&dst)[KQ], int g) {
+    const fb_f4v* Qg = Q4 + (size_t)g * gstride;
 #pragma unroll
-    for (int k = 0; k < KQ; ++k) dst[k] = Q4[qoff[k] + (size_t)g * gstride];
+    for (int k = 0; k < KQ; ++k) dst[k] = Qg[qoff[k]];
   };
   auto load_q = [&](int g) { load_q_into(qr, g); };
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
@@ -933,7 +934,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
     load_q(gb);
   }
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 PA0 = z4, PB0 = z4, PA1 = z4, PB1 = z4, PA2 = z4, PB2 = z4, PA3 = z4, PB3 = z4;
+  float4 PA0 = z4, PB0 = z4, PA1 = z4, PB1 = z4;
   for (int s = 0; s < nsteps; ++s) {
     const int ci = s / ng, gi = s - ci * ng;
     const int g = gb + gi * t.nsub;
@@ -968,9 +969,7 @@ __global__ __launch_bounds__(NT, 4) void k_adj_spread(const float2* __restrict__
         PB = rb;
       };
       if (gi == 0) upd(PA0, PB0);
-      else if (gi == 1) upd(PA1, PB1);
-      else if (gi == 2) upd(PA2, PB2);
-      else upd(PA3, PB3);
+      else upd(PA1, PB1);
     }
     if (ci == nch - 1) {
       gather_slots(ra, rb);
@@ -1399,6 +1398,13 @@ hipError_t launch_adjoint_angular(const Plan& pl, const float2* D, float2* Q, in
   return hipGetLastError();
 }
 
+int64_t spread_max_images(const Plan& pl) {
+  // the spread addresses one pass's polar values (n_xi x groups x H x 8 16-byte vectors)
+  // with 32-bit offsets
+  const int64_t per_group = (int64_t)pl.n_xi * pl.H * (kImgGroup / 2);
+  return (int64_t)(0xffffffffull / (uint64_t)per_group) * kImgGroup;
+}
+
 hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float2* bufA, float2* bufB,
                                 float* images, hipStream_t st) {
   const int N = pl.N, L = pl.L, Nh = N / 2 + 1;
@@ -1406,7 +1412,7 @@ hipError_t launch_adjoint_nufft(const Plan& pl, const float2* Q, int nimg, float
   constexpr int NT = kSpreadPairs * kImgGroup / 2;
   const int nsl = (ngrp + kSpreadSlice - 1) / kSpreadSlice;
   const size_t nblk = pl.sblocks.size() * (size_t)nsl;
-  if (nblk > 0x7fffffffu) return hipErrorInvalidValue;
+  if (nblk > 0x7fffffffu || nimg > spread_max_images(pl)) return hipErrorInvalidValue;
   pl.prof.begin(ST_ADJ_SPREAD, st);
   hipLaunchKernelGGL((k_adj_spread<NT>), dim3((unsigned)nblk), dim3(NT), 0, st, Q, bufB, pl.d_stiles,
                      pl.d_sblocks, pl.d_schunks, pl.d_snodes, pl.d_sseg, pl.d_sslot, pl.d_sent, N, Nh, pl.H, ngrp,

@@ -112,7 +112,7 @@ constexpr int kSpreadNodes = 256;
 constexpr int kSpreadEntries = 4096;
 constexpr int kSpreadBatch = 4;
 constexpr int kSpreadSlice = 16;
-constexpr int kSpreadHeavyGroups = 4;
+constexpr int kSpreadHeavyGroups = 2;
 // slot table entry: pair index in the cell (bits 0-5) | log2 of the pair's slot count << 8,
 // or kSpreadIdleSlot for a slot without a pair
 constexpr uint16_t kSpreadIdleSlot = 0x8000;
