@@ -42,6 +42,11 @@ STAGES = {
     "fwd_angular": ("k_fwd_angular",),
     "radial_fwd": ("k_radial_fwd",),
     "covariance": ("k_covariance", "k_cov_reduce"),
+    "radial_adj": ("k_radial_adj",),
+    "adj_angular": ("k_adj_angular",),
+    "adj_spread": ("k_adj_spread",),
+    "adj_cols": ("k_adj_cols",),
+    "adj_rows": ("k_adj_rows",),
 }
 SIMDS = 256 * 4  # MI355X: 256 compute units of 4 SIMDs
 XCDS = 8         # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs (each counts the same busy cycles)
@@ -172,8 +177,10 @@ def algorithmic_bytes_per_image(L: int, grid_n: int, w: int, n_xi: int, H: int, 
     c8 = 8
     img, g1, g = 4 * L * L, c8 * M2 * L, c8 * M2 * grid_n
     P, fh, co = c8 * n_xi * H, c8 * (k_max + 1) * n_xi, c8 * p_half
+    y, y1 = c8 * (grid_n // 2 + 1) * grid_n, c8 * (grid_n // 2 + 1) * L  # adjoint half-plane grid, column pass
     return {"fwd_rows": img + g1, "fwd_cols": g1 + g, "fwd_gather": g + P, "fwd_angular": P + fh,
-            "radial_fwd": fh + co, "covariance": co}
+            "radial_fwd": fh + co, "covariance": co, "radial_adj": co + fh, "adj_angular": fh + P,
+            "adj_spread": P + y, "adj_cols": y + y1, "adj_rows": y1 + img}
 
 
 def cmd_hbm(a):
@@ -185,7 +192,10 @@ def cmd_hbm(a):
     f = _counter_table(a.fetch)
     w = _counter_table(a.write)
     digest = source_digest()
+    wanted = set(a.stages.split(",")) if a.stages else set(STAGES)
     for stage, prefixes in STAGES.items():
+        if stage not in wanted:
+            continue
         names = sorted(n for n in set(f) | set(w) if any(n.startswith(p) for p in prefixes))
         if not names:
             continue
@@ -264,6 +274,7 @@ def main(argv=None):
     p.add_argument("--cov-images", type=int, required=True)
     p.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
     p.add_argument("--form", default="BF16x3")
+    p.add_argument("--stages", default="", help="comma-separated stages to write (default: every stage found)")
     p.add_argument("--command-fetch", required=True)
     p.add_argument("--command-write", required=True)
     p = sub.add_parser("counters")
