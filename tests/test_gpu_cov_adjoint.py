@@ -242,6 +242,30 @@ def test_adjoint_many_images():
     assert np.max(np.abs(part - full[280:])) <= 1e-6 * np.max(np.abs(full[280:]))
 
 
+def test_adjoint_l128_split_cells_match_oracle_and_repeat():
+    """L = 128: the spread shares the crowded cells near the origin over several tiles and
+    gives their heaviest pairs up to 8 lane groups whose sums meet in a butterfly, and cuts
+    many cells into several chunks.  Sampled images of a 300-image batch against the
+    oracle; the same batch again, and in other pass sizes, bit for bit (fixed summation
+    order, no atomics)."""
+    L, c, R = 128, 0.5, 64
+    print(f"[adjoint] L={L} n=300 split cells", flush=True)
+    po = oracle.plan(L, c, R)
+    k, q = po.kq[:, 0], po.kq[:, 1]
+    b = synth.random_coefficients(12, np.arange(300), k, q)
+    plan = Plan(L, c, R)
+    bt = torch.tensor(np.stack([b.real, b.imag], axis=-1).astype(np.float32), device="cuda")
+    full = plan.adjoint(bt).clone()
+    again = plan.adjoint(bt)
+    small = plan.adjoint(bt, batch=48)
+    torch.cuda.synchronize()
+    assert torch.equal(full, again)
+    assert torch.equal(full, small)
+    pick = [5, 211]
+    ref = oracle.adjoint(b[pick], po)
+    assert rel_l2(full.cpu().numpy()[pick], ref) <= TOL
+
+
 @pytest.mark.parametrize("L,c,R", [(32, 0.5, 16), (128, 0.5, 64), (31, 0.5, 15.5), (256, 0.5, 128)])
 def test_dot_product_identity_gpu(L, c, R):
     """<T* I, b> = <I, T b> with the folded inner product, to 1e-6 in FP32 relative to the
