@@ -13,6 +13,8 @@
 // v_mfma_f32_32x32x2f32 in 64 x 64 tiles (FP32 products and sums; U rounded to FP32).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace fb {
@@ -41,9 +43,14 @@ __global__ void k_spca_select(const double* __restrict__ evals, const int* __res
 
 // MODE 0 (project): out[i][off + l] = sum_q (a[i][off + q] - m_q [k = 0, re]) U[q][l]
 // MODE 1 (rebuild): out[i][off + q] = sum_l U[q][l] w[off + l] c[i][off + l] + m_q [k = 0, re]
-// grid: (image tiles of 32, work items (k, 64-wide output tile)); rows of a tile are
-// (image, re/im) pairs.
-template <int MODE>
+// grid: (runs of kSpcaBlocks image blocks of 32, work items (k, 64-wide output tile)); rows
+// of a tile are (image, re/im) pairs.  PANEL: the item's whole B operand (p_k rows of its 64
+// columns, rounded to FP32 once) sits in LDS for all the run's image blocks; otherwise it is
+// read per chunk of 16 rows (blocks above the panel's capacity).  An image's coefficients of
+// block k are one contiguous run, read as (re, im) pairs along q.
+constexpr int kSpcaBlocks = 8;
+constexpr int kSpcaTK = 16, kSpcaLd = 64 + 4;
+template <int MODE, bool PANEL>
 __global__ __launch_bounds__(256) void k_spca_apply(const float* __restrict__ in, float* __restrict__ out,
                                                     const double* __restrict__ evecs,
                                                     const double* __restrict__ mean,
@@ -52,58 +59,81 @@ __global__ __launch_bounds__(256) void k_spca_apply(const float* __restrict__ in
                                                     const int* __restrict__ coef_off, const int* __restrict__ p,
                                                     const long long* __restrict__ cov_off, long long n,
                                                     long long p_half) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ float As[TK][TM + 4];
-  __shared__ float Bs[TK][TN + 4];
+  constexpr int TM = 64, TK = kSpcaTK, LD = kSpcaLd;
+  extern __shared__ float spca_lds[];
+  float(*As)[LD] = (float(*)[LD])spca_lds;              // TK rows
+  float(*Bs)[LD] = (float(*)[LD])(spca_lds + TK * LD);  // p_k rounded to TK rows (PANEL) or TK rows
   const GemmItem it = items[blockIdx.y];
   const int k = it.k, n0 = it.t0, pk = p[k], off = coef_off[k];
-  const long long i0 = (long long)blockIdx.x * (TM / 2);
   const double* U = evecs + cov_off[k];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  f32x16_s acc = {};
-  for (int k0 = 0; k0 < pk; k0 += TK) {
-    for (int e = tid; e < TK * TM; e += 256) {
-      const int kk = e / TM, m = e - kk * TM;
-      const long long img = i0 + (m >> 1);
-      const int ri = m & 1, q = k0 + kk;
-      float v = 0.f;
-      if (img < n && q < pk) {
-        v = in[(size_t)img * 2 * p_half + 2 * (size_t)(off + q) + ri];
-        if (MODE == 0 && k == 0 && ri == 0) v -= (float)mean[q];
-      }
-      As[kk][m] = v;
-    }
-    for (int e = tid; e < TK * TN; e += 256) {
-      const int kk = e / TN, nn = e - kk * TN;
-      const int r = k0 + kk, c = n0 + nn;
+  // B rows r0 .. r0 + nr - 1 of this item's 64 columns into Bs[d0 + ...]
+  auto load_b = [&](int r0, int nr, int d0) {
+    for (int e = tid; e < nr * 64; e += 256) {
+      const int kk = e >> 6, nn = e & 63;
+      const int r = r0 + kk, c = n0 + nn;
       float v = 0.f;
       if (r < pk && c < pk) {
         if (MODE == 0)
-          v = (float)U[(size_t)r * pk + c];                            // U[q = r][l = c]
+          v = (float)U[(size_t)r * pk + c];                                     // U[q = r][l = c]
         else
           v = (float)(U[(size_t)c * pk + r] * (weights ? weights[off + r] : 1.0));  // U[q = c][l = r] w_l
       }
-      Bs[kk][nn] = v;
+      Bs[d0 + kk][nn] = v;
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 2) {
-      float a = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
-      float b = Bs[kk + (lane >> 5)][wn * 32 + (lane & 31)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    }
+  };
+  const int pk_pad = (pk + TK - 1) / TK * TK;
+  if (PANEL) {
+    load_b(0, pk_pad, 0);
     __syncthreads();
   }
+  // the A chunk: thread t loads image t / 8 of the block, q = k0 + 2 (t % 8) + {0, 1}
+  const int ai = tid >> 3, aq = 2 * (tid & 7);
+  for (int blk = 0; blk < kSpcaBlocks; ++blk) {
+    const long long i0 = ((long long)blockIdx.x * kSpcaBlocks + blk) * (TM / 2);
+    if (i0 >= n) break;
+    const long long img = i0 + ai;
+    const float2* arow = (const float2*)(in + (size_t)min(img, n - 1) * 2 * p_half) + off;
+    // the next chunk's pair of values is loaded while the current one is multiplied; the
+    // loads are unconditional (clamped to the block), values outside it are replaced by 0
+    float2 pa[2];
+    auto fetch = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int m = wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-    const int c = n0 + wn * 32 + (lane & 31);
-    const long long img = i0 + (m >> 1);
-    const int ri = m & 1;
-    if (img < n && c < pk) {
-      float v = acc[i];
-      if (MODE == 1 && k == 0 && ri == 0) v += (float)mean[c];
-      out[(size_t)img * 2 * p_half + 2 * (size_t)(off + c) + ri] = v;
+      for (int h = 0; h < 2; ++h) pa[h] = arow[min(k0 + aq + h, pk - 1)];
+    };
+    fetch(0);
+    f32x16_s acc = {};
+    for (int k0 = 0; k0 < pk; k0 += TK) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = k0 + aq + h;
+        float2 v = (img < n && q < pk) ? pa[h] : make_float2(0.f, 0.f);
+        if (MODE == 0 && k == 0 && q < pk) v.x -= (float)mean[q];
+        *(float2*)&As[aq + h][2 * ai] = v;
+      }
+      if (!PANEL) load_b(k0, TK, 0);
+      __syncthreads();
+      if (k0 + TK < pk) fetch(k0 + TK);
+      const int b0 = PANEL ? k0 : 0;
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 2) {
+        const float a = As[kk + (lane >> 5)][wm * 32 + (lane & 31)];
+        const float b = Bs[b0 + kk + (lane >> 5)][wn * 32 + (lane & 31)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int m = wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+      const int c = n0 + wn * 32 + (lane & 31);
+      const long long oi = i0 + (m >> 1);
+      const int ri = m & 1;
+      if (oi < n && c < pk) {
+        float v = acc[i];
+        if (MODE == 1 && k == 0 && ri == 0) v += (float)mean[c];
+        out[(size_t)oi * 2 * p_half + 2 * (size_t)(off + c) + ri] = v;
+      }
     }
   }
 }
@@ -221,14 +251,25 @@ hipError_t launch_spca_select(const Plan& pl, const double* evals, long long cou
 
 hipError_t launch_spca_apply(const Plan& pl, int mode, const float* in, long long n, const double* evecs,
                              const double* mean, const double* weights, float* out, hipStream_t st) {
-  dim3 g((unsigned)((n + 31) / 32), (unsigned)pl.items_spca.size());
+  const long long runs = (n + 32LL * kSpcaBlocks - 1) / (32LL * kSpcaBlocks);
+  if (runs > 0x7fffffffLL) return hipErrorInvalidValue;
+  dim3 g((unsigned)runs, (unsigned)pl.items_spca.size());
+  int pmax = 0;
+  for (int v : pl.p) pmax = std::max(pmax, v);
+  const int rows = (pmax + kSpcaTK - 1) / kSpcaTK * kSpcaTK;
+  // B panel resident while the kernel's LDS stays within 64 KB (p_k <= 224), otherwise
+  // streamed by chunks
+  const bool panel = (kSpcaTK + rows) * kSpcaLd * sizeof(float) <= 64u * 1024u;
+  const size_t lds = (size_t)(kSpcaTK + (panel ? rows : kSpcaTK)) * kSpcaLd * sizeof(float);
   pl.prof.begin(ST_SPCA, st);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, g, dim3(256), lds, st, in, out, evecs, mean, weights, pl.d_items_spca, pl.d_coef_off,
+                       pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+  };
   if (mode == 0)
-    hipLaunchKernelGGL(k_spca_apply<0>, g, dim3(256), 0, st, in, out, evecs, mean, weights, pl.d_items_spca,
-                       pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+    panel ? go(k_spca_apply<0, true>) : go(k_spca_apply<0, false>);
   else
-    hipLaunchKernelGGL(k_spca_apply<1>, g, dim3(256), 0, st, in, out, evecs, mean, weights, pl.d_items_spca,
-                       pl.d_coef_off, pl.d_p, pl.d_cov_off, n, (long long)pl.p_half);
+    panel ? go(k_spca_apply<1, true>) : go(k_spca_apply<1, false>);
   pl.prof.end(st);
   return hipGetLastError();
 }

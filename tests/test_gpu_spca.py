@@ -106,3 +106,31 @@ def test_denoising_reduces_error():
     e_den = float(((den - clean) ** 2).mean())
     print(f"  mse noisy {e_noisy:.4g}  denoised {e_den:.4g}", flush=True)
     assert e_den < 0.5 * e_noisy
+
+
+def test_coeffs_and_reconstruct_large_blocks():
+    """L = 456: blocks of up to 227 coefficients, more than the products keep resident in LDS,
+    so their U operand is read by chunks; 300 images (a ragged last run of image blocks).
+    Random coefficients, mean and orthogonal U (QR of Gaussian blocks) and weights in [0, 1],
+    against the oracle's projection and rebuild."""
+    torch.cuda.set_device(0)
+    L, c, R, n = 456, 0.5, 228.0, 300
+    print(f"[spca] L={L} large blocks", flush=True)
+    po = oracle.plan(L, c, R)
+    assert max(po.p) > 224
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((n, po.p_half)) + 1j * rng.standard_normal((n, po.p_half))
+    a[:, :po.p[0]] = a[:, :po.p[0]].real
+    a32 = np.stack([a.real, a.imag], axis=-1).astype(np.float32)
+    a = a32[..., 0].astype(np.float64) + 1j * a32[..., 1].astype(np.float64)
+    mean0 = rng.standard_normal(po.p[0])
+    U = [np.linalg.qr(rng.standard_normal((pk, pk)))[0] for pk in po.p]
+    w = [rng.uniform(0.0, 1.0, pk) for pk in po.p]
+    plan = Plan(L, c, R)
+    dU = torch.tensor(np.concatenate([u.ravel() for u in U]), device="cuda")
+    dm = torch.tensor(mean0, device="cuda")
+    cg = plan.spca_coeffs(torch.tensor(a32, device="cuda"), dU, dm)
+    assert rel_l2(_cplx(cg), spca.coefficients(a, mean0, U, po)) <= 1e-6
+    c32 = _cplx(cg)
+    back = plan.spca_reconstruct(cg, dU, dm, torch.tensor(np.concatenate(w), device="cuda"))
+    assert rel_l2(_cplx(back), spca.reconstruct(c32, mean0, U, w, po)) <= 1e-6
