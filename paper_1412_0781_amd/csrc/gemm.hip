@@ -327,48 +327,83 @@ __global__ __launch_bounds__(256) void k_radial_fwd_b3(const unsigned short* __r
 
 // ---------------------------------------------------------------------------
 // transpose of the radial step: D^(k)[j][col] = w_k sum_q B^(k)[q][j] X^(k)[q][col]
-// grid: (column tiles, work items (k, j-tile)); FP32
+// grid: (runs of kAdjBlocks column tiles of 32 images, work items (k, j-tile)); FP32.
+// PANEL: the item's table panel (all p_k rows of its 64 rings) sits in LDS for the whole
+// run; otherwise it is read per chunk of 16 rows (blocks above the panel's capacity).  An
+// image's block-k coefficients are one contiguous run, read as (re, im) pairs along q with
+// the next chunk in flight.
 // ---------------------------------------------------------------------------
+constexpr int kAdjBlocks = 8;
+template <bool PANEL>
 __global__ __launch_bounds__(256) void k_radial_adj_f32(const float* __restrict__ radial,
                                                         const float* __restrict__ coeffs, float* __restrict__ D,
                                                         const GemmItem* __restrict__ items,
                                                         const int* __restrict__ coef_off, const int* __restrict__ p,
                                                         int n_xi, int nk, int ncol, long long p_half,
                                                         int weight_mode, const float* __restrict__ ring_filter) {
-  __shared__ float As[BK][BM + 4];
-  __shared__ float Bs[BK][BN + 4];
+  extern __shared__ float adj_lds[];
+  float(*Bs)[BN + 4] = (float(*)[BN + 4])adj_lds;                   // BK rows: coefficients
+  float(*As)[BM + 4] = (float(*)[BM + 4])(adj_lds + BK * (BN + 4));  // table rows
   const GemmItem it = items[blockIdx.y];
   const int k = it.k, j0 = it.t0, pk = p[k], off = coef_off[k];
-  const int n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  f32x16 acc = {};
-  for (int k0 = 0; k0 < pk; k0 += BK) {
-    for (int i = tid; i < BM * BK; i += 256) {
-      int kk = i / BM, m = i - kk * BM;
-      int q = k0 + kk, j = j0 + m;
-      As[kk][m] = (q < pk && j < n_xi) ? radial[(size_t)(off + q) * n_xi + j] : 0.f;
+  auto load_a = [&](int r0, int nr) {  // table rows r0 .. r0 + nr - 1 into As[0 ..] (PANEL: As[r0 ..])
+    for (int i = tid; i < BM * nr; i += 256) {
+      const int kk = i / BM, m = i - kk * BM;
+      const int q = r0 + kk, j = j0 + m;
+      As[(PANEL ? r0 : 0) + kk][m] = (q < pk && j < n_xi) ? radial[(size_t)(off + q) * n_xi + j] : 0.f;
     }
-    for (int i = tid; i < BK * BN; i += 256) {
-      int il = i / (2 * BK), rem = i - il * 2 * BK, kk = rem >> 1, ri = rem & 1;
-      int n = 2 * il + ri, q = k0 + kk, col = n0 + n;
-      bool ok = q < pk && col < ncol && !(k == 0 && ri);
-      Bs[kk][n] = ok ? coeffs[(size_t)(col >> 1) * 2 * p_half + 2 * (size_t)(off + q) + ri] : 0.f;
-    }
-    __syncthreads();
-    mma_f32(As, Bs, acc, wm, wn, lane);
+  };
+  if (PANEL) {
+    load_a(0, (pk + BK - 1) / BK * BK);
     __syncthreads();
   }
-  // D grouped like the forward spectrum: [image group][ring j][k][16 images] complex, so
-  // that a (ring, group) unit of the angular step reads one contiguous run
   const float wk = (k == 0 || weight_mode == 1) ? 1.f : 2.f;
+  const int nimg = ncol / 2;
+  const int bi = tid >> 3, bq = 2 * (tid & 7);  // coefficient loads: image bi of the block, q = k0 + bq + {0, 1}
+  for (int blk = 0; blk < kAdjBlocks; ++blk) {
+    const int n0 = (blockIdx.x * kAdjBlocks + blk) * BN;
+    if (n0 >= ncol) break;
+    const int img = n0 / 2 + bi;
+    const float2* brow = (const float2*)(coeffs + (size_t)min(img, nimg - 1) * 2 * p_half) + off;
+    float2 pb[2];
+    auto fetch = [&](int k0) {  // unconditional (clamped to the block): stays in flight
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    int j = j0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
-    if (j < n_xi && c < ncol) {
-      const int img = c >> 1;
-      const float h = ring_filter ? ring_filter[j] : 1.f;  // radial filter H(xi_j), if any
-      D[((((size_t)(img / kImgGroup) * n_xi + j) * nk + k) * kImgGroup + (img & (kImgGroup - 1))) * 2 + (c & 1)] =
-          h * (wk * acc[i]);
+      for (int h = 0; h < 2; ++h) pb[h] = brow[min(k0 + bq + h, pk - 1)];
+    };
+    fetch(0);
+    f32x16 acc = {};
+    for (int k0 = 0; k0 < pk; k0 += BK) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = k0 + bq + h;
+        float2 v = (img < nimg && q < pk) ? pb[h] : make_float2(0.f, 0.f);
+        if (k == 0) v.y = 0.f;  // the k = 0 coefficients are real
+        *(float2*)&Bs[bq + h][2 * bi] = v;
+      }
+      if (!PANEL) load_a(k0, BK);
+      __syncthreads();
+      if (k0 + BK < pk) fetch(k0 + BK);
+      const int a0 = PANEL ? k0 : 0;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float a = As[a0 + kk + (lane >> 5)][wm * 32 + (lane & 31)];
+        const float b = Bs[kk + (lane >> 5)][wn * 32 + (lane & 31)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // D grouped like the forward spectrum: [image group][ring j][k][16 images] complex, so
+    // that a (ring, group) unit of the angular step reads one contiguous run
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int j = j0 + wm * 32 + acc_row(i, lane), c = n0 + wn * 32 + (lane & 31);
+      if (j < n_xi && c < ncol) {
+        const int im = c >> 1;
+        const float h = ring_filter ? ring_filter[j] : 1.f;  // radial filter H(xi_j), if any
+        D[((((size_t)(im / kImgGroup) * n_xi + j) * nk + k) * kImgGroup + (im & (kImgGroup - 1))) * 2 + (c & 1)] =
+            h * (wk * acc[i]);
+      }
     }
   }
 }
@@ -698,11 +733,23 @@ hipError_t launch_radial_forward(const Plan& pl, const float2* Fh, float* coeffs
 hipError_t launch_radial_adjoint(const Plan& pl, const float* coeffs, float2* D, int nimg, int weight_mode,
                                  const float* ring_filter, hipStream_t st) {
   const int ncol = 2 * nimg;
-  dim3 g((unsigned)((ncol + BN - 1) / BN), (unsigned)pl.items_adj.size());
+  const int tiles = (ncol + BN - 1) / BN;
+  dim3 g((unsigned)((tiles + kAdjBlocks - 1) / kAdjBlocks), (unsigned)pl.items_adj.size());
+  int pmax = 0;
+  for (int v : pl.p) pmax = std::max(pmax, v);
+  const int rows = (pmax + BK - 1) / BK * BK;
+  // table panel resident while the kernel's LDS stays within 64 KB (p_k <= 224)
+  const bool panel = (size_t)(BK * (BN + 4) + rows * (BM + 4)) * sizeof(float) <= 64u * 1024u;
+  const size_t lds = (size_t)(BK * (BN + 4) + (panel ? rows : BK) * (BM + 4)) * sizeof(float);
   pl.prof.begin(ST_RADIAL_ADJ, st);
-  hipLaunchKernelGGL(k_radial_adj_f32, g, dim3(256), 0, st, pl.d_radial, coeffs, (float*)D, pl.d_items_adj,
-                     pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half, weight_mode,
-                     ring_filter);
+  if (panel)
+    hipLaunchKernelGGL(k_radial_adj_f32<true>, g, dim3(256), lds, st, pl.d_radial, coeffs, (float*)D,
+                       pl.d_items_adj, pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half,
+                       weight_mode, ring_filter);
+  else
+    hipLaunchKernelGGL(k_radial_adj_f32<false>, g, dim3(256), lds, st, pl.d_radial, coeffs, (float*)D,
+                       pl.d_items_adj, pl.d_coef_off, pl.d_p, pl.n_xi, pl.k_max + 1, ncol, (long long)pl.p_half,
+                       weight_mode, ring_filter);
   pl.prof.end(st);
   return hipGetLastError();
 }

@@ -294,6 +294,33 @@ def test_dot_product_identity_gpu(L, c, R):
     assert np.max(rel) <= 1e-6
 
 
+def test_dot_product_identity_large_blocks():
+    """L = 456: blocks of up to 227 coefficients, more than the adjoint's radial step keeps
+    resident in LDS, so its table is read by chunks; <T* I, b> = <I, T b> with b = T* I plus
+    10 % noise (so that neither side cancels), to 1e-6."""
+    L, c, R = 456, 0.5, 228.0
+    print(f"[adjoint] dot test L={L}", flush=True)
+    plan = Plan(L, c, R)
+    assert max(int(x) for x in plan.p) > 224
+    rng = np.random.default_rng(3)
+    I_np = rng.standard_normal((3, L, L)).astype(np.float32)
+    I = torch.tensor(I_np, device="cuda")
+    a = plan.expand(I)
+    noise = torch.tensor(rng.standard_normal(tuple(a.shape)).astype(np.float32), device="cuda")
+    scale = a.norm(dim=(1, 2), keepdim=True) / np.sqrt(plan.p_half)
+    bt = a + 0.1 * scale * noise
+    bt[:, :int(plan.p[0]), 1] = 0.0
+    Tb = plan.adjoint(bt).cpu().numpy().astype(np.float64)
+    ac, bc = as_complex(a), as_complex(bt)
+    p0 = int(plan.p[0])
+    lhs = (np.sum(ac[:, :p0].real * bc[:, :p0].real, axis=1)
+           + 2.0 * np.sum((np.conj(ac[:, p0:]) * bc[:, p0:]).real, axis=1))
+    rhs = np.sum(I_np.astype(np.float64) * Tb, axis=(1, 2))
+    rel = np.abs(lhs - rhs) / np.abs(lhs)
+    print(f"  dot test {np.max(rel):.3e}", flush=True)
+    assert np.max(rel) <= 1e-6
+
+
 def test_autograd_expand_dot_identity():
     """FBExpand backward is the plain transpose of the expansion (weight 1 for every k)."""
     L = 32
