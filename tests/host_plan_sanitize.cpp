@@ -5,6 +5,7 @@
 // plans of several shapes and rejects the invalid ones, and checks the FP64 host numerics
 // against values they must reproduce.  Any memory error or undefined behaviour aborts the
 // run; a wrong value makes it exit non-zero.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -147,6 +148,22 @@ int main() {
         for (auto& kv : leads)
           for (int v : kv.second) sl_ok = sl_ok && v == 1;
         check(sl_ok, "spread slot tables cover every pair once");
+        // balance: a step lasts as long as its fullest slot, so the mean slot load over the
+        // fullest one, summed over chunks, is the share of lane time that does work
+        double mean_sum = 0.0, max_sum = 0.0;
+        for (const fb::SpreadChunk& ch : pl.schunks) {
+          int mx = 0, tot = 0;
+          for (int sl = 0; sl < fb::kSpreadPairs; ++sl) {
+            const int c = pl.sseg[ch.seg + sl + 1] - pl.sseg[ch.seg + sl];
+            mx = std::max(mx, c);
+            tot += c;
+          }
+          mean_sum += (double)tot / fb::kSpreadPairs;
+          max_sum += mx;
+        }
+        const double balance = max_sum > 0 ? mean_sum / max_sum : 1.0;
+        std::printf("  spread slot balance %.3f\n", balance);
+        if (s.L >= 128 && s.R == s.L / 2.0) check(balance >= 0.7, "spread slots balanced");
         std::printf("  spread: %zu cells, %zu chunks, %lld entries\n", pl.stiles.size(), pl.schunks.size(), nsent);
       }
       std::printf("  grid points stored by the column pass: %.3f of %d x %d\n", (double)stored / ((double)pl.M2 * pl.N),
